@@ -1,0 +1,43 @@
+"""FP64 CPU oracle of the massively parallel algorithm (MPA) and of split-step.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls or
+links anything in this package: only the tests, the smoke check and the CPU
+baseline leg of the benchmark do.  It shares no code with the HIP library.
+
+Every function follows one passage of Korotkevich & Lushnikov,
+"Proof-of-concept implementation of the massively parallel algorithm for
+simulation of dispersion-managed WDM optical fiber systems"
+(arXiv:1101.0086), cited by equation number (Eq. 1 ... Eq. 7, in order of
+appearance) or by the numbered MPA steps 1-7.
+
+Parity status of each function (what pins it, see tests/test_oracle_*.py):
+
+* ``paper_fft`` / ``paper_ifft``: brute-force DFT with the e^{+i omega t}
+  kernel of the Fourier transform definition.
+* ``linear_step``: Gaussian closed form (beta3 = 0) and the exact centroid
+  drift from the moment equation of Eq. 1 (beta3 != 0).
+* ``mpa_long_step``: sigma = 0 exactness; the beta = 0 closed forms
+  (first iterate = Euler over L, exact rational second iterate, Cayley
+  limit); n -> infinity equals the sequential implicit trapezoid; SPM with
+  loss; soliton; the analytic MPA/SS error ratio 2 of Eqs. 5 and 7.
+* ``mpa_blocked_long_step``: block = N reproduces the full window bitwise;
+  shift equivariance; sigma = 0 blocked error below the halo bound.
+* ``ss_long_step`` / ``ss_propagate``: linear closed forms; exact SPM
+  kick; second order; unitarity; time reversibility.
+* ``mpa_propagate``: marching and resume identity; lumped gain restores the
+  span loss exactly.
+* the FP32 compensated-sum behaviour of the GPU path has no oracle: FP32
+  results are judged against this FP64 oracle ("parity unpinned" for the
+  FP32 rounding pattern itself).
+"""
+from .nlse import (DMMapSpec, paper_fft, paper_ifft, omega_grid, beta_phase,
+                   linear_step, mpa_long_step, mpa_blocked_long_step,
+                   block_partition, block_taper, halo_rate, mpa_step, mpa_propagate, ss_long_step,
+                   ss_propagate, reference_propagate, if_trapezoid_long_step,
+                   span_of_long_step, rel_l2)
+
+__all__ = ["DMMapSpec", "paper_fft", "paper_ifft", "omega_grid", "beta_phase",
+           "linear_step", "mpa_long_step", "mpa_blocked_long_step",
+           "block_partition", "block_taper", "halo_rate", "mpa_step", "mpa_propagate", "ss_long_step",
+           "ss_propagate", "reference_propagate", "if_trapezoid_long_step",
+           "span_of_long_step", "rel_l2"]

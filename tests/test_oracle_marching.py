@@ -1,0 +1,128 @@
+"""Oracle pins: time blocking, marching, lumped gain, resume.
+
+* One block covering the window reproduces the full-window MPA bitwise.
+* Shifting the input by a whole number of block cores shifts the blocked
+  output by the same amount (no hidden dependence on the block index).
+* With sigma = 0 the blocked MPA equals exact linear propagation to within a
+  small error once the halo exceeds the group-delay excursion of the signal
+  over the long step, and fails clearly when it does not.
+* Marching is memoryless: propagate(z0 -> z1 -> z2) equals propagate(z0 -> z2).
+* A global phase factor commutes with the method.
+* The lumped gain exp(gamma z_a) exactly undoes one amplifier span of loss.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import Grid, dm_map, wdm_field
+
+
+def _field(n=4096, dt=10 / 256, bits=16, ch=1, seed=1):
+    return wdm_field(Grid(n, dt), bits, ch, "ook", np.random.default_rng(seed))
+
+
+def test_single_block_is_full_window_bitwise():
+    a = _field()
+    dt = 10 / 256
+    args = (20.0, 0.0, 1.0, 0.05, 0.05, 8, 3)
+    full = O.mpa_long_step(a, O.omega_grid(a.size, dt), *args)
+    blk = O.mpa_blocked_long_step(a, dt, a.size, 0, *args)
+    assert np.array_equal(full, blk)
+
+
+def test_block_partition_covers_each_sample_once():
+    for n, b, h in ((4096, 1024, 128), (1 << 14, 4096, 512), (5000, 512, 64)):
+        parts = O.block_partition(n, b, h)
+        owned = np.zeros(n, int)
+        for w0, c0, clen in parts:
+            assert w0 == c0 - h and 0 < clen <= b - 2 * h
+            owned[c0:c0 + clen] += 1
+        assert np.all(owned == 1)
+
+
+def test_blocked_shift_equivariance():
+    n, dt, B, H = 8192, 10 / 512, 1024, 128
+    C = B - 2 * H
+    a = wdm_field(Grid(n, dt), 16, 2, "ook", np.random.default_rng(2))
+    args = (dt, B, H, 20.0, 0.1, 1.0, 0.05, 2e-3, 4, 2)
+    out = O.mpa_blocked_long_step(a, *args)
+    shift = 3 * C
+    # n is not a multiple of C: only shifts keeping the partition aligned are
+    # exact, which holds for samples whose block does not wrap
+    out_s = O.mpa_blocked_long_step(np.roll(a, shift), *args)
+    nb_full = n // C
+    lo, hi = shift, nb_full * C
+    assert np.max(np.abs(out_s[lo:hi] - np.roll(out, shift)[lo:hi])) == 0.0
+
+
+def test_block_taper_shape():
+    w = O.block_taper(4096, 512)
+    assert np.all(w[256:4096 - 256] == 1.0)
+    assert np.array_equal(w[:256], w[::-1][:256])
+    assert w[0] < 1e-8 and 1 - w[255] < 1e-8 and np.all(np.diff(w[:256]) > 0)
+    assert np.all(O.block_taper(1024, 0) == 1.0)
+
+
+def test_blocked_linear_error_controlled_by_halo():
+    """sigma = 0: the tapered blocks reproduce exact linear propagation once
+    the group delay of the signal band over L stays well inside the halo
+    (rate * L <= 0.25 halo dt), and fail clearly when it does not."""
+    n, dt, B, H = 8192, 10 / 512, 1024, 128
+    a = wdm_field(Grid(n, dt), 32, 3, "ook", np.random.default_rng(4))
+    b2 = 20.0
+    rate = O.halo_rate(45.0, b2, 0.0)
+    for frac, good in ((0.1, True), (0.25, True), (1.5, False)):
+        L = frac * H * dt / rate
+        exact = O.linear_step(a, O.omega_grid(n, dt), b2, 0.0, 0.0, L)
+        out = O.mpa_blocked_long_step(a, dt, B, H, b2, 0.0, 0.0, 0.0, L, 2, 1)
+        err = O.rel_l2(out, exact)
+        assert (err < 1e-9) if good else (err > 1e-3)
+
+
+def test_blocked_nonlinear_close_to_full_window():
+    """The blocking error of the full method (8 channels, beta3 != 0, loss)
+    stays at the 1e-10 level inside the halo rule."""
+    n, dt, B, H = 1 << 13, 10 / 1024, 2048, 256
+    a = wdm_field(Grid(n, dt), 8, 8, "ook", np.random.default_rng(7))
+    rate = O.halo_rate(145.0, 20.0, 0.1)
+    L = 0.2 * H * dt / rate
+    full = O.mpa_long_step(a, O.omega_grid(n, dt), 20.0, 0.1, 1.0, 0.05, L, 2, 2)
+    blk = O.mpa_blocked_long_step(a, dt, B, H, 20.0, 0.1, 1.0, 0.05, L, 2, 2)
+    assert O.rel_l2(blk, full) < 1e-9
+
+
+def test_marching_resume_and_global_phase():
+    a = _field()
+    dt = 10 / 256
+    dmm = dm_map(beta3=0.0)
+    L, M, nit = 0.05, 4, 2
+    whole = O.mpa_propagate(a, dt, dmm, L, M, nit, 0.0, 1.5)
+    part = O.mpa_propagate(a, dt, dmm, L, M, nit, 0.0, 0.75)
+    part = O.mpa_propagate(part, dt, dmm, L, M, nit, 0.75, 1.5)
+    assert np.array_equal(whole, part)
+    ph = np.exp(0.7j)
+    rot = O.mpa_propagate(a * ph, dt, dmm, L, M, nit, 0.0, 0.25)
+    assert O.rel_l2(rot, ph * O.mpa_propagate(a, dt, dmm, L, M, nit, 0.0, 0.25)) < 1e-14
+
+
+def test_lumped_gain_restores_span_loss():
+    a = _field()
+    dt = 10 / 256
+    dmm = O.DMMapSpec((0.5, 0.5), (0.0, 0.0), (0.0, 0.0), (0.0, 0.0), 0.3, 1.0)
+    out = O.mpa_propagate(a, dt, dmm, 0.1, 2, 1, 0.0, 1.0)
+    assert O.rel_l2(out, a) < 1e-14
+    half = O.mpa_propagate(a, dt, dmm, 0.1, 2, 1, 0.0, 0.5)
+    assert O.rel_l2(half, a * math.exp(-0.3 * 0.5)) < 1e-14
+    ss = O.ss_propagate(a, dt, dmm, 0.05, 0.0, 1.0)
+    assert O.rel_l2(ss, a) < 1e-14
+
+
+def test_span_schedule_uses_integer_counters():
+    dmm = dm_map()
+    L = 0.1
+    spans = [O.span_of_long_step(dmm, L, m) for m in range(20)]
+    assert spans == ([0] * 5 + [1] * 5) * 2
+    with pytest.raises(ValueError):
+        O.span_of_long_step(dmm, 0.3, 0)
