@@ -1,0 +1,160 @@
+/*
+ * mpa.h -- C ABI of the MI355X (gfx950) implementation of the massively
+ * parallel algorithm (MPA) for the scalar NLSE of dispersion-managed WDM
+ * links, and of the split-step (SS) comparator.
+ *
+ * Source of the method: Korotkevich & Lushnikov, "Proof-of-concept
+ * implementation of the massively parallel algorithm for simulation of
+ * dispersion-managed WDM optical fiber systems" (arXiv:1101.0086).
+ *
+ *   Model, Eq. 1:  i A_z - (1/2) beta2(z) A_tt - (i/6) beta3(z) A_ttt
+ *                  + sigma(z) |A|^2 A = i G(z) A,
+ *   G = -gamma between lumped amplifiers that multiply A by exp(gamma z_a)
+ *   at z = k z_a.  Fourier transform with kernel exp(+i omega t).
+ *
+ *   MPA (Eqs. 2 and 6, steps 1-7): on each long step [z0, z0 + L] the
+ *   interaction-picture spectrum psi(omega, z) is obtained by n_iter Picard
+ *   sweeps of the integral equation, with the z-integral taken by the
+ *   cumulative trapezoid rule on M + 1 equally spaced nodes; the result at
+ *   z0 + L starts the next long step.
+ *
+ *   SS (Eq. 4): composite symmetric split-step with exact linear and
+ *   nonlinear sub-steps.
+ *
+ * Conventions shared by every entry point
+ *   - A field is N interleaved complex samples A(t_n), t_n = n dt,
+ *     n = 0..N-1, on a periodic window of length N dt: float2 (real, imag)
+ *     for MPA_C64, double2 for MPA_C128.  It lives in device memory of the
+ *     plan's device, is owned by the caller, and is updated in place.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is
+ *     the default stream).  Calls return once the work is enqueued.
+ *   - Every function returns an mpa_status (0 on success, < 0 on error).
+ *     Argument validation happens on the host before any device call, so a
+ *     rejected call has no effect; mpa_last_error() returns a message for
+ *     the calling thread's most recent failure.
+ *   - A plan is not thread safe: calls on one plan must not overlap in time
+ *     on different host threads.  Different plans are independent.
+ *
+ * Time blocking (not part of the paper): with block = B < N the window is
+ * cut into blocks of B samples that overlap by `halo` samples per side; each
+ * block owns the core [b C, min((b+1) C, N)), C = B - 2 halo, runs the long
+ * step on its own periodic window (rolled off by an erf taper over its outer
+ * halo/2 samples per side) and writes its core back.  The plan rejects a
+ * long step whose group-delay excursion over the signal band,
+ * (|beta2| w + |beta3| w^2 / 2) L with w = omega_band, exceeds a quarter of
+ * the halo duration halo * dt, since the core would then see the block edges.
+ */
+#ifndef MPA_H
+#define MPA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MPA_OK = 0,
+    MPA_EINVAL = -1,       /* a size, count, pointer or coefficient is invalid      */
+    MPA_ENOMEM = -2,       /* device allocation failed                              */
+    MPA_EDEVICE = -3,      /* no usable gfx950 device, or a HIP runtime error        */
+    MPA_EALIGN = -4,       /* z0/z1 off the step grid, or a step not dividing a span */
+    MPA_EHALO = -5,        /* halo too small for the long step (see above)           */
+    MPA_EUNSUPPORTED = -6  /* valid request outside the sizes this build compiles    */
+} mpa_status;
+
+typedef enum {
+    MPA_C64 = 0,    /* FP32 complex field and FFTs, FP64-built dispersion phases,
+                       compensated FP32 accumulation of the z-integral        */
+    MPA_C128 = 1    /* FP64 everywhere                                        */
+} mpa_precision;
+
+/* One period of a piecewise-constant dispersion map (coefficients constant on
+ * each span, the assumption of the paper's accuracy analysis).  The arrays
+ * are host memory of n_seg entries, read and copied during plan creation.
+ * The map repeats with period sum(seg_len), starting at z = 0 with span 0. */
+typedef struct {
+    int32_t n_seg;
+    const double* seg_len;   /* span lengths, > 0                                 */
+    const double* beta2;     /* GVD beta2 per span (Eq. 1)                        */
+    const double* beta3;     /* third-order dispersion beta3 per span             */
+    const double* sigma;     /* nonlinear coefficient per span                    */
+    double gamma;            /* amplitude loss rate, G = -gamma (>= 0)            */
+    double z_amp;            /* amplifier spacing z_a (0: no amplifiers); gain
+                                exp(gamma z_a) is applied at z = k z_a           */
+} mpa_map;
+
+/* MPA plan parameters. */
+typedef struct {
+    int64_t n;             /* modes N: power of two                              */
+    double dt;             /* sample spacing (> 0)                               */
+    double L;              /* long step; must divide every span and z_amp        */
+    int32_t M;             /* quadrature intervals per long step (>= 1)          */
+    int32_t n_iter;        /* Picard sweeps per long step (1..5)                 */
+    int32_t block;         /* B: power of two, or 0 / N for one full window      */
+    int32_t halo;          /* samples of overlap per side (0 for a full window)  */
+    int32_t precision;     /* mpa_precision                                      */
+    double omega_band;     /* highest |omega| carrying signal, for the halo
+                              check; 0 means the grid's Nyquist frequency        */
+} mpa_params;
+
+typedef struct mpa_plan mpa_plan;   /* opaque: device tables and workspace */
+
+typedef struct {
+    int64_t n;
+    int32_t block, halo, core, n_blocks;
+    int32_t threads_per_block;
+    int64_t table_bytes;       /* device bytes of phase/twiddle/taper tables   */
+    int64_t workspace_bytes;   /* device bytes of the ping-pong field buffer    */
+} mpa_plan_info;
+
+/* Validate parameters, build the FP64 dispersion-phase tables on `device`
+ * (e^{i beta(omega_k, z_j)} for every span, node j = 0..M and block
+ * frequency omega_k, argument reduced in FP64; Eq. 2 and the definition of
+ * V_j in Eq. 6) and allocate a workspace of N complex samples.
+ * *out receives the plan (NULL on failure).                                  */
+int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device,
+                    mpa_plan** out);
+
+/* Release a plan (NULL is accepted).  Waits for the plan's pending work.    */
+int mpa_plan_destroy(mpa_plan* plan);
+
+int mpa_plan_get_info(const mpa_plan* plan, mpa_plan_info* info);
+
+/* Host-only validation of (params, map): the checks of mpa_plan_create that
+ * need no device.  Returns MPA_OK or the status plan creation would return. */
+int mpa_plan_validate(const mpa_params* params, const mpa_map* map);
+
+/* One long step [z0, z0 + L] (steps 1-7 and Eq. 6, then the lumped gain if an
+ * amplifier sits at z0 + L), in place on `field`.  z0 must be a multiple of
+ * L (it selects the span and the amplifier; beta and the loss integral are
+ * measured from z0).                                                         */
+int mpa_step(mpa_plan* plan, void* field, double z0, void* stream);
+
+/* March long steps from z0 to z1 (both multiples of L, z1 >= z0) in place;
+ * the state carried between long steps is the field alone.                  */
+int mpa_propagate(mpa_plan* plan, void* field, double z0, double z1, void* stream);
+
+/* Split-step comparator plan (Eq. 4): step dz must divide every span and
+ * z_amp.  Half steps of adjacent split-steps are merged into one spectral
+ * multiply; the nonlinear sub-step multiplies by exp(i sigma |A|^2 dz).      */
+typedef struct ss_plan ss_plan;
+
+int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz,
+                   int32_t precision, int device, ss_plan** out);
+int ss_plan_destroy(ss_plan* plan);
+
+/* Split-step from z0 to z1 (multiples of dz), in place.                      */
+int ss_propagate(ss_plan* plan, void* field, double z0, double z1, void* stream);
+
+const char* mpa_status_string(int status);
+
+/* Copies the calling thread's last error message (NUL-terminated, truncated
+ * to len bytes) and returns its full length.                                */
+int mpa_last_error(char* buf, int len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPA_H */

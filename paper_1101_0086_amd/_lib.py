@@ -1,0 +1,111 @@
+"""ctypes binding of libmpa.so (include/mpa.h): argument marshalling only.
+
+Every step of the propagation runs in the library's HIP kernels.  Loading
+fails loudly if the library has not been built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpa.so")
+
+MPA_OK = 0
+MPA_EINVAL = -1
+MPA_ENOMEM = -2
+MPA_EDEVICE = -3
+MPA_EALIGN = -4
+MPA_EHALO = -5
+MPA_EUNSUPPORTED = -6
+
+MPA_C64 = 0
+MPA_C128 = 1
+
+# symbols declared in include/mpa.h
+EXPORTED = ("mpa_plan_create", "mpa_plan_destroy", "mpa_plan_get_info", "mpa_plan_validate",
+            "mpa_step", "mpa_propagate", "ss_plan_create", "ss_plan_destroy", "ss_propagate",
+            "mpa_status_string", "mpa_last_error")
+
+
+class mpa_map(C.Structure):
+    _fields_ = [("n_seg", C.c_int32), ("seg_len", C.POINTER(C.c_double)),
+                ("beta2", C.POINTER(C.c_double)), ("beta3", C.POINTER(C.c_double)),
+                ("sigma", C.POINTER(C.c_double)), ("gamma", C.c_double), ("z_amp", C.c_double)]
+
+
+class mpa_params(C.Structure):
+    _fields_ = [("n", C.c_int64), ("dt", C.c_double), ("L", C.c_double), ("M", C.c_int32),
+                ("n_iter", C.c_int32), ("block", C.c_int32), ("halo", C.c_int32),
+                ("precision", C.c_int32), ("omega_band", C.c_double)]
+
+
+class mpa_plan_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("block", C.c_int32), ("halo", C.c_int32),
+                ("core", C.c_int32), ("n_blocks", C.c_int32), ("threads_per_block", C.c_int32),
+                ("table_bytes", C.c_int64), ("workspace_bytes", C.c_int64)]
+
+
+class MPAError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch carries its own HIP runtime; importing it first makes libmpa.so
+    # bind to that same runtime (one HIP runtime per process) instead of
+    # loading a second copy from the system ROCm.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    h = C.CDLL(LIB_PATH)
+    vp, dp = C.c_void_p, C.c_double
+    h.mpa_plan_create.argtypes = [C.POINTER(mpa_params), C.POINTER(mpa_map), C.c_int, C.POINTER(vp)]
+    h.mpa_plan_destroy.argtypes = [vp]
+    h.mpa_plan_get_info.argtypes = [vp, C.POINTER(mpa_plan_info)]
+    h.mpa_plan_validate.argtypes = [C.POINTER(mpa_params), C.POINTER(mpa_map)]
+    h.mpa_step.argtypes = [vp, vp, dp, vp]
+    h.mpa_propagate.argtypes = [vp, vp, dp, dp, vp]
+    h.ss_plan_create.argtypes = [C.POINTER(mpa_map), C.c_int64, dp, dp, C.c_int32, C.c_int, C.POINTER(vp)]
+    h.ss_plan_destroy.argtypes = [vp]
+    h.ss_propagate.argtypes = [vp, vp, dp, dp, vp]
+    h.mpa_status_string.argtypes = [C.c_int]
+    h.mpa_status_string.restype = C.c_char_p
+    h.mpa_last_error.argtypes = [C.c_char_p, C.c_int]
+    for name in EXPORTED:
+        if name not in ("mpa_status_string",):
+            getattr(h, name).restype = C.c_int
+    _lib = h
+    return h
+
+
+def check(status: int) -> None:
+    if status != MPA_OK:
+        buf = C.create_string_buffer(1024)
+        lib().mpa_last_error(buf, 1024)
+        raise MPAError(status, buf.value.decode() or lib().mpa_status_string(status).decode())
+
+
+class MapStruct:
+    """Keeps the ctypes arrays of an mpa_map alive."""
+
+    def __init__(self, dmmap):
+        n = len(dmmap.seg_len)
+        arr = C.c_double * n
+        self._a = [arr(*map(float, getattr(dmmap, f))) for f in ("seg_len", "beta2", "beta3", "sigma")]
+        self.s = mpa_map(n, self._a[0], self._a[1], self._a[2], self._a[3],
+                         float(dmmap.gamma), float(dmmap.z_amp))
+
+
+def make_params(n, dt, L, M, n_iter, block=0, halo=0, precision=MPA_C64, omega_band=0.0):
+    return mpa_params(int(n), float(dt), float(L), int(M), int(n_iter), int(block), int(halo),
+                      int(precision), float(omega_band))

@@ -1,0 +1,162 @@
+// Workgroup-wide power-of-two FFT held in registers, exchanged through LDS.
+//
+// A workgroup of NT = B / R threads transforms B points; thread `tid` holds
+// the R points with index tid + NT * m (m = 0..R-1) in registers, both before
+// and after the transform.  Every array indexed by frequency (spectra,
+// running sums, phase factors) can therefore stay in the registers of the
+// thread that owns those frequencies for the whole long step.
+//
+// The passes follow the Stockham autosort formulation: pass s with radix r
+// and span p (product of the earlier radices) reads x[i + q B / r] for
+// butterfly i (q = 0..r-1), multiplies by w^(q k), k = i mod p,
+// w = exp(SIGN 2 pi i / (p r)), takes an r-point DFT and writes
+// y[(i - k) r + k + q p].  The first pass reads registers, the last pass
+// writes registers (its output index set is again tid + NT m), the passes in
+// between exchange through LDS.  Results come out in natural order.
+//
+// SIGN = +1 is the transform with kernel exp(+i omega t) (the paper's F),
+// SIGN = -1 its unnormalised inverse.
+#pragma once
+
+#include "cx.hpp"
+
+namespace mpa {
+
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
+// LDS slot of element j: one pad slot every 8 elements breaks the
+// power-of-two write strides of the early passes across banks.
+__device__ __forceinline__ int lds_slot(int j) { return j + (j >> 3); }
+
+template <int B>
+constexpr int lds_elems() { return B + B / 8; }
+
+// ---- small DFTs in registers (output in natural order, in place) ----------
+
+template <int SIGN, typename T>
+__device__ __forceinline__ void dft2(cx<T>& a, cx<T>& b) {
+    cx<T> t = a;
+    a = t + b;
+    b = t - b;
+}
+
+template <int SIGN, typename T>
+__device__ __forceinline__ void dft4(cx<T>& x0, cx<T>& x1, cx<T>& x2, cx<T>& x3) {
+    cx<T> t0 = x0 + x2, t1 = x0 - x2, t2 = x1 + x3, t3 = rot<SIGN>(x1 - x3);
+    x0 = t0 + t2;
+    x2 = t0 - t2;
+    x1 = t1 + t3;
+    x3 = t1 - t3;
+}
+
+// 8-point DFT as two 4-point DFTs of the even and odd samples:
+// X_k = E_k + w^k O_k, X_{k+4} = E_k - w^k O_k, w = exp(SIGN 2 pi i / 8).
+template <int SIGN, typename T>
+__device__ __forceinline__ void dft8(cx<T> (&x)[8]) {
+    const T h = T(0.70710678118654752440084436210484903928);
+    dft4<SIGN>(x[0], x[2], x[4], x[6]);
+    dft4<SIGN>(x[1], x[3], x[5], x[7]);
+    // twiddle the odd half: O_1 *= w, O_2 *= w^2 = SIGN i, O_3 *= w^3
+    cx<T> o1 = x[3], o2 = x[5], o3 = x[7];
+    const T s = T(SIGN);
+    o1 = {(o1.re - s * o1.im) * h, (o1.im + s * o1.re) * h};
+    o2 = rot<SIGN>(o2);
+    o3 = {(-o3.re - s * o3.im) * h, (-o3.im + s * o3.re) * h};
+    cx<T> e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6], o0 = x[1];
+    x[0] = e0 + o0;
+    x[4] = e0 - o0;
+    x[1] = e1 + o1;
+    x[5] = e1 - o1;
+    x[2] = e2 + o2;
+    x[6] = e2 - o2;
+    x[3] = e3 + o3;
+    x[7] = e3 - o3;
+}
+
+template <int SIGN, int r, typename T>
+__device__ __forceinline__ void dft(cx<T> (&x)[r]) {
+    if constexpr (r == 2) {
+        dft2<SIGN>(x[0], x[1]);
+    } else if constexpr (r == 4) {
+        dft4<SIGN>(x[0], x[1], x[2], x[3]);
+    } else {
+        static_assert(r == 8, "radix");
+        dft8<SIGN>(x);
+    }
+}
+
+// ---- one Stockham pass ------------------------------------------------------
+
+template <typename T, int B, int R, int r, int p, int SIGN, bool FROM_LDS, bool TO_LDS>
+__device__ __forceinline__ void fft_pass(cx<T> (&v)[R], cx<T>* lds,
+                                         const cx<T>* __restrict__ tw, int tid) {
+    constexpr int NT = B / R;
+    constexpr int NB = R / r;   // butterflies per thread in this pass
+    if constexpr (FROM_LDS) {
+        __syncthreads();        // the previous pass's writes are visible
+#pragma unroll
+        for (int m = 0; m < R; ++m) v[m] = lds[lds_slot(tid + NT * m)];
+        __syncthreads();        // every read done before this pass overwrites
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int i = tid + u * NT;
+        const int k = i & (p - 1);
+        cx<T> x[r];
+#pragma unroll
+        for (int q = 0; q < r; ++q) x[q] = v[u + q * NB];
+        if constexpr (p > 1) {
+            constexpr int stride = B / (p * r);
+#pragma unroll
+            for (int q = 1; q < r; ++q) {
+                cx<T> w = tw[q * k * stride];   // exp(+2 pi i q k / (p r))
+                if constexpr (SIGN < 0) w.im = -w.im;
+                x[q] = cmul(x[q], w);
+            }
+        }
+        dft<SIGN, r>(x);
+        if constexpr (TO_LDS) {
+            const int base = (i - k) * r + k;
+#pragma unroll
+            for (int q = 0; q < r; ++q) lds[lds_slot(base + q * p)] = x[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < r; ++q) v[u + q * NB] = x[q];
+        }
+    }
+}
+
+// Radix of the pass whose span is P: the first pass takes the remainder
+// 2^(log2 B mod 3) when B is not a power of 8, every other pass is radix 8.
+template <int B, int P>
+constexpr int pass_radix() {
+    if constexpr (P == 1) {
+        constexpr int rem = ilog2(B) % 3;
+        return rem == 0 ? 8 : (1 << rem);
+    } else {
+        return 8;
+    }
+}
+
+template <typename T, int B, int R, int SIGN, int P>
+__device__ __forceinline__ void fft_from(cx<T> (&v)[R], cx<T>* lds,
+                                         const cx<T>* __restrict__ tw, int tid) {
+    constexpr int r = pass_radix<B, P>();
+    constexpr bool first = (P == 1);
+    constexpr bool last = (P * r == B);
+    static_assert(R % r == 0, "points per thread must be a multiple of every radix");
+    fft_pass<T, B, R, r, P, SIGN, !first, !last>(v, lds, tw, tid);
+    if constexpr (!last) fft_from<T, B, R, SIGN, P * r>(v, lds, tw, tid);
+}
+
+// B-point transform of the workgroup's registers (see the file comment).
+// `tw` holds exp(+2 pi i j / B), j = 0..B-1.  Must be called by every
+// thread of the workgroup (it contains barriers).
+template <typename T, int B, int R, int SIGN>
+__device__ __forceinline__ void block_fft(cx<T> (&v)[R], cx<T>* lds,
+                                          const cx<T>* __restrict__ tw, int tid) {
+    static_assert((B & (B - 1)) == 0 && B >= 64, "power-of-two block");
+    fft_from<T, B, R, SIGN, 1>(v, lds, tw, tid);
+}
+
+}  // namespace mpa

@@ -1,0 +1,40 @@
+// Internal interface between the C ABI (host) and the kernel translation
+// units.  Not part of the public header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mpa {
+
+// One fused long step over every block of one field.
+struct BlockStepArgs {
+    const void* in;          // field at z0 (N complex of the plan's precision)
+    void* out;               // field at z0 + L (must not alias `in`)
+    int64_t n;
+    int32_t block, halo, core, n_blocks;
+    const void* phase;       // (M+1) x B unit phasors e^{i beta(omega_k, z_j)} of the span
+    const void* phase_last;  // B FP64 phasors of node M of the span (reconstruction)
+    const void* node_scale;  // 2 (M+1) reals per span: c_j = e^{Gamma_j}/B, d_j = sigma dz e^{-Gamma_j}
+    const void* twiddle;     // B phasors exp(+2 pi i j / B), node precision
+    const void* twiddle64;   // the same in FP64 (carry transforms)
+    const void* taper;       // B FP64 reals
+    int32_t M, n_iter;
+    double d0;               // sigma dz (node 0)
+    double out_scale;        // e^{Gamma_M} / B, times the lumped gain
+    int32_t precision;       // 0: FP32 field / 1: FP64
+    hipStream_t stream;
+};
+
+bool block_step_supported(int precision, int block, int n_iter);
+int threads_per_block(int precision, int block);
+hipError_t launch_block_step(const BlockStepArgs& a);
+
+// FP64 phase table: rows r = 0..rows-1, column k = 0..B-1,
+// turns = c2[r] k'^2 + c3[r] k'^3 (k' the signed harmonic index),
+// table[r][k] = (cos 2 pi frac(turns), sin 2 pi frac(turns)) stored in the
+// plan precision.  `coef` holds c2[0..rows-1] then c3[0..rows-1] (device).
+hipError_t launch_phase_table(void* table, int precision, int B, int rows,
+                              const double* coef, hipStream_t stream);
+
+}  // namespace mpa

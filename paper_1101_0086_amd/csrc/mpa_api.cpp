@@ -1,0 +1,438 @@
+// C ABI of the MPA library: validation, plans, marching (see include/mpa.h).
+#include "../../include/mpa.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+bool is_finite(double x) { return std::isfinite(x); }
+
+// k such that k * h == len to 1e-9 relative, or -1.
+int64_t steps_per(double len, double h) {
+    const double q = len / h;
+    const double k = std::nearbyint(q);
+    if (k < 1 || std::fabs(k * h - len) > 1e-9 * std::fmax(len, h)) return -1;
+    return (int64_t)k;
+}
+
+// Grid index of z on a grid of spacing h (z must lie on it), or INT64_MIN.
+int64_t grid_index(double z, double h) {
+    const double k = std::nearbyint(z / h);
+    if (!is_finite(z) || std::fabs(k * h - z) > 1e-9 * std::fmax(std::fabs(z), h)) return INT64_MIN;
+    return (int64_t)k;
+}
+
+int validate_map(const mpa_map* map) {
+    if (!map) return fail(MPA_EINVAL, "map is NULL");
+    if (map->n_seg < 1 || map->n_seg > 64) return fail(MPA_EINVAL, "n_seg = %d not in 1..64", map->n_seg);
+    if (!map->seg_len || !map->beta2 || !map->beta3 || !map->sigma)
+        return fail(MPA_EINVAL, "a map array is NULL");
+    for (int i = 0; i < map->n_seg; ++i) {
+        if (!(map->seg_len[i] > 0) || !is_finite(map->seg_len[i]))
+            return fail(MPA_EINVAL, "seg_len[%d] must be finite and > 0", i);
+        if (!is_finite(map->beta2[i]) || !is_finite(map->beta3[i]) || !is_finite(map->sigma[i]))
+            return fail(MPA_EINVAL, "coefficients of span %d must be finite", i);
+    }
+    if (!(map->gamma >= 0) || !is_finite(map->gamma)) return fail(MPA_EINVAL, "gamma must be finite and >= 0");
+    if (!(map->z_amp >= 0) || !is_finite(map->z_amp)) return fail(MPA_EINVAL, "z_amp must be finite and >= 0");
+    return MPA_OK;
+}
+
+// Span schedule on a step grid h: steps per span and per amplifier.
+struct Schedule {
+    std::vector<int64_t> span_steps;   // steps in each span
+    int64_t period_steps = 0;
+    int64_t amp_steps = 0;             // 0: no amplifiers
+    int span_of(int64_t m) const {
+        int64_t r = m % period_steps;
+        if (r < 0) r += period_steps;
+        for (size_t i = 0; i < span_steps.size(); ++i) {
+            if (r < span_steps[i]) return (int)i;
+            r -= span_steps[i];
+        }
+        return (int)span_steps.size() - 1;
+    }
+    bool amp_after(int64_t m) const { return amp_steps > 0 && ((m + 1) % amp_steps) == 0; }
+};
+
+int make_schedule(const mpa_map* map, double h, const char* what, Schedule* s) {
+    s->span_steps.clear();
+    s->period_steps = 0;
+    for (int i = 0; i < map->n_seg; ++i) {
+        const int64_t k = steps_per(map->seg_len[i], h);
+        if (k < 0) return fail(MPA_EALIGN, "%s %g does not divide span %d of length %g", what, h, i,
+                               map->seg_len[i]);
+        s->span_steps.push_back(k);
+        s->period_steps += k;
+    }
+    s->amp_steps = 0;
+    if (map->z_amp > 0) {
+        const int64_t k = steps_per(map->z_amp, h);
+        if (k < 0) return fail(MPA_EALIGN, "%s %g does not divide the amplifier spacing %g", what, h,
+                               map->z_amp);
+        s->amp_steps = k;
+    }
+    return MPA_OK;
+}
+
+int check_device(int device) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return fail(MPA_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= count) return fail(MPA_EDEVICE, "device %d out of range (%d devices)", device, count);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+        return fail(MPA_EDEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(MPA_EDEVICE, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
+    return MPA_OK;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+struct mpa_plan {
+    mpa_params prm{};
+    int device = 0;
+    int block = 0, halo = 0, core = 0, n_blocks = 0;
+    size_t elem = 8;                    // bytes per complex sample
+    std::vector<double> beta2, beta3, sigma;
+    double gamma = 0, z_amp = 0;
+    Schedule sched;
+    void* phase = nullptr;              // n_seg x (M+1) x B complex (plan precision)
+    void* phase_last = nullptr;         // n_seg x B FP64 complex: node M (reconstruction)
+    void* node_scale = nullptr;         // n_seg x 2 (M+1) reals (plan precision)
+    void* twiddle = nullptr;            // B complex (plan precision)
+    void* twiddle64 = nullptr;          // B FP64 complex (carry transforms)
+    void* taper = nullptr;              // B FP64 reals
+    void* work = nullptr;               // N complex
+    int64_t table_bytes = 0;
+};
+
+static void plan_free(mpa_plan* p) {
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    for (void* q : {p->phase, p->phase_last, p->node_scale, p->twiddle, p->twiddle64, p->taper, p->work})
+        if (q) (void)hipFree(q);
+    delete p;
+}
+
+static int validate_params(const mpa_params* p, const mpa_map* map, Schedule* sched) {
+    if (!p) return fail(MPA_EINVAL, "params is NULL");
+    int st = validate_map(map);
+    if (st) return st;
+    if (!is_pow2(p->n) || p->n < 64 || p->n > (int64_t(1) << 30))
+        return fail(MPA_EINVAL, "n = %lld must be a power of two in [64, 2^30]", (long long)p->n);
+    if (!(p->dt > 0) || !is_finite(p->dt)) return fail(MPA_EINVAL, "dt must be finite and > 0");
+    if (!(p->L > 0) || !is_finite(p->L)) return fail(MPA_EINVAL, "L must be finite and > 0");
+    if (p->M < 1 || p->M > 65536) return fail(MPA_EINVAL, "M = %d not in 1..65536", p->M);
+    if (p->n_iter < 1 || p->n_iter > 5) return fail(MPA_EINVAL, "n_iter = %d not in 1..5", p->n_iter);
+    if (p->precision != MPA_C64 && p->precision != MPA_C128)
+        return fail(MPA_EINVAL, "precision = %d is not MPA_C64 or MPA_C128", p->precision);
+    if (!(p->omega_band >= 0) || !is_finite(p->omega_band)) return fail(MPA_EINVAL, "omega_band must be >= 0");
+    const bool full = (p->block == 0 || p->block == p->n);
+    if (full) {
+        if (p->halo != 0) return fail(MPA_EINVAL, "halo must be 0 for a full-window plan");
+    } else {
+        if (!is_pow2(p->block) || p->block > p->n)
+            return fail(MPA_EINVAL, "block = %d must be a power of two <= n", p->block);
+        if (p->halo < 0 || 2 * (int64_t)p->halo >= p->block)
+            return fail(MPA_EINVAL, "halo = %d must satisfy 0 <= 2 halo < block", p->halo);
+    }
+    st = make_schedule(map, p->L, "long step L", sched);
+    if (st) return st;
+    if (!full) {
+        const double pi = 3.14159265358979323846;
+        const double w = p->omega_band > 0 ? p->omega_band : pi / p->dt;
+        for (int i = 0; i < map->n_seg; ++i) {
+            const double rate = std::fabs(map->beta2[i]) * w + 0.5 * std::fabs(map->beta3[i]) * w * w;
+            if (rate * p->L > 0.25 * p->halo * p->dt)
+                return fail(MPA_EHALO,
+                            "span %d: group-delay excursion %g over L exceeds a quarter of the halo "
+                            "duration %g",
+                            i, rate * p->L, p->halo * p->dt);
+        }
+    }
+    const int B = full ? (int)p->n : p->block;
+    if (!mpa::block_step_supported(p->precision, B, p->n_iter))
+        return fail(MPA_EUNSUPPORTED, "block size %d with n_iter %d is not compiled (512..4096)", B,
+                    p->n_iter);
+    return MPA_OK;
+}
+
+extern "C" {
+
+int mpa_plan_validate(const mpa_params* params, const mpa_map* map) {
+    Schedule s;
+    return validate_params(params, map, &s);
+}
+
+int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mpa_plan** out) {
+    if (!out) return fail(MPA_EINVAL, "out is NULL");
+    *out = nullptr;
+    Schedule sched;
+    int st = validate_params(params, map, &sched);
+    if (st) return st;
+    st = check_device(device);
+    if (st) return st;
+    if (hipSetDevice(device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice(%d) failed", device);
+
+    auto* p = new mpa_plan();
+    p->prm = *params;
+    p->device = device;
+    p->sched = sched;
+    const bool full = (params->block == 0 || params->block == params->n);
+    p->block = full ? (int)params->n : params->block;
+    p->halo = full ? 0 : params->halo;
+    p->core = p->block - 2 * p->halo;
+    p->n_blocks = (int)((params->n + p->core - 1) / p->core);
+    p->elem = params->precision == MPA_C64 ? 8 : 16;
+    p->beta2.assign(map->beta2, map->beta2 + map->n_seg);
+    p->beta3.assign(map->beta3, map->beta3 + map->n_seg);
+    p->sigma.assign(map->sigma, map->sigma + map->n_seg);
+    p->gamma = map->gamma;
+    p->z_amp = map->z_amp;
+
+    const int B = p->block, M = params->M, S = map->n_seg;
+    const bool f32 = params->precision == MPA_C64;
+    const size_t rsz = f32 ? 4 : 8;
+    const size_t phase_bytes = (size_t)S * (M + 1) * B * p->elem;
+    const size_t ns_bytes = (size_t)S * 2 * (M + 1) * rsz;
+    const size_t last_bytes = (size_t)S * B * 16;
+    const size_t tw_bytes = (size_t)B * p->elem;
+    const size_t tw64_bytes = (size_t)B * 16;
+    const size_t tp_bytes = (size_t)B * 8;
+    const size_t work_bytes = (size_t)params->n * p->elem;
+    p->table_bytes = (int64_t)(phase_bytes + last_bytes + ns_bytes + tw_bytes + tw64_bytes + tp_bytes);
+    if (hipMalloc(&p->phase, phase_bytes) != hipSuccess || hipMalloc(&p->phase_last, last_bytes) != hipSuccess ||
+        hipMalloc(&p->node_scale, ns_bytes) != hipSuccess || hipMalloc(&p->twiddle, tw_bytes) != hipSuccess ||
+        hipMalloc(&p->twiddle64, tw64_bytes) != hipSuccess || hipMalloc(&p->taper, tp_bytes) != hipSuccess ||
+        hipMalloc(&p->work, work_bytes) != hipSuccess) {
+        plan_free(p);
+        return fail(MPA_ENOMEM, "device allocation of %zu bytes failed", (size_t)p->table_bytes + work_bytes);
+    }
+
+    const double pi = 3.14159265358979323846;
+    const double dz = params->L / M;
+    const double bdt = (double)B * params->dt;
+    // phase coefficients in turns: beta/(2 pi) = c2 k'^2 + c3 k'^3 with
+    // omega = 2 pi k' / (B dt): c2 = pi beta2 z / (B dt)^2, c3 = (2 pi^2 / 3) beta3 z / (B dt)^3
+    const int rows = S * (M + 1);
+    std::vector<double> coef(2 * (size_t)rows);
+    for (int s = 0; s < S; ++s)
+        for (int j = 0; j <= M; ++j) {
+            const double z = j * dz;
+            coef[(size_t)s * (M + 1) + j] = pi * p->beta2[s] * z / (bdt * bdt);
+            coef[rows + (size_t)s * (M + 1) + j] = (2.0 * pi * pi / 3.0) * p->beta3[s] * z / (bdt * bdt * bdt);
+        }
+    // node scalars: c_j = e^{Gamma_j} / B, d_j = sigma dz e^{-Gamma_j}, Gamma_j = -gamma j dz
+    std::vector<double> ns((size_t)S * 2 * (M + 1));
+    for (int s = 0; s < S; ++s)
+        for (int j = 0; j <= M; ++j) {
+            const double g = -p->gamma * j * dz;
+            ns[(size_t)s * 2 * (M + 1) + 2 * j] = std::exp(g) / B;
+            ns[(size_t)s * 2 * (M + 1) + 2 * j + 1] = p->sigma[s] * dz * std::exp(-g);
+        }
+    // twiddles exp(+2 pi i j / B) and the erf taper over the outer halo/2 samples
+    std::vector<double> tw(2 * (size_t)B), tp((size_t)B, 1.0);
+    for (int j = 0; j < B; ++j) {
+        const double a = 2.0 * pi * j / B;
+        tw[2 * j] = std::cos(a);
+        tw[2 * j + 1] = std::sin(a);
+    }
+    const int W = p->halo / 2;
+    for (int i = 0; i < W; ++i) {
+        const double x = (i + 0.5) / W;
+        const double s = 0.5 * (1.0 + std::erf(8.0 * (x - 0.5)));
+        tp[i] = s;
+        tp[B - 1 - i] = s;
+    }
+
+    // the node-M rows again, in FP64
+    std::vector<double> coef_last(2 * (size_t)S);
+    for (int s = 0; s < S; ++s) {
+        coef_last[s] = coef[(size_t)s * (M + 1) + M];
+        coef_last[S + s] = coef[rows + (size_t)s * (M + 1) + M];
+    }
+    DevBuf dcoef, dlast;
+    bool ok = hipMalloc(&dcoef.p, coef.size() * sizeof(double)) == hipSuccess &&
+              hipMemcpy(dcoef.p, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMalloc(&dlast.p, coef_last.size() * sizeof(double)) == hipSuccess &&
+              hipMemcpy(dlast.p, coef_last.data(), coef_last.size() * sizeof(double), hipMemcpyHostToDevice) ==
+                  hipSuccess;
+    if (ok) ok = mpa::launch_phase_table(p->phase, params->precision, B, rows, (const double*)dcoef.p, 0) == hipSuccess;
+    if (ok) ok = mpa::launch_phase_table(p->phase_last, MPA_C128, B, S, (const double*)dlast.p, 0) == hipSuccess;
+    auto upload_real = [&](void* dst, const std::vector<double>& v) {
+        if (f32) {
+            std::vector<float> f(v.begin(), v.end());
+            return hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+        }
+        return hipMemcpy(dst, v.data(), v.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (ok) ok = upload_real(p->node_scale, ns) && upload_real(p->twiddle, tw);
+    if (ok) ok = hipMemcpy(p->twiddle64, tw.data(), tw.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+                 hipMemcpy(p->taper, tp.data(), tp.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+    if (ok) ok = hipDeviceSynchronize() == hipSuccess;
+    if (!ok) {
+        plan_free(p);
+        return fail(MPA_EDEVICE, "plan table construction failed");
+    }
+    *out = p;
+    return MPA_OK;
+}
+
+int mpa_plan_destroy(mpa_plan* plan) {
+    plan_free(plan);
+    return MPA_OK;
+}
+
+int mpa_plan_get_info(const mpa_plan* p, mpa_plan_info* info) {
+    if (!p || !info) return fail(MPA_EINVAL, "NULL argument");
+    info->n = p->prm.n;
+    info->block = p->block;
+    info->halo = p->halo;
+    info->core = p->core;
+    info->n_blocks = p->n_blocks;
+    info->threads_per_block = mpa::threads_per_block(p->prm.precision, p->block);
+    info->table_bytes = p->table_bytes;
+    info->workspace_bytes = p->prm.n * (int64_t)p->elem;
+    return MPA_OK;
+}
+
+static int launch_long_step(mpa_plan* p, const void* in, void* out, int64_t m, hipStream_t stream) {
+    const int s = p->sched.span_of(m);
+    const int M = p->prm.M;
+    const double dz = p->prm.L / M;
+    const double gain = p->sched.amp_after(m) ? std::exp(p->gamma * p->z_amp) : 1.0;
+    mpa::BlockStepArgs a;
+    a.in = in;
+    a.out = out;
+    a.n = p->prm.n;
+    a.block = p->block;
+    a.halo = p->halo;
+    a.core = p->core;
+    a.n_blocks = p->n_blocks;
+    a.phase = (const char*)p->phase + (size_t)s * (M + 1) * p->block * p->elem;
+    a.phase_last = (const char*)p->phase_last + (size_t)s * p->block * 16;
+    a.twiddle64 = p->twiddle64;
+    a.node_scale = (const char*)p->node_scale + (size_t)s * 2 * (M + 1) * (p->elem / 2);
+    a.twiddle = p->twiddle;
+    a.taper = p->taper;
+    a.M = M;
+    a.n_iter = p->prm.n_iter;
+    a.d0 = p->sigma[s] * dz;
+    a.out_scale = std::exp(-p->gamma * p->prm.L) / p->block * gain;
+    a.precision = p->prm.precision;
+    a.stream = stream;
+    const hipError_t e = mpa::launch_block_step(a);
+    if (e != hipSuccess) return fail(MPA_EDEVICE, "block step launch failed: %s", hipGetErrorString(e));
+    return MPA_OK;
+}
+
+int mpa_step(mpa_plan* p, void* field, double z0, void* stream) {
+    if (!p || !field) return fail(MPA_EINVAL, "NULL plan or field");
+    const int64_t m = grid_index(z0, p->prm.L);
+    if (m == INT64_MIN) return fail(MPA_EALIGN, "z0 = %g is not a multiple of L = %g", z0, p->prm.L);
+    if (hipSetDevice(p->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+    int st = launch_long_step(p, field, p->work, m, s);
+    if (st) return st;
+    if (hipMemcpyAsync(field, p->work, (size_t)p->prm.n * p->elem, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return fail(MPA_EDEVICE, "copy back failed");
+    return MPA_OK;
+}
+
+int mpa_propagate(mpa_plan* p, void* field, double z0, double z1, void* stream) {
+    if (!p || !field) return fail(MPA_EINVAL, "NULL plan or field");
+    const int64_t m0 = grid_index(z0, p->prm.L), m1 = grid_index(z1, p->prm.L);
+    if (m0 == INT64_MIN || m1 == INT64_MIN)
+        return fail(MPA_EALIGN, "z0 = %g or z1 = %g is not a multiple of L = %g", z0, z1, p->prm.L);
+    if (m1 < m0) return fail(MPA_EINVAL, "z1 < z0");
+    if (hipSetDevice(p->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+    void* src = field;
+    void* dst = p->work;
+    for (int64_t m = m0; m < m1; ++m) {
+        int st = launch_long_step(p, src, dst, m, s);
+        if (st) return st;
+        void* t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != field &&
+        hipMemcpyAsync(field, src, (size_t)p->prm.n * p->elem, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return fail(MPA_EDEVICE, "copy back failed");
+    return MPA_OK;
+}
+
+const char* mpa_status_string(int status) {
+    switch (status) {
+        case MPA_OK: return "MPA_OK";
+        case MPA_EINVAL: return "MPA_EINVAL: invalid argument";
+        case MPA_ENOMEM: return "MPA_ENOMEM: device allocation failed";
+        case MPA_EDEVICE: return "MPA_EDEVICE: no usable gfx950 device or HIP error";
+        case MPA_EALIGN: return "MPA_EALIGN: position or step off the grid";
+        case MPA_EHALO: return "MPA_EHALO: halo too small for the long step";
+        case MPA_EUNSUPPORTED: return "MPA_EUNSUPPORTED: size not compiled in this build";
+        default: return "unknown mpa_status";
+    }
+}
+
+int mpa_last_error(char* buf, int len) {
+    const int n = (int)g_last_error.size();
+    if (buf && len > 0) {
+        const int c = n < len - 1 ? n : len - 1;
+        std::memcpy(buf, g_last_error.data(), c);
+        buf[c] = 0;
+    }
+    return n;
+}
+
+}  // extern "C"
+
+// ---- split-step plan ------------------------------------------------------------
+
+namespace mpa_internal {
+int fail_status(int status, const char* msg) { return fail(status, "%s", msg); }
+int validate_map_c(const mpa_map* map) { return validate_map(map); }
+int schedule_c(const mpa_map* map, double h, int64_t* span_steps, int64_t* period, int64_t* amp) {
+    Schedule s;
+    int st = make_schedule(map, h, "split-step dz", &s);
+    if (st) return st;
+    for (size_t i = 0; i < s.span_steps.size(); ++i) span_steps[i] = s.span_steps[i];
+    *period = s.period_steps;
+    *amp = s.amp_steps;
+    return MPA_OK;
+}
+int check_device_c(int device) { return check_device(device); }
+int64_t grid_index_c(double z, double h) { return grid_index(z, h); }
+}  // namespace mpa_internal

@@ -1,0 +1,251 @@
+// Fused MPA long step for gfx950: one workgroup per time block.
+//
+// Per block (Eqs. 2 and 6, steps 1-7 of the MPA; the block decomposition
+// itself is not in the paper):
+//   gather   A_0(t)  = taper(t) * field[(b C - H + t) mod N]        (HBM read)
+//   step 1   psi_0   = F[A_0],   U_0 = i sigma dz F[|A_0|^2 A_0]
+//   nodes    for l = 1..M, for sweep n = 0..n_iter-1 (wavefront order):
+//              A     = e^{Gamma_l} F^-1[psi^(n)_l e^{i beta_l}]            (steps 2, 3)
+//              U_l   = i sigma dz e^{-Gamma_l} e^{-i beta_l} F[|A|^2 A]    (step 4, V_j of Eq. 6)
+//              psi^(n+1)_l = psi_0 + S^(n) + U_l / 2,  S^(n) += U_l       (step 5, Eq. 6)
+//   step 7   A(z0+L) = e^{Gamma_M} F^-1[psi^(n_iter)_M e^{i beta_M}]
+//   scatter  the block's core, times the lumped gain when an amplifier ends the step.
+//
+// The wavefront order (all sweeps of node l before node l+1) performs the
+// same operations as the paper's sweep-by-sweep order: psi^(n+1)_l only
+// needs sweep-n values at nodes <= l.  It keeps the state of a block to
+// psi_0 and one running trapezoid sum S^(n) per sweep, all in registers of
+// the thread owning those frequencies, instead of (M+1) spectra per sweep.
+//
+// Precision.  T is the type of the node evaluations (steps 2-4: 2 n_iter M
+// transforms and the nonlinearity) and of the trapezoid sums S^(n), which
+// are accumulated with Neumaier compensation per component when T is float.
+// The carry of the field across the long step -- the transform giving
+// psi_0, the sums psi_0 + S^(n), the node-M phase and the reconstruction
+// transform -- is always FP64, and the field is rounded to T once, when it
+// is stored.  With FP32 carry transforms the rounding of the FFT with FP32
+// twiddles repeats identically every long step and the error grows linearly
+// with the number of long steps; with the FP64 carry it grows like its
+// square root.  Phases e^{i beta} are built in FP64 (argument reduced in
+// turns) and rounded to T for the node evaluations.
+#include "block_fft.hpp"
+#include "launch.hpp"
+
+#include <type_traits>
+
+namespace mpa {
+
+constexpr int PTS = 8;   // points per thread in the block kernels
+
+__device__ __forceinline__ void comp_add(float& s, float& c, float x) {
+    const float t = s + x;
+    const float e = (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
+    s = t;
+    c += e;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<double> widen(cx<T> a) { return {double(a.re), double(a.im)}; }
+
+template <typename T>
+__device__ __forceinline__ cx<T> narrow(cx<double> a) { return {T(a.re), T(a.im)}; }
+
+template <typename T, int B, int NIT>
+__global__ void __launch_bounds__(B / PTS)
+mpa_block_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long long n,
+                 int core, int halo, const cx<T>* __restrict__ phase,
+                 const cx<double>* __restrict__ phase_last, const T* __restrict__ node_scale,
+                 const cx<T>* __restrict__ tw, const cx<double>* __restrict__ tw64,
+                 const double* __restrict__ taper, int M, T d0, double out_scale) {
+    constexpr int R = PTS;
+    constexpr int NT = B / R;
+    constexpr bool COMP = std::is_same<T, float>::value;
+    // one LDS exchange buffer, sized for FP64 and shared by both precisions
+    __shared__ cx<double> lds64[lds_elems<B>()];
+    cx<T>* ldsT = reinterpret_cast<cx<T>*>(lds64);
+
+    const int tid = threadIdx.x;
+    const long long c0 = (long long)blockIdx.x * core;
+    const long long w0 = c0 - halo;
+
+    cx<double> psi0[R];
+    cx<T> cur[R], ph[R];
+    cx<T> S[NIT][R];
+    T Cre[COMP ? NIT : 1][R], Cim[COMP ? NIT : 1][R];
+
+    // gather the tapered window; node 0 needs |A_0|^2 A_0
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int t = tid + NT * m;
+        long long g = w0 + t;
+        if (g < 0) g += n;
+        if (g >= n) g -= n;
+        const cx<double> a = scale(widen(in[g]), taper[t]);
+        psi0[m] = a;
+        cur[m] = narrow<T>(scale(a, norm2(a)));
+    }
+    // step 1 and node 0: psi_0 = F[A_0] (FP64); U_0 = i sigma dz F[|A_0|^2 A_0]
+    block_fft<double, B, R, +1>(psi0, lds64, tw64, tid);
+    block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const cx<T> u0 = rot<+1>(scale(cur[m], d0 * T(0.5)));
+#pragma unroll
+        for (int s = 0; s < NIT; ++s) {
+            S[s][m] = u0;
+            if constexpr (COMP) {
+                Cre[s][m] = T(0);
+                Cim[s][m] = T(0);
+            }
+        }
+    }
+
+    for (int l = 1; l <= M; ++l) {
+        const cx<T>* __restrict__ phl = phase + (size_t)l * B;
+        const T cl = node_scale[2 * l];
+        const T dl = node_scale[2 * l + 1];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            ph[m] = phl[tid + NT * m];
+            cur[m] = narrow<T>(psi0[m]);
+        }
+        const bool last_node = (l == M);
+#pragma unroll
+        for (int s = 0; s < NIT; ++s) {
+            // steps 2-3: A = e^{Gamma_l} F^-1[psi e^{i beta_l}]
+#pragma unroll
+            for (int m = 0; m < R; ++m) cur[m] = cmul(cur[m], ph[m]);
+            block_fft<T, B, R, -1>(cur, ldsT, tw, tid);
+            // nonlinearity |A|^2 A
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const cx<T> a = scale(cur[m], cl);
+                cur[m] = scale(a, norm2(a));
+            }
+            // step 4: U = i sigma dz e^{-Gamma_l} e^{-i beta_l} F[|A|^2 A]
+            block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
+            const bool need_next = (s < NIT - 1) || last_node;
+            const bool final_sum = last_node && (s == NIT - 1);
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const cx<T> u = rot<+1>(scale(cmulc(cur[m], ph[m]), dl));
+                // step 5 (Eq. 6): psi^(s+1)_l = psi_0 + S^(s) + U/2, then S^(s) += U
+                if (need_next) {
+                    cx<T> acc = S[s][m];
+                    if constexpr (COMP) {
+                        acc.re += Cre[s][m];
+                        acc.im += Cim[s][m];
+                    }
+                    const cx<double> nxt = psi0[m] + (widen(acc) + scale(widen(u), 0.5));
+                    if (final_sum) psi0[m] = nxt;      // psi^(n_iter)_M, kept in FP64
+                    else cur[m] = narrow<T>(nxt);
+                }
+                if (!last_node) {
+                    if constexpr (COMP) {
+                        comp_add(S[s][m].re, Cre[s][m], u.re);
+                        comp_add(S[s][m].im, Cim[s][m], u.im);
+                    } else {
+                        S[s][m] = S[s][m] + u;
+                    }
+                }
+            }
+        }
+    }
+
+    // step 7: reconstruct A(z0 + L) from psi^(n_iter)_M in FP64
+    const cx<double>* __restrict__ phM = phase_last;
+#pragma unroll
+    for (int m = 0; m < R; ++m) psi0[m] = scale(cmul(psi0[m], phM[tid + NT * m]), out_scale);
+    block_fft<double, B, R, -1>(psi0, lds64, tw64, tid);
+
+    // scatter the core
+    const long long rest = n - c0;
+    const int clen = rest < core ? (int)rest : core;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int t = tid + NT * m;
+        if (t >= halo && t < halo + clen) out[c0 + (t - halo)] = narrow<T>(psi0[m]);
+    }
+}
+
+template <typename T, int B, int NIT>
+static hipError_t launch_typed(const BlockStepArgs& a) {
+    hipLaunchKernelGGL((mpa_block_kernel<T, B, NIT>), dim3(a.n_blocks), dim3(B / PTS), 0,
+                       a.stream, static_cast<const cx<T>*>(a.in), static_cast<cx<T>*>(a.out),
+                       (long long)a.n, a.core, a.halo, static_cast<const cx<T>*>(a.phase),
+                       static_cast<const cx<double>*>(a.phase_last),
+                       static_cast<const T*>(a.node_scale), static_cast<const cx<T>*>(a.twiddle),
+                       static_cast<const cx<double>*>(a.twiddle64),
+                       static_cast<const double*>(a.taper), a.M, T(a.d0), a.out_scale);
+    return hipGetLastError();
+}
+
+template <typename T, int B>
+static hipError_t launch_nit(const BlockStepArgs& a) {
+    switch (a.n_iter) {
+        case 1: return launch_typed<T, B, 1>(a);
+        case 2: return launch_typed<T, B, 2>(a);
+        case 3: return launch_typed<T, B, 3>(a);
+        case 4: return launch_typed<T, B, 4>(a);
+        case 5: return launch_typed<T, B, 5>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+static hipError_t launch_b(const BlockStepArgs& a) {
+    switch (a.block) {
+        case 512: return launch_nit<T, 512>(a);
+        case 1024: return launch_nit<T, 1024>(a);
+        case 2048: return launch_nit<T, 2048>(a);
+        case 4096: return launch_nit<T, 4096>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool block_step_supported(int precision, int block, int n_iter) {
+    const bool b_ok = block == 512 || block == 1024 || block == 2048 || block == 4096;
+    return (precision == 0 || precision == 1) && b_ok && n_iter >= 1 && n_iter <= 5;
+}
+
+int threads_per_block(int precision, int block) { return block / PTS; }
+
+hipError_t launch_block_step(const BlockStepArgs& a) {
+    if (!block_step_supported(a.precision, a.block, a.n_iter)) return hipErrorInvalidValue;
+    return a.precision == 0 ? launch_b<float>(a) : launch_b<double>(a);
+}
+
+// ---- FP64 phase tables --------------------------------------------------------
+
+template <typename T>
+__global__ void phase_table_kernel(cx<T>* __restrict__ out, int B, int rows,
+                                   const double* __restrict__ coef) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)rows * B) return;
+    const int r = (int)(idx / B);
+    const int k = (int)(idx - (long long)r * B);
+    const double kp = (k < B / 2) ? double(k) : double(k - B);   // signed harmonic index
+    const double k2 = kp * kp;
+    const double k3 = k2 * kp;                                    // exact: |k'|^3 < 2^53
+    const double turns = fma(coef[rows + r], k3, coef[r] * k2);   // beta / (2 pi)
+    const double f = turns - rint(turns);                         // reduced to [-1/2, 1/2]
+    double s, c;
+    sincospi(2.0 * f, &s, &c);
+    out[idx] = cx<T>{T(c), T(s)};
+}
+
+hipError_t launch_phase_table(void* table, int precision, int B, int rows, const double* coef,
+                              hipStream_t stream) {
+    const long long total = (long long)rows * B;
+    const int tpb = 256;
+    const unsigned grid = (unsigned)((total + tpb - 1) / tpb);
+    if (precision == 0)
+        hipLaunchKernelGGL(phase_table_kernel<float>, dim3(grid), dim3(tpb), 0, stream,
+                           static_cast<cx<float>*>(table), B, rows, coef);
+    else
+        hipLaunchKernelGGL(phase_table_kernel<double>, dim3(grid), dim3(tpb), 0, stream,
+                           static_cast<cx<double>*>(table), B, rows, coef);
+    return hipGetLastError();
+}
+
+}  // namespace mpa

@@ -1,0 +1,98 @@
+"""The C ABI library on the host: it loads, exports every function that
+include/mpa.h declares, and rejects invalid requests with the documented
+status codes before touching a device (no kernel runs here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from workloads import WORKLOADS, dm_map
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpa.h")
+
+
+def _lib():
+    from paper_1101_0086_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libmpa.so is not built (run __graft_entry__.build())")
+    return L
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_exports_every_declared_symbol():
+    L = _lib()
+    h = C.CDLL(L.LIB_PATH)
+    names = _declared_functions()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(h, name), name
+    assert set(names) == set(L.EXPORTED)
+
+
+def _validate(**kw):
+    L = _lib()
+    w = WORKLOADS["wdm8_n262144_f32"]
+    base = dict(n=w.grid.n, dt=w.grid.dt, L=w.mpa.L, M=w.mpa.M, n_iter=w.mpa.n_iter,
+                block=w.mpa.block, halo=w.mpa.halo, precision=0, omega_band=w.mpa.omega_band)
+    dmm = kw.pop("dmmap", w.dmmap)
+    base.update(kw)
+    p = L.make_params(**base)
+    m = L.MapStruct(dmm)
+    return L.lib().mpa_plan_validate(C.byref(p), C.byref(m.s))
+
+
+def test_validation_status_codes():
+    L = _lib()
+    assert _validate() == L.MPA_OK
+    assert _validate(n=3000) == L.MPA_EINVAL
+    assert _validate(dt=-1.0) == L.MPA_EINVAL
+    assert _validate(M=0) == L.MPA_EINVAL
+    assert _validate(n_iter=9) == L.MPA_EINVAL
+    assert _validate(precision=7) == L.MPA_EINVAL
+    assert _validate(halo=3000) == L.MPA_EINVAL
+    assert _validate(block=3000) == L.MPA_EINVAL
+    assert _validate(L=3e-4) == L.MPA_EALIGN            # does not divide the 0.5 spans
+    assert _validate(L=1e-3) == L.MPA_EHALO             # group delay over L too large for H
+    assert _validate(halo=64) == L.MPA_EHALO
+    assert _validate(block=1 << 14, halo=2048) == L.MPA_EUNSUPPORTED
+    assert _validate(dmmap=dm_map(beta3=0.1, z_amp=1.0 / 3.0)) == L.MPA_EALIGN
+    # a full-window plan needs no halo rule
+    assert _validate(n=4096, block=0, halo=0, L=0.05) == L.MPA_OK
+    assert _validate(n=4096, block=4096, halo=8, L=0.05) == L.MPA_EINVAL
+
+
+def test_error_message_and_status_strings():
+    L = _lib()
+    assert _validate(L=1e-3) == L.MPA_EHALO
+    buf = C.create_string_buffer(256)
+    n = L.lib().mpa_last_error(buf, 256)
+    assert n > 0 and b"halo" in buf.value
+    for s in (0, -1, -2, -3, -4, -5, -6):
+        assert L.lib().mpa_status_string(s).startswith(b"MPA_")
+
+
+def test_null_arguments_rejected():
+    L = _lib()
+    h = L.lib()
+    assert h.mpa_plan_validate(None, None) == L.MPA_EINVAL
+    assert h.mpa_step(None, None, C.c_double(0.0), None) == L.MPA_EINVAL
+    assert h.mpa_propagate(None, None, C.c_double(0.0), C.c_double(1.0), None) == L.MPA_EINVAL
+    assert h.ss_propagate(None, None, C.c_double(0.0), C.c_double(1.0), None) == L.MPA_EINVAL
+    out = C.c_void_p(123)
+    assert h.mpa_plan_create(None, None, 0, C.byref(out)) == L.MPA_EINVAL and out.value is None
+    assert h.mpa_plan_destroy(None) == L.MPA_OK
+
+
+def test_python_binding_raises_on_invalid():
+    import paper_1101_0086_amd as P
+    w = WORKLOADS["wdm8_n262144_f32"]
+    with pytest.raises(P.MPAError) as e:
+        P.validate(w.grid.n, w.grid.dt, w.dmmap, 1e-3, 2, 2, 4096, 512, P.MPA_C64, w.mpa.omega_band)
+    assert e.value.status == -5

@@ -215,7 +215,7 @@ WORKLOADS = {
     "wdm32_n4194304_f32": Workload(
         "wdm32_n4194304_f32", Grid(1 << 22, T_BIT / 4096), 1024, 32, "qpsk",
         dm_map(beta3=0.1), 200,
-        MPASettings(L=1.5625e-5, M=1, n_iter=2, block=8192, halo=1024,
+        MPASettings(L=7.8125e-6, M=1, n_iter=2, block=4096, halo=512,
                     omega_band=_omega_sig(32)),
         "f32", 3, _omega_sig(32)),
     # 4-channel, 2^16 modes (the gradient workload's forward)
