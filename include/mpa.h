@@ -43,6 +43,11 @@
  * long step whose group-delay excursion over the signal band,
  * (|beta2| w + |beta3| w^2 / 2) L with w = omega_band, exceeds a quarter of
  * the halo duration halo * dt, since the core would then see the block edges.
+ * Stitching overlapping windows is not unitary, so each block's spectrum is
+ * also rolled off when it is reconstructed: with g = |beta2 omega +
+ * beta3 omega^2 / 2| L / (halo dt), by a raised cosine from 1 at g = 0.35 to
+ * 0 at g = 0.5, and from 1 at |omega| = 0.8 pi/dt to 0 at 0.9 pi/dt.  Without
+ * it, content at the grid's Nyquist frequency grows every long step.
  */
 #ifndef MPA_H
 #define MPA_H

@@ -77,7 +77,7 @@ def rel_l2(a: np.ndarray, ref: np.ndarray) -> float:
 
 def mpa_long_step(a_z0: np.ndarray, omega: np.ndarray, beta2: float, beta3: float,
                   sigma: float, gamma: float, L: float, M: int, n_iter: int,
-                  return_iterates: bool = False):
+                  return_iterates: bool = False, out_mask=None):
     """Advance A(t, z0) to A(t, z0 + L) by n_iter Picard sweeps of the
     discretised integral equation, Eq. 6, in the order of MPA steps 1-7.
 
@@ -108,7 +108,10 @@ def mpa_long_step(a_z0: np.ndarray, omega: np.ndarray, beta2: float, beta3: floa
         new[1:] = psi0[None, :] + 1j * (csum[1:] - 0.5 * v[0][None, :] - 0.5 * v[1:])
         psi = new                                                 # step 6: next sweep
         iterates.append(psi[M].copy())
-    out = paper_ifft(psi[M] * to_a[M])                            # step 7
+    spec = psi[M] * to_a[M]                                      # step 7
+    if out_mask is not None:
+        spec = spec * out_mask
+    out = paper_ifft(spec)
     if return_iterates:
         return out, iterates
     return out
@@ -194,24 +197,56 @@ def block_taper(block: int, halo: int) -> np.ndarray:
     return w
 
 
+MASK_PASS = 0.35       # group delay over L, in units of the halo duration
+MASK_STOP = 0.5
+NYQ_PASS = 0.8         # |omega| in units of the grid's Nyquist frequency pi/dt
+NYQ_STOP = 0.9
+
+
+def _raised_cosine_drop(x: np.ndarray) -> np.ndarray:
+    """1 for x <= 0, 0 for x >= 1, (1 + cos(pi x)) / 2 in between."""
+    return np.where(x <= 0, 1.0, np.where(x >= 1, 0.0, 0.5 * (1.0 + np.cos(math.pi * np.clip(x, 0, 1)))))
+
+
+def block_mask(omega_b: np.ndarray, beta2: float, beta3: float, L: float, halo: int,
+               dt: float) -> np.ndarray:
+    """Spectral roll-off applied to each block's spectrum when it is
+    reconstructed (step 7 of a blocked long step).
+
+    Stitching overlapping periodic windows is not a unitary map, and two
+    kinds of content grow under it by a fixed factor every long step even
+    with sigma = 0: content whose group delay over L carries it into the
+    tapered outer halo, and, when beta3 != 0, content at the grid's Nyquist
+    frequency, where the odd beta3 term makes beta(omega) jump between
+    +pi/dt and -pi/dt.  The mask is the product of two raised-cosine
+    roll-offs: in g = |beta2 omega + beta3 omega^2 / 2| L / (halo dt), from 1
+    at g = 0.35 to 0 at g = 0.5 (the halo rule keeps the signal band at
+    g <= 0.25), and in |omega| dt / pi, from 1 at 0.8 to 0 at 0.9."""
+    g = np.abs(beta2 * omega_b + 0.5 * beta3 * omega_b ** 2) * L / (halo * dt)
+    r = np.abs(omega_b) * dt / math.pi
+    return (_raised_cosine_drop((g - MASK_PASS) / (MASK_STOP - MASK_PASS))
+            * _raised_cosine_drop((r - NYQ_PASS) / (NYQ_STOP - NYQ_PASS)))
+
+
 def mpa_blocked_long_step(a_z0: np.ndarray, dt: float, block: int, halo: int,
                           beta2: float, beta3: float, sigma: float, gamma: float,
                           L: float, M: int, n_iter: int) -> np.ndarray:
     """One MPA long step run independently on every periodic block window
     (frequency grid of the block: omega^B = 2 pi fftfreq(block, dt)), keeping
     each block's core.  Each window is multiplied by :func:`block_taper`
-    first."""
+    first and each block's final spectrum by :func:`block_mask`."""
     n = a_z0.shape[0]
     if block == 0 or block == n:
         return mpa_long_step(a_z0, omega_grid(n, dt), beta2, beta3, sigma, gamma,
                              L, M, n_iter)
     omega_b = omega_grid(block, dt)
     taper = block_taper(block, halo)
+    mask = block_mask(omega_b, beta2, beta3, L, halo, dt) if halo > 0 else None
     out = np.empty_like(a_z0)
     for w0, c0, clen in block_partition(n, block, halo):
         idx = (w0 + np.arange(block)) % n
         res = mpa_long_step(a_z0[idx] * taper, omega_b, beta2, beta3, sigma, gamma,
-                            L, M, n_iter)
+                            L, M, n_iter, out_mask=mask)
         out[c0:c0 + clen] = res[halo:halo + clen]
     return out
 

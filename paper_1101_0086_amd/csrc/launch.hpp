@@ -34,7 +34,12 @@ hipError_t launch_block_step(const BlockStepArgs& a);
 // turns = c2[r] k'^2 + c3[r] k'^3 (k' the signed harmonic index),
 // table[r][k] = (cos 2 pi frac(turns), sin 2 pi frac(turns)) stored in the
 // plan precision.  `coef` holds c2[0..rows-1] then c3[0..rows-1] (device).
+// With `mask` (device, g1[0..rows-1] then g2[0..rows-1]) each entry is also
+// multiplied by the block roll-off: with g = |g1 k' + g2 k'^2| (group delay
+// over L in units of the halo duration) and q = 2 |k'| / B (|omega| in units
+// of pi/dt), the factor is d((g - 0.35) / 0.15) d((q - 0.8) / 0.1),
+// d(x) = 1 for x <= 0, 0 for x >= 1, (1 + cos pi x) / 2 between.
 hipError_t launch_phase_table(void* table, int precision, int B, int rows,
-                              const double* coef, hipStream_t stream);
+                              const double* coef, const double* mask, hipStream_t stream);
 
 }  // namespace mpa

@@ -277,20 +277,32 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
         tp[B - 1 - i] = s;
     }
 
-    // the node-M rows again, in FP64
-    std::vector<double> coef_last(2 * (size_t)S);
+    // the node-M rows again, in FP64, times the block roll-off (blocked plans):
+    // g = |beta2 omega + beta3 omega^2 / 2| L / (H dt) with omega = 2 pi k' / (B dt)
+    std::vector<double> coef_last(2 * (size_t)S), mask_last(2 * (size_t)S);
     for (int s = 0; s < S; ++s) {
         coef_last[s] = coef[(size_t)s * (M + 1) + M];
         coef_last[S + s] = coef[rows + (size_t)s * (M + 1) + M];
+        if (p->halo > 0) {
+            const double w1 = 2.0 * pi / bdt;
+            const double hd = params->L / (p->halo * params->dt);
+            mask_last[s] = p->beta2[s] * w1 * hd;
+            mask_last[S + s] = 0.5 * p->beta3[s] * w1 * w1 * hd;
+        }
     }
-    DevBuf dcoef, dlast;
+    DevBuf dcoef, dlast, dmask;
     bool ok = hipMalloc(&dcoef.p, coef.size() * sizeof(double)) == hipSuccess &&
               hipMemcpy(dcoef.p, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
               hipMalloc(&dlast.p, coef_last.size() * sizeof(double)) == hipSuccess &&
               hipMemcpy(dlast.p, coef_last.data(), coef_last.size() * sizeof(double), hipMemcpyHostToDevice) ==
+                  hipSuccess &&
+              hipMalloc(&dmask.p, mask_last.size() * sizeof(double)) == hipSuccess &&
+              hipMemcpy(dmask.p, mask_last.data(), mask_last.size() * sizeof(double), hipMemcpyHostToDevice) ==
                   hipSuccess;
-    if (ok) ok = mpa::launch_phase_table(p->phase, params->precision, B, rows, (const double*)dcoef.p, 0) == hipSuccess;
-    if (ok) ok = mpa::launch_phase_table(p->phase_last, MPA_C128, B, S, (const double*)dlast.p, 0) == hipSuccess;
+    if (ok) ok = mpa::launch_phase_table(p->phase, params->precision, B, rows, (const double*)dcoef.p, nullptr, 0) ==
+                 hipSuccess;
+    if (ok) ok = mpa::launch_phase_table(p->phase_last, MPA_C128, B, S, (const double*)dlast.p,
+                                         p->halo > 0 ? (const double*)dmask.p : nullptr, 0) == hipSuccess;
     auto upload_real = [&](void* dst, const std::vector<double>& v) {
         if (f32) {
             std::vector<float> f(v.begin(), v.end());

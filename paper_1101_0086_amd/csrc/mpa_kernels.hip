@@ -217,9 +217,15 @@ hipError_t launch_block_step(const BlockStepArgs& a) {
 
 // ---- FP64 phase tables --------------------------------------------------------
 
+// 1 for x <= 0, 0 for x >= 1, (1 + cos(pi x)) / 2 in between.
+__device__ __forceinline__ double rc_drop(double x) {
+    return x <= 0.0 ? 1.0 : (x >= 1.0 ? 0.0 : 0.5 * (1.0 + cospi(x)));
+}
+
 template <typename T>
 __global__ void phase_table_kernel(cx<T>* __restrict__ out, int B, int rows,
-                                   const double* __restrict__ coef) {
+                                   const double* __restrict__ coef,
+                                   const double* __restrict__ mask) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)rows * B) return;
     const int r = (int)(idx / B);
@@ -231,20 +237,28 @@ __global__ void phase_table_kernel(cx<T>* __restrict__ out, int B, int rows,
     const double f = turns - rint(turns);                         // reduced to [-1/2, 1/2]
     double s, c;
     sincospi(2.0 * f, &s, &c);
+    if (mask) {
+        // block roll-off: group delay over L in halo units, and |omega| in Nyquist units
+        const double g = fabs(fma(mask[rows + r], k2, mask[r] * kp));
+        const double nyq = 2.0 * fabs(kp) / B;
+        const double m = rc_drop((g - 0.35) / 0.15) * rc_drop((nyq - 0.8) / 0.1);
+        s *= m;
+        c *= m;
+    }
     out[idx] = cx<T>{T(c), T(s)};
 }
 
 hipError_t launch_phase_table(void* table, int precision, int B, int rows, const double* coef,
-                              hipStream_t stream) {
+                              const double* mask, hipStream_t stream) {
     const long long total = (long long)rows * B;
     const int tpb = 256;
     const unsigned grid = (unsigned)((total + tpb - 1) / tpb);
     if (precision == 0)
         hipLaunchKernelGGL(phase_table_kernel<float>, dim3(grid), dim3(tpb), 0, stream,
-                           static_cast<cx<float>*>(table), B, rows, coef);
+                           static_cast<cx<float>*>(table), B, rows, coef, mask);
     else
         hipLaunchKernelGGL(phase_table_kernel<double>, dim3(grid), dim3(tpb), 0, stream,
-                           static_cast<cx<double>*>(table), B, rows, coef);
+                           static_cast<cx<double>*>(table), B, rows, coef, mask);
     return hipGetLastError();
 }
 

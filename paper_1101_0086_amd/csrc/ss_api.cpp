@@ -30,16 +30,56 @@ struct ss_plan {
     std::vector<int64_t> span_steps;
     int64_t period = 0, amp = 0;
     void* tables = nullptr;    // per span: half-step then full-step phasors (N each)
-    void* twiddle = nullptr;
+    void* twiddle = nullptr;   // small path: N phasors
+    bool large = false;        // four-step path
+    int n1 = 0, n2 = 0, split = 0;
+    void* tw1 = nullptr;       // large path twiddles
+    void* tw2 = nullptr;
+    void* twl = nullptr;
+    void* twh = nullptr;
 };
 
 static void ss_free(ss_plan* p) {
     if (!p) return;
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
-    if (p->tables) (void)hipFree(p->tables);
-    if (p->twiddle) (void)hipFree(p->twiddle);
+    for (void* q : {p->tables, p->twiddle, p->tw1, p->tw2, p->twl, p->twh})
+        if (q) (void)hipFree(q);
     delete p;
+}
+
+// One run of `steps` split-steps on the four-step path:
+// column FFT, [row: phase (half first, then full); column: inverse FFT, kick, FFT] x steps,
+// row: final half phase (with the gain), column inverse FFT.
+static bool run_large(ss_plan* p, void* field, const void* half_ph, const void* full_ph, int64_t steps,
+                      double sdz, double hs, double fs, double es, hipStream_t stream) {
+    mpa::SSLargeArgs a;
+    a.field = field;
+    a.n = p->n;
+    a.n1 = p->n1;
+    a.n2 = p->n2;
+    a.tw1 = p->tw1;
+    a.tw2 = p->tw2;
+    a.twl = p->twl;
+    a.twh = p->twh;
+    a.split = p->split;
+    a.sigma_dz = sdz;
+    a.precision = p->precision;
+    a.stream = stream;
+    a.mode = mpa::SS_COL_FIRST;
+    if (mpa::launch_ss_cols(a) != hipSuccess) return false;
+    a.phase = half_ph;
+    a.scale = hs;
+    if (mpa::launch_ss_rows(a) != hipSuccess) return false;
+    for (int64_t j = 1; j <= steps; ++j) {
+        a.mode = mpa::SS_COL_MID;
+        if (mpa::launch_ss_cols(a) != hipSuccess) return false;
+        a.phase = j < steps ? full_ph : half_ph;
+        a.scale = j < steps ? fs : es;
+        if (mpa::launch_ss_rows(a) != hipSuccess) return false;
+    }
+    a.mode = mpa::SS_COL_LAST;
+    return mpa::launch_ss_cols(a) == hipSuccess;
 }
 
 extern "C" {
@@ -60,8 +100,8 @@ int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz, int32_t 
     int64_t period = 0, amp = 0;
     st = schedule_c(map, dz, steps.data(), &period, &amp);
     if (st) return st;
-    if (!mpa::ss_small_supported(precision, n))
-        return fail_status(MPA_EUNSUPPORTED, "split-step window size not compiled in this build");
+    if (!mpa::ss_small_supported(precision, n) && !mpa::ss_large_supported(precision, n))
+        return fail_status(MPA_EUNSUPPORTED, "split-step window size not compiled in this build (512..2^22)");
     st = check_device_c(device);
     if (st) return st;
     if (hipSetDevice(device) != hipSuccess) return fail_status(MPA_EDEVICE, "hipSetDevice failed");
@@ -82,11 +122,8 @@ int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz, int32_t 
 
     const int S = map->n_seg;
     const int rows = 2 * S;
+    p->large = !mpa::ss_small_supported(precision, n);
     const size_t tbytes = (size_t)rows * n * p->elem;
-    if (hipMalloc(&p->tables, tbytes) != hipSuccess || hipMalloc(&p->twiddle, (size_t)n * p->elem) != hipSuccess) {
-        ss_free(p);
-        return fail_status(MPA_ENOMEM, "device allocation failed");
-    }
     const double pi = 3.14159265358979323846;
     const double ndt = (double)n * dt;
     std::vector<double> coef(2 * (size_t)rows);
@@ -96,23 +133,46 @@ int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz, int32_t 
             coef[2 * s + h] = pi * map->beta2[s] * z / (ndt * ndt);
             coef[rows + 2 * s + h] = (2.0 * pi * pi / 3.0) * map->beta3[s] * z / (ndt * ndt * ndt);
         }
-    std::vector<double> tw(2 * (size_t)n);
-    for (int64_t j = 0; j < n; ++j) {
-        const double a = 2.0 * pi * (double)j / (double)n;
-        tw[2 * j] = std::cos(a);
-        tw[2 * j + 1] = std::sin(a);
+    // host tables of phasors exp(+2 pi i j step / len), j = 0..count-1
+    auto phasors = [&](int64_t count, double step, double len) {
+        std::vector<double> v(2 * (size_t)count);
+        for (int64_t j = 0; j < count; ++j) {
+            const double a = 2.0 * pi * (double)j * step / len;
+            v[2 * j] = std::cos(a);
+            v[2 * j + 1] = std::sin(a);
+        }
+        return v;
+    };
+    auto upload = [&](void** dst, const std::vector<double>& v) {
+        const size_t cnt = v.size();
+        if (hipMalloc(dst, cnt * (precision == MPA_C64 ? 4 : 8)) != hipSuccess) return false;
+        if (precision == MPA_C64) {
+            std::vector<float> f(v.begin(), v.end());
+            return hipMemcpy(*dst, f.data(), cnt * 4, hipMemcpyHostToDevice) == hipSuccess;
+        }
+        return hipMemcpy(*dst, v.data(), cnt * 8, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    bool ok = hipMalloc(&p->tables, tbytes) == hipSuccess;
+    if (!ok) {
+        ss_free(p);
+        return fail_status(MPA_ENOMEM, "device allocation failed");
     }
     void* dcoef = nullptr;
-    bool ok = hipMalloc(&dcoef, coef.size() * 8) == hipSuccess &&
-              hipMemcpy(dcoef, coef.data(), coef.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
-    if (ok) ok = mpa::launch_phase_table(p->tables, precision, (int)n, rows, (const double*)dcoef, 0) == hipSuccess;
-    if (ok) {
-        if (precision == MPA_C64) {
-            std::vector<float> f(tw.begin(), tw.end());
-            ok = hipMemcpy(p->twiddle, f.data(), f.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
-        } else {
-            ok = hipMemcpy(p->twiddle, tw.data(), tw.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
-        }
+    ok = hipMalloc(&dcoef, coef.size() * 8) == hipSuccess &&
+         hipMemcpy(dcoef, coef.data(), coef.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+    if (!p->large) {
+        if (ok) ok = mpa::launch_phase_table(p->tables, precision, (int)n, rows, (const double*)dcoef, nullptr, 0) == hipSuccess;
+        if (ok) ok = upload(&p->twiddle, phasors(n, 1.0, (double)n));
+    } else {
+        mpa::ss_large_shape(n, &p->n1, &p->n2);
+        int lg = 0;
+        while ((int64_t(1) << lg) < n) ++lg;
+        p->split = lg / 2;
+        if (ok) ok = mpa::launch_phase_table_t(p->tables, precision, p->n1, p->n2, rows, (const double*)dcoef, 0) ==
+                     hipSuccess;
+        if (ok) ok = upload(&p->tw1, phasors(p->n1, 1.0, p->n1)) && upload(&p->tw2, phasors(p->n2, 1.0, p->n2)) &&
+                     upload(&p->twl, phasors(int64_t(1) << p->split, 1.0, (double)n)) &&
+                     upload(&p->twh, phasors(n >> p->split, (double)(int64_t(1) << p->split), (double)n));
     }
     if (ok) ok = hipDeviceSynchronize() == hipSuccess;
     if (dcoef) (void)hipFree(dcoef);
@@ -155,19 +215,30 @@ int ss_propagate(ss_plan* p, void* field, double z0, double z1, void* stream) {
         }
         const bool amp_end = p->amp > 0 && ((j + run) % p->amp) == 0;
         const double gain = amp_end ? std::exp(p->gamma * p->z_amp) : 1.0;
+        const double hs = std::exp(-0.5 * p->gamma * p->dz) * ln;
+        const double fs = std::exp(-p->gamma * p->dz) * ln;
+        const void* half_ph = (const char*)p->tables + (size_t)(2 * s) * p->n * p->elem;
+        const void* full_ph = (const char*)p->tables + (size_t)(2 * s + 1) * p->n * p->elem;
+        if (p->large) {
+            if (!run_large(p, field, half_ph, full_ph, run, p->sigma[s] * p->dz, hs, fs, hs * gain,
+                           (hipStream_t)stream))
+                return fail_status(MPA_EDEVICE, "split-step launch failed");
+            j += run;
+            continue;
+        }
         while (run > 0) {
             const int chunk = run > (1 << 30) ? (1 << 30) : (int)run;
             mpa::SSRunArgs a;
             a.field = field;
             a.n = p->n;
-            a.half_ph = (const char*)p->tables + (size_t)(2 * s) * p->n * p->elem;
-            a.full_ph = (const char*)p->tables + (size_t)(2 * s + 1) * p->n * p->elem;
+            a.half_ph = half_ph;
+            a.full_ph = full_ph;
             a.twiddle = p->twiddle;
             a.steps = chunk;
             a.sigma_dz = p->sigma[s] * p->dz;
-            a.half_scale = std::exp(-0.5 * p->gamma * p->dz) * ln;
-            a.full_scale = std::exp(-p->gamma * p->dz) * ln;
-            a.end_scale = std::exp(-0.5 * p->gamma * p->dz) * ln * (chunk == run ? gain : 1.0);
+            a.half_scale = hs;
+            a.full_scale = fs;
+            a.end_scale = hs * (chunk == run ? gain : 1.0);
             a.precision = p->precision;
             a.stream = (hipStream_t)stream;
             if (mpa::launch_ss_run_small(a) != hipSuccess)

@@ -39,3 +39,25 @@ def test_split_step_partial_runs():
     plan.close()
     ref = O.ss_propagate(a, w.grid.dt, w.dmmap, dz, 0.3, 1.2)
     assert rel_l2(got, ref) < TOL_F64
+
+
+@pytest.mark.parametrize("n,prec", [(1 << 13, 1), (1 << 14, 0), (1 << 15, 1), (1 << 18, 0)])
+def test_split_step_four_step_path(n, prec):
+    """Windows above one workgroup: row/column kernels of the four-step FFT,
+    across the span change at z = 0.5, against the oracle's Eq. 4."""
+    import paper_1101_0086_amd as P
+    from workloads import Grid, dm_map
+    from workloads.wdm import _fast_wdm_field
+    dt = 10.0 / 1024
+    a = _fast_wdm_field(Grid(n, dt), n // 1024, 8, "ook", np.random.default_rng(9))
+    dmm = dm_map(beta3=0.1)
+    dz = 0.5 / 4000
+    z0, z1 = 0.5 - 4 * dz, 0.5 + 4 * dz
+    say("ss four-step", n, prec)
+    plan = P.SSPlan(n, dt, dmm, dz, prec)
+    x = to_dev(a, prec)
+    plan.propagate(x, z0, z1)
+    got = to_host(x)
+    plan.close()
+    ref = O.ss_propagate(a, dt, dmm, dz, z0, z1)
+    assert rel_l2(got, ref) < (TOL_F64 if prec == 1 else TOL_F32)
