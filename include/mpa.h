@@ -69,8 +69,9 @@ typedef enum {
 } mpa_status;
 
 typedef enum {
-    MPA_C64 = 0,    /* FP32 complex field and FFTs, FP64-built dispersion phases,
-                       compensated FP32 accumulation of the z-integral        */
+    MPA_C64 = 0,    /* FP32 field and node evaluations (2 n_iter M FFTs and the
+                       nonlinearity per block and long step), FP64-built phases,
+                       FP64 carry (psi_0 transform, z-integral, reconstruction) */
     MPA_C128 = 1    /* FP64 everywhere                                        */
 } mpa_precision;
 

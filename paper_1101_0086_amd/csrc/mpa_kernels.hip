@@ -18,31 +18,24 @@
 // the thread owning those frequencies, instead of (M+1) spectra per sweep.
 //
 // Precision.  T is the type of the node evaluations (steps 2-4: 2 n_iter M
-// transforms and the nonlinearity) and of the trapezoid sums S^(n), which
-// are accumulated with Neumaier compensation per component when T is float.
-// The carry of the field across the long step -- the transform giving
-// psi_0, the sums psi_0 + S^(n), the node-M phase and the reconstruction
-// transform -- is always FP64, and the field is rounded to T once, when it
-// is stored.  With FP32 carry transforms the rounding of the FFT with FP32
-// twiddles repeats identically every long step and the error grows linearly
-// with the number of long steps; with the FP64 carry it grows like its
-// square root.  Phases e^{i beta} are built in FP64 (argument reduced in
-// turns) and rounded to T for the node evaluations.
+// transforms and the nonlinearity).  The carry of the field across the long
+// step -- the transform giving psi_0, the trapezoid sums S^(n), the sums
+// psi_0 + S^(n) + U/2, the node-M phase and the reconstruction transform --
+// is always FP64, and the field is rounded to T once, when it is stored.
+// With FP32 carry transforms the rounding of the FFT with FP32 twiddles
+// repeats identically every long step and the error grows linearly with the
+// number of long steps; with the FP64 carry it grows like its square root.
+// On gfx950 an FP64 add issues at the FP32 rate, so FP64 trapezoid sums are
+// both more accurate and cheaper than compensated FP32 sums.  Phases
+// e^{i beta} are built in FP64 (argument reduced in turns) and rounded to T
+// for the node evaluations.
 #include "block_fft.hpp"
 #include "launch.hpp"
 
-#include <type_traits>
 
 namespace mpa {
 
 constexpr int PTS = 8;   // points per thread in the block kernels
-
-__device__ __forceinline__ void comp_add(float& s, float& c, float x) {
-    const float t = s + x;
-    const float e = (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
-    s = t;
-    c += e;
-}
 
 template <typename T>
 __device__ __forceinline__ cx<double> widen(cx<T> a) { return {double(a.re), double(a.im)}; }
@@ -59,7 +52,6 @@ mpa_block_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long lon
                  const double* __restrict__ taper, int M, T d0, double out_scale) {
     constexpr int R = PTS;
     constexpr int NT = B / R;
-    constexpr bool COMP = std::is_same<T, float>::value;
     // one LDS exchange buffer, sized for FP64 and shared by both precisions
     __shared__ cx<double> lds64[lds_elems<B>()];
     cx<T>* ldsT = reinterpret_cast<cx<T>*>(lds64);
@@ -68,10 +60,8 @@ mpa_block_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long lon
     const long long c0 = (long long)blockIdx.x * core;
     const long long w0 = c0 - halo;
 
-    cx<double> psi0[R];
+    cx<double> psi0[R], S[NIT][R];
     cx<T> cur[R], ph[R];
-    cx<T> S[NIT][R];
-    T Cre[COMP ? NIT : 1][R], Cim[COMP ? NIT : 1][R];
 
     // gather the tapered window; node 0 needs |A_0|^2 A_0
 #pragma unroll
@@ -89,15 +79,9 @@ mpa_block_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long lon
     block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        const cx<T> u0 = rot<+1>(scale(cur[m], d0 * T(0.5)));
+        const cx<double> u0 = widen(rot<+1>(scale(cur[m], d0 * T(0.5))));
 #pragma unroll
-        for (int s = 0; s < NIT; ++s) {
-            S[s][m] = u0;
-            if constexpr (COMP) {
-                Cre[s][m] = T(0);
-                Cim[s][m] = T(0);
-            }
-        }
+        for (int s = 0; s < NIT; ++s) S[s][m] = u0;
     }
 
     for (int l = 1; l <= M; ++l) {
@@ -128,26 +112,14 @@ mpa_block_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long lon
             const bool final_sum = last_node && (s == NIT - 1);
 #pragma unroll
             for (int m = 0; m < R; ++m) {
-                const cx<T> u = rot<+1>(scale(cmulc(cur[m], ph[m]), dl));
+                const cx<double> u = widen(rot<+1>(scale(cmulc(cur[m], ph[m]), dl)));
                 // step 5 (Eq. 6): psi^(s+1)_l = psi_0 + S^(s) + U/2, then S^(s) += U
                 if (need_next) {
-                    cx<T> acc = S[s][m];
-                    if constexpr (COMP) {
-                        acc.re += Cre[s][m];
-                        acc.im += Cim[s][m];
-                    }
-                    const cx<double> nxt = psi0[m] + (widen(acc) + scale(widen(u), 0.5));
+                    const cx<double> nxt = psi0[m] + (S[s][m] + scale(u, 0.5));
                     if (final_sum) psi0[m] = nxt;      // psi^(n_iter)_M, kept in FP64
                     else cur[m] = narrow<T>(nxt);
                 }
-                if (!last_node) {
-                    if constexpr (COMP) {
-                        comp_add(S[s][m].re, Cre[s][m], u.re);
-                        comp_add(S[s][m].im, Cim[s][m], u.im);
-                    } else {
-                        S[s][m] = S[s][m] + u;
-                    }
-                }
+                if (!last_node) S[s][m] = S[s][m] + u;
             }
         }
     }

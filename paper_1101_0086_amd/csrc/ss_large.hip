@@ -103,7 +103,9 @@ bool ss_large_supported(int precision, int64_t n) {
 
 template <typename T, int N2>
 static hipError_t rows_t(const SSLargeArgs& a) {
-    constexpr int TR = (256 / (N2 / SL_PTS)) > 0 ? (256 / (N2 / SL_PTS)) : 1;
+    // at least one wave per workgroup; one row per workgroup from N2 = 512 up
+    // (a sweep at 2^18 modes: 4.7 us per pass with one row, 6.5 with four)
+    constexpr int TR = (512 / N2) > 1 ? (512 / N2) : 1;
     if (a.n1 % TR) return hipErrorInvalidValue;
     hipLaunchKernelGGL((ss_rows_kernel<T, N2, TR>), dim3(a.n1 / TR), dim3(TR * N2 / SL_PTS), 0, a.stream,
                        static_cast<cx<T>*>(a.field), a.n1, static_cast<const cx<T>*>(a.tw2),
@@ -114,7 +116,9 @@ static hipError_t rows_t(const SSLargeArgs& a) {
 
 template <typename T, int N1, int MODE>
 static hipError_t cols_tm(const SSLargeArgs& a) {
-    constexpr int TC = (8192 / N1) < 16 ? (8192 / N1) : 16;
+    // 2048 points per workgroup: at 2^18 modes four columns (11.4 us per pass)
+    // beat sixteen (31.4 us, only 32 workgroups) and one or two (14.1, 12.2 us)
+    constexpr int TC = (2048 / N1) > 16 ? 16 : ((2048 / N1) < 1 ? 1 : (2048 / N1));
     if (a.n2 % TC) return hipErrorInvalidValue;
     hipLaunchKernelGGL((ss_cols_kernel<T, N1, TC, MODE>), dim3(a.n2 / TC), dim3(TC * N1 / SL_PTS), 0,
                        a.stream, static_cast<cx<T>*>(a.field), a.n2, static_cast<const cx<T>*>(a.tw1),
