@@ -70,6 +70,7 @@ def main():
     ap.add_argument("--workload", default="wdm8_n262144_f32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip accuracy and split-step comparison")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-instance measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this implementation runs on one GPU; --gpus must be 1 "
@@ -135,11 +136,54 @@ def main():
 
     if not args.no_compare:
         out.update(compare(w, a0, plan, x, torch, P))
+    if not args.no_batch:
+        out["batched"] = batched(torch, P)
     plan.close()
     if not args.no_cpu:
         log("CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
+
+
+def batched(torch, P, count=256, steps=200):
+    """256 independent fields, N uniform over 2^14..2^18, 1-16 channels,
+    sigma uniform in [0.5, 2], 4096-blocks with 512-halos, L = 5e-5, M = 1,
+    2 sweeps: one launch per long step for all instances, eager and as a
+    replayed HIP graph of `steps` long steps."""
+    import numpy as np
+    from workloads import dm_map
+    from workloads.wdm import batched_instances
+    inst = batched_instances(count, 4)
+    ns = [g.n for g, _, _, _ in inst]
+    sig = [s for _, _, s, _ in inst]
+    dt = inst[0][0].dt
+    band = 0.5 * 15 * 40.0 + 5.0
+    L, M, nit = 5e-5, 1, 2
+    bp = P.MPABatchPlan(ns, dt, dm_map(beta3=0.1), L, M, nit, 4096, 512, P.MPA_C64, band, sigma_scale=sig)
+    info = bp.info()
+    x = torch.from_numpy(np.concatenate([f for _, _, _, f in inst])).to(device="cuda:0", dtype=torch.complex64)
+    z1 = steps * L
+    bp.propagate(x, 0.0, z1)                        # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bp.propagate(x, 0.0, z1)
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t0
+    g = bp.capture(x, 0.0, z1)
+    g.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.launch()
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    g.close()
+    bp.close()
+    ms = info["total_samples"] * M * steps
+    log(f"batched: {info['work_items']} work items, eager {ms / t_eager:.3e}, graph {ms / t_graph:.3e} mode-steps/s")
+    return {"instances": count, "total_modes": info["total_samples"], "work_items_per_launch": info["work_items"],
+            "L": L, "M": M, "n_iter": nit, "block": 4096, "halo": 512, "long_steps": steps,
+            "mode_steps_per_s_eager": ms / t_eager, "mode_steps_per_s_graph": ms / t_graph,
+            "us_per_long_step_graph": t_graph / steps * 1e6}
 
 
 def compare(w, a0, plan, x, torch, P):

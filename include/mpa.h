@@ -97,7 +97,8 @@ typedef struct {
     double L;              /* long step; must divide every span and z_amp        */
     int32_t M;             /* quadrature intervals per long step (>= 1)          */
     int32_t n_iter;        /* Picard sweeps per long step (1..5)                 */
-    int32_t block;         /* B: power of two, or 0 / N for one full window      */
+    int32_t block;         /* B: power of two <= N; 0 (or N with halo 0) for one
+                              full periodic window                              */
     int32_t halo;          /* samples of overlap per side (0 for a full window)  */
     int32_t precision;     /* mpa_precision                                      */
     double omega_band;     /* highest |omega| carrying signal, for the halo
@@ -140,6 +141,50 @@ int mpa_step(mpa_plan* plan, void* field, double z0, void* stream);
 /* March long steps from z0 to z1 (both multiples of L, z1 >= z0) in place;
  * the state carried between long steps is the field alone.                  */
 int mpa_propagate(mpa_plan* plan, void* field, double z0, double z1, void* stream);
+
+/* ---- batches of independent fields (one launch per long step for all) ----
+ *
+ * Instances share dt, L, M, n_iter, block, halo, precision and the map (so
+ * they share the phase tables); each has its own length n[i] (a power of two
+ * >= block) and a multiplier sigma_scale[i] of the map's sigma.  The fields
+ * are concatenated in one device buffer: instance i starts at sample
+ * sum_{j<i} n[j].  Each long step is one launch in which a fixed grid of
+ * workgroups walks the list of (instance, block) work items.              */
+typedef struct {
+    int32_t count;               /* number of instances (1..2^20)                 */
+    const int64_t* n;            /* host array: samples of each instance          */
+    const double* sigma_scale;   /* host array or NULL (all 1)                    */
+} mpa_batch_desc;
+
+typedef struct mpa_batch_plan mpa_batch_plan;
+
+/* Host-only validation; params->n is ignored (the instances give the sizes). */
+int mpa_batch_plan_validate(const mpa_params* params, const mpa_map* map,
+                            const mpa_batch_desc* desc);
+int mpa_batch_plan_create(const mpa_params* params, const mpa_map* map,
+                          const mpa_batch_desc* desc, int device, mpa_batch_plan** out);
+int mpa_batch_plan_destroy(mpa_batch_plan* plan);
+int mpa_batch_get_info(const mpa_batch_plan* plan, int64_t* total_samples,
+                       int32_t* work_items);
+
+/* March every instance from z0 to z1 (multiples of L) in place.              */
+int mpa_batch_propagate(mpa_batch_plan* plan, void* fields, double z0, double z1,
+                        void* stream);
+
+/* ---- captured launch sequences (HIP graphs) ------------------------------
+ *
+ * Record the launches of mpa_propagate / mpa_batch_propagate from z0 to z1
+ * on the given buffer into an executable HIP graph (captured on a private
+ * stream; the graph contains kernel nodes only).  Replaying it repeats
+ * exactly that work on the same buffers, so a graph of one period of the
+ * span/amplifier schedule can be replayed to march period after period.   */
+typedef struct mpa_graph mpa_graph;
+
+int mpa_graph_capture(mpa_plan* plan, void* field, double z0, double z1, mpa_graph** out);
+int mpa_batch_graph_capture(mpa_batch_plan* plan, void* fields, double z0, double z1,
+                            mpa_graph** out);
+int mpa_graph_launch(mpa_graph* graph, void* stream);
+int mpa_graph_destroy(mpa_graph* graph);
 
 /* Split-step comparator plan (Eq. 4): step dz must divide every span and
  * z_amp.  Half steps of adjacent split-steps are merged into one spectral

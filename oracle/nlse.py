@@ -163,7 +163,7 @@ def block_partition(n: int, block: int, halo: int) -> List[Tuple[int, int, int]]
     (window_start, core_start, core_len) per block.  block = n (halo = 0)
     gives the single full window.
     """
-    if block == n:
+    if block == n and halo == 0:
         return [(0, 0, n)]
     core = block - 2 * halo
     nb = -(-n // core)
@@ -236,7 +236,7 @@ def mpa_blocked_long_step(a_z0: np.ndarray, dt: float, block: int, halo: int,
     each block's core.  Each window is multiplied by :func:`block_taper`
     first and each block's final spectrum by :func:`block_mask`."""
     n = a_z0.shape[0]
-    if block == 0 or block == n:
+    if block == 0 or (block == n and halo == 0):
         return mpa_long_step(a_z0, omega_grid(n, dt), beta2, beta3, sigma, gamma,
                              L, M, n_iter)
     omega_b = omega_grid(block, dt)

@@ -12,7 +12,7 @@ import ctypes as C
 from . import _lib
 from ._lib import MPA_C64, MPA_C128, MPAError
 
-__all__ = ["MPAPlan", "SSPlan", "MPA_C64", "MPA_C128", "MPAError", "validate"]
+__all__ = ["MPAPlan", "MPABatchPlan", "Graph", "SSPlan", "MPA_C64", "MPA_C128", "MPAError", "validate"]
 
 
 def _stream_handle(torch, device):
@@ -67,6 +67,87 @@ class MPAPlan:
     def close(self):
         if getattr(self, "_h", None):
             _lib.lib().mpa_plan_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+class Graph:
+    """An executable HIP graph of captured launches (mpa_graph_*)."""
+
+    def __init__(self, handle, device):
+        self._h, self.device = handle, device
+
+    def launch(self):
+        import torch
+        _lib.check(_lib.lib().mpa_graph_launch(self._h, _stream_handle(torch, self.device)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().mpa_graph_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+def _capture_propagate(self, field, z0, z1):
+    _check_field(field, self.precision, self.n)
+    h = C.c_void_p()
+    _lib.check(_lib.lib().mpa_graph_capture(self._h, C.c_void_p(field.data_ptr()), float(z0),
+                                            float(z1), C.byref(h)))
+    return Graph(h, field.device)
+
+
+MPAPlan.capture = _capture_propagate
+
+
+class MPABatchPlan:
+    """mpa_batch_plan_create / mpa_batch_propagate: many fields of different
+    lengths (each a power of two >= block) marched by one launch per long
+    step.  Fields are concatenated in one tensor; use :meth:`split` to view
+    the instances."""
+
+    def __init__(self, ns, dt, dmmap, L, M, n_iter, block, halo, precision=MPA_C64,
+                 omega_band=0.0, sigma_scale=None, device=0):
+        self.ns = [int(v) for v in ns]
+        self.n = sum(self.ns)
+        self.precision, self.device = int(precision), int(device)
+        p = _lib.make_params(max(self.ns), dt, L, M, n_iter, block, halo, precision, omega_band)
+        m = _lib.MapStruct(dmmap)
+        d = _lib.BatchDesc(self.ns, sigma_scale)
+        h = C.c_void_p()
+        _lib.check(_lib.lib().mpa_batch_plan_create(C.byref(p), C.byref(m.s), C.byref(d.s),
+                                                    int(device), C.byref(h)))
+        self._h = h
+
+    def info(self):
+        total, items = C.c_int64(), C.c_int32()
+        _lib.check(_lib.lib().mpa_batch_get_info(self._h, C.byref(total), C.byref(items)))
+        return {"total_samples": total.value, "work_items": items.value}
+
+    def split(self, fields):
+        out, o = [], 0
+        for k in self.ns:
+            out.append(fields[o:o + k])
+            o += k
+        return out
+
+    def propagate(self, fields, z0, z1):
+        torch = _check_field(fields, self.precision, self.n)
+        _lib.check(_lib.lib().mpa_batch_propagate(self._h, C.c_void_p(fields.data_ptr()), float(z0),
+                                                  float(z1), _stream_handle(torch, fields.device)))
+        return fields
+
+    def capture(self, fields, z0, z1):
+        _check_field(fields, self.precision, self.n)
+        h = C.c_void_p()
+        _lib.check(_lib.lib().mpa_batch_graph_capture(self._h, C.c_void_p(fields.data_ptr()), float(z0),
+                                                      float(z1), C.byref(h)))
+        return Graph(h, fields.device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().mpa_batch_plan_destroy(self._h)
             self._h = None
 
     __del__ = close

@@ -24,8 +24,10 @@ MPA_C128 = 1
 
 # symbols declared in include/mpa.h
 EXPORTED = ("mpa_plan_create", "mpa_plan_destroy", "mpa_plan_get_info", "mpa_plan_validate",
-            "mpa_step", "mpa_propagate", "ss_plan_create", "ss_plan_destroy", "ss_propagate",
-            "mpa_status_string", "mpa_last_error")
+            "mpa_step", "mpa_propagate", "mpa_batch_plan_validate", "mpa_batch_plan_create",
+            "mpa_batch_plan_destroy", "mpa_batch_get_info", "mpa_batch_propagate",
+            "mpa_graph_capture", "mpa_batch_graph_capture", "mpa_graph_launch", "mpa_graph_destroy",
+            "ss_plan_create", "ss_plan_destroy", "ss_propagate", "mpa_status_string", "mpa_last_error")
 
 
 class mpa_map(C.Structure):
@@ -38,6 +40,10 @@ class mpa_params(C.Structure):
     _fields_ = [("n", C.c_int64), ("dt", C.c_double), ("L", C.c_double), ("M", C.c_int32),
                 ("n_iter", C.c_int32), ("block", C.c_int32), ("halo", C.c_int32),
                 ("precision", C.c_int32), ("omega_band", C.c_double)]
+
+
+class mpa_batch_desc(C.Structure):
+    _fields_ = [("count", C.c_int32), ("n", C.POINTER(C.c_int64)), ("sigma_scale", C.POINTER(C.c_double))]
 
 
 class mpa_plan_info(C.Structure):
@@ -75,6 +81,16 @@ def lib() -> C.CDLL:
     h.mpa_plan_validate.argtypes = [C.POINTER(mpa_params), C.POINTER(mpa_map)]
     h.mpa_step.argtypes = [vp, vp, dp, vp]
     h.mpa_propagate.argtypes = [vp, vp, dp, dp, vp]
+    h.mpa_batch_plan_validate.argtypes = [C.POINTER(mpa_params), C.POINTER(mpa_map), C.POINTER(mpa_batch_desc)]
+    h.mpa_batch_plan_create.argtypes = [C.POINTER(mpa_params), C.POINTER(mpa_map), C.POINTER(mpa_batch_desc),
+                                        C.c_int, C.POINTER(vp)]
+    h.mpa_batch_plan_destroy.argtypes = [vp]
+    h.mpa_batch_get_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+    h.mpa_batch_propagate.argtypes = [vp, vp, dp, dp, vp]
+    h.mpa_graph_capture.argtypes = [vp, vp, dp, dp, C.POINTER(vp)]
+    h.mpa_batch_graph_capture.argtypes = [vp, vp, dp, dp, C.POINTER(vp)]
+    h.mpa_graph_launch.argtypes = [vp, vp]
+    h.mpa_graph_destroy.argtypes = [vp]
     h.ss_plan_create.argtypes = [C.POINTER(mpa_map), C.c_int64, dp, dp, C.c_int32, C.c_int, C.POINTER(vp)]
     h.ss_plan_destroy.argtypes = [vp]
     h.ss_propagate.argtypes = [vp, vp, dp, dp, vp]
@@ -109,3 +125,13 @@ class MapStruct:
 def make_params(n, dt, L, M, n_iter, block=0, halo=0, precision=MPA_C64, omega_band=0.0):
     return mpa_params(int(n), float(dt), float(L), int(M), int(n_iter), int(block), int(halo),
                       int(precision), float(omega_band))
+
+
+class BatchDesc:
+    """Keeps the ctypes arrays of an mpa_batch_desc alive."""
+
+    def __init__(self, ns, sigma_scale=None):
+        k = len(ns)
+        self._n = (C.c_int64 * k)(*[int(v) for v in ns])
+        self._s = (C.c_double * k)(*[float(v) for v in sigma_scale]) if sigma_scale is not None else None
+        self.s = mpa_batch_desc(k, self._n, self._s if self._s is not None else None)

@@ -7,7 +7,18 @@
 
 namespace mpa {
 
-// One fused long step over every block of one field.
+// Work list of a batched launch (device arrays).
+struct BatchItems {
+    const void* items;        // int2 {instance, block} per work item
+    int32_t n_items;
+    const void* offset;       // int64 start of each instance in the concatenated fields
+    const void* len;          // int64 samples of each instance
+    const void* sigma_scale;  // double multiplier of the span's sigma per instance
+    int32_t grid;             // workgroups walking the list
+};
+
+// One fused long step over every block of one field (batch == nullptr) or
+// of every instance of a batch.
 struct BlockStepArgs {
     const void* in;          // field at z0 (N complex of the plan's precision)
     void* out;               // field at z0 + L (must not alias `in`)
@@ -15,20 +26,22 @@ struct BlockStepArgs {
     int32_t block, halo, core, n_blocks;
     const void* phase;       // (M+1) x B unit phasors e^{i beta(omega_k, z_j)} of the span
     const void* phase_last;  // B FP64 phasors of node M of the span (reconstruction)
-    const void* node_scale;  // 2 (M+1) reals per span: c_j = e^{Gamma_j}/B, d_j = sigma dz e^{-Gamma_j}
+    const void* node_scale;  // 2 (M+1) reals per span: c_j = e^{Gamma_j}/B, e_j = dz e^{-Gamma_j}
     const void* twiddle;     // B phasors exp(+2 pi i j / B), node precision
     const void* twiddle64;   // the same in FP64 (carry transforms)
     const void* taper;       // B FP64 reals
     int32_t M, n_iter;
-    double d0;               // sigma dz (node 0)
+    double sigma;            // the span's sigma (times the instance's scale for a batch)
     double out_scale;        // e^{Gamma_M} / B, times the lumped gain
     int32_t precision;       // 0: FP32 field / 1: FP64
+    const BatchItems* batch; // nullptr for a single field
     hipStream_t stream;
 };
 
 bool block_step_supported(int precision, int block, int n_iter);
 int threads_per_block(int precision, int block);
 hipError_t launch_block_step(const BlockStepArgs& a);
+hipError_t launch_copy_field(const void* src, void* dst, int64_t count, int precision, hipStream_t stream);
 
 // FP64 phase table: rows r = 0..rows-1, column k = 0..B-1,
 // turns = c2[r] k'^2 + c3[r] k'^3 (k' the signed harmonic index),

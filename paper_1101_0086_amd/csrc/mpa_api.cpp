@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -159,7 +160,7 @@ static int validate_params(const mpa_params* p, const mpa_map* map, Schedule* sc
     if (p->precision != MPA_C64 && p->precision != MPA_C128)
         return fail(MPA_EINVAL, "precision = %d is not MPA_C64 or MPA_C128", p->precision);
     if (!(p->omega_band >= 0) || !is_finite(p->omega_band)) return fail(MPA_EINVAL, "omega_band must be >= 0");
-    const bool full = (p->block == 0 || p->block == p->n);
+    const bool full = (p->block == 0 || (p->block == p->n && p->halo == 0));
     if (full) {
         if (p->halo != 0) return fail(MPA_EINVAL, "halo must be 0 for a full-window plan");
     } else {
@@ -210,7 +211,7 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
     p->prm = *params;
     p->device = device;
     p->sched = sched;
-    const bool full = (params->block == 0 || params->block == params->n);
+    const bool full = (params->block == 0 || (params->block == params->n && params->halo == 0));
     p->block = full ? (int)params->n : params->block;
     p->halo = full ? 0 : params->halo;
     p->core = p->block - 2 * p->halo;
@@ -254,13 +255,14 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
             coef[(size_t)s * (M + 1) + j] = pi * p->beta2[s] * z / (bdt * bdt);
             coef[rows + (size_t)s * (M + 1) + j] = (2.0 * pi * pi / 3.0) * p->beta3[s] * z / (bdt * bdt * bdt);
         }
-    // node scalars: c_j = e^{Gamma_j} / B, d_j = sigma dz e^{-Gamma_j}, Gamma_j = -gamma j dz
+    // node scalars: c_j = e^{Gamma_j} / B, e_j = dz e^{-Gamma_j}, Gamma_j = -gamma j dz
+    // (sigma multiplies e_j in the kernel, so batches can scale it per instance)
     std::vector<double> ns((size_t)S * 2 * (M + 1));
     for (int s = 0; s < S; ++s)
         for (int j = 0; j <= M; ++j) {
             const double g = -p->gamma * j * dz;
             ns[(size_t)s * 2 * (M + 1) + 2 * j] = std::exp(g) / B;
-            ns[(size_t)s * 2 * (M + 1) + 2 * j + 1] = p->sigma[s] * dz * std::exp(-g);
+            ns[(size_t)s * 2 * (M + 1) + 2 * j + 1] = dz * std::exp(-g);
         }
     // twiddles exp(+2 pi i j / B) and the erf taper over the outer halo/2 samples
     std::vector<double> tw(2 * (size_t)B), tp((size_t)B, 1.0);
@@ -340,10 +342,10 @@ int mpa_plan_get_info(const mpa_plan* p, mpa_plan_info* info) {
     return MPA_OK;
 }
 
-static int launch_long_step(mpa_plan* p, const void* in, void* out, int64_t m, hipStream_t stream) {
+static int launch_long_step(mpa_plan* p, const void* in, void* out, int64_t m, hipStream_t stream,
+                            const mpa::BatchItems* batch = nullptr) {
     const int s = p->sched.span_of(m);
     const int M = p->prm.M;
-    const double dz = p->prm.L / M;
     const double gain = p->sched.amp_after(m) ? std::exp(p->gamma * p->z_amp) : 1.0;
     mpa::BlockStepArgs a;
     a.in = in;
@@ -361,9 +363,10 @@ static int launch_long_step(mpa_plan* p, const void* in, void* out, int64_t m, h
     a.taper = p->taper;
     a.M = M;
     a.n_iter = p->prm.n_iter;
-    a.d0 = p->sigma[s] * dz;
+    a.sigma = p->sigma[s];
     a.out_scale = std::exp(-p->gamma * p->prm.L) / p->block * gain;
     a.precision = p->prm.precision;
+    a.batch = batch;
     a.stream = stream;
     const hipError_t e = mpa::launch_block_step(a);
     if (e != hipSuccess) return fail(MPA_EDEVICE, "block step launch failed: %s", hipGetErrorString(e));
@@ -378,31 +381,228 @@ int mpa_step(mpa_plan* p, void* field, double z0, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     int st = launch_long_step(p, field, p->work, m, s);
     if (st) return st;
-    if (hipMemcpyAsync(field, p->work, (size_t)p->prm.n * p->elem, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    if (mpa::launch_copy_field(p->work, field, p->prm.n, p->prm.precision, s) != hipSuccess)
+        return fail(MPA_EDEVICE, "copy back failed");
+    return MPA_OK;
+}
+
+static int march(mpa_plan* p, void* field, void* work, int64_t count, double z0, double z1, hipStream_t s,
+                 const mpa::BatchItems* batch) {
+    const int64_t m0 = grid_index(z0, p->prm.L), m1 = grid_index(z1, p->prm.L);
+    if (m0 == INT64_MIN || m1 == INT64_MIN)
+        return fail(MPA_EALIGN, "z0 = %g or z1 = %g is not a multiple of L = %g", z0, z1, p->prm.L);
+    if (m1 < m0) return fail(MPA_EINVAL, "z1 < z0");
+    void* src = field;
+    void* dst = work;
+    for (int64_t m = m0; m < m1; ++m) {
+        int st = launch_long_step(p, src, dst, m, s, batch);
+        if (st) return st;
+        void* t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != field && mpa::launch_copy_field(src, field, count, p->prm.precision, s) != hipSuccess)
         return fail(MPA_EDEVICE, "copy back failed");
     return MPA_OK;
 }
 
 int mpa_propagate(mpa_plan* p, void* field, double z0, double z1, void* stream) {
     if (!p || !field) return fail(MPA_EINVAL, "NULL plan or field");
-    const int64_t m0 = grid_index(z0, p->prm.L), m1 = grid_index(z1, p->prm.L);
-    if (m0 == INT64_MIN || m1 == INT64_MIN)
-        return fail(MPA_EALIGN, "z0 = %g or z1 = %g is not a multiple of L = %g", z0, z1, p->prm.L);
-    if (m1 < m0) return fail(MPA_EINVAL, "z1 < z0");
     if (hipSetDevice(p->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
-    hipStream_t s = (hipStream_t)stream;
-    void* src = field;
-    void* dst = p->work;
-    for (int64_t m = m0; m < m1; ++m) {
-        int st = launch_long_step(p, src, dst, m, s);
-        if (st) return st;
-        void* t = src;
-        src = dst;
-        dst = t;
+    return march(p, field, p->work, p->prm.n, z0, z1, (hipStream_t)stream, nullptr);
+}
+
+// ---- batches of independent fields -------------------------------------------------
+
+struct mpa_batch_plan {
+    mpa_plan* base = nullptr;           // shared tables (plan of the longest instance)
+    std::vector<int64_t> len, offset;
+    std::vector<double> sigma_scale;
+    int64_t total = 0;
+    mpa::BatchItems items{};
+    void* d_items = nullptr;
+    void* d_offset = nullptr;
+    void* d_len = nullptr;
+    void* d_sigma = nullptr;
+    void* work = nullptr;
+};
+
+static void batch_free(mpa_batch_plan* b) {
+    if (!b) return;
+    if (b->base) {
+        (void)hipSetDevice(b->base->device);
+        (void)hipDeviceSynchronize();
     }
-    if (src != field &&
-        hipMemcpyAsync(field, src, (size_t)p->prm.n * p->elem, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return fail(MPA_EDEVICE, "copy back failed");
+    for (void* q : {b->d_items, b->d_offset, b->d_len, b->d_sigma, b->work})
+        if (q) (void)hipFree(q);
+    plan_free(b->base);
+    delete b;
+}
+
+int mpa_batch_plan_validate(const mpa_params* params, const mpa_map* map, const mpa_batch_desc* desc) {
+    if (!params || !desc) return fail(MPA_EINVAL, "NULL params or batch description");
+    if (desc->count < 1 || desc->count > (1 << 20) || !desc->n)
+        return fail(MPA_EINVAL, "batch count must be in 1..2^20 with an n array");
+    if (params->block <= 0 || params->halo <= 0)
+        return fail(MPA_EINVAL, "a batch needs time blocks (block > 0, halo > 0)");
+    int64_t nmax = 0;
+    for (int i = 0; i < desc->count; ++i) {
+        const int64_t n = desc->n[i];
+        if (!is_pow2(n) || n < params->block || n > (int64_t(1) << 30))
+            return fail(MPA_EINVAL, "instance %d: n = %lld must be a power of two >= block", i, (long long)n);
+        if (desc->sigma_scale && !is_finite(desc->sigma_scale[i]))
+            return fail(MPA_EINVAL, "instance %d: sigma_scale must be finite", i);
+        if (n > nmax) nmax = n;
+    }
+    mpa_params q = *params;
+    q.n = nmax;
+    Schedule sched;
+    return validate_params(&q, map, &sched);
+}
+
+int mpa_batch_plan_create(const mpa_params* params, const mpa_map* map, const mpa_batch_desc* desc, int device,
+                          mpa_batch_plan** out) {
+    if (!out) return fail(MPA_EINVAL, "out is NULL");
+    *out = nullptr;
+    int st = mpa_batch_plan_validate(params, map, desc);
+    if (st) return st;
+    int64_t nmax = 0;
+    for (int i = 0; i < desc->count; ++i) nmax = desc->n[i] > nmax ? desc->n[i] : nmax;
+    mpa_params q = *params;
+    q.n = nmax;
+    auto* b = new mpa_batch_plan();
+    st = mpa_plan_create(&q, map, device, &b->base);
+    if (st) {
+        delete b;
+        return st;
+    }
+    const int C = b->base->core;
+    std::vector<int> items;
+    for (int i = 0; i < desc->count; ++i) {
+        b->len.push_back(desc->n[i]);
+        b->offset.push_back(b->total);
+        b->sigma_scale.push_back(desc->sigma_scale ? desc->sigma_scale[i] : 1.0);
+        b->total += desc->n[i];
+        const int nb = (int)((desc->n[i] + C - 1) / C);
+        for (int k = 0; k < nb; ++k) {
+            items.push_back(i);
+            items.push_back(k);
+        }
+    }
+    const int n_items = (int)(items.size() / 2);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0) cus = 256;
+    bool ok = hipMalloc(&b->d_items, items.size() * sizeof(int)) == hipSuccess &&
+              hipMalloc(&b->d_offset, b->offset.size() * 8) == hipSuccess &&
+              hipMalloc(&b->d_len, b->len.size() * 8) == hipSuccess &&
+              hipMalloc(&b->d_sigma, b->sigma_scale.size() * 8) == hipSuccess &&
+              hipMalloc(&b->work, (size_t)b->total * b->base->elem) == hipSuccess;
+    if (!ok) {
+        batch_free(b);
+        return fail(MPA_ENOMEM, "batch allocation failed");
+    }
+    ok = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->d_offset, b->offset.data(), b->offset.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->d_len, b->len.data(), b->len.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->d_sigma, b->sigma_scale.data(), b->sigma_scale.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        batch_free(b);
+        return fail(MPA_EDEVICE, "batch upload failed");
+    }
+    b->items.items = b->d_items;
+    b->items.n_items = n_items;
+    b->items.offset = b->d_offset;
+    b->items.len = b->d_len;
+    b->items.sigma_scale = b->d_sigma;
+    b->items.grid = n_items < 4 * cus ? n_items : 4 * cus;
+    *out = b;
+    return MPA_OK;
+}
+
+int mpa_batch_plan_destroy(mpa_batch_plan* plan) {
+    batch_free(plan);
+    return MPA_OK;
+}
+
+int mpa_batch_get_info(const mpa_batch_plan* b, int64_t* total_samples, int32_t* work_items) {
+    if (!b) return fail(MPA_EINVAL, "NULL batch plan");
+    if (total_samples) *total_samples = b->total;
+    if (work_items) *work_items = b->items.n_items;
+    return MPA_OK;
+}
+
+int mpa_batch_propagate(mpa_batch_plan* b, void* fields, double z0, double z1, void* stream) {
+    if (!b || !fields) return fail(MPA_EINVAL, "NULL batch plan or fields");
+    if (hipSetDevice(b->base->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
+    return march(b->base, fields, b->work, b->total, z0, z1, (hipStream_t)stream, &b->items);
+}
+
+// ---- captured launch sequences ----------------------------------------------------
+
+struct mpa_graph {
+    int device = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static void graph_free(mpa_graph* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+static int capture(int device, const std::function<int(hipStream_t)>& body, mpa_graph** out) {
+    if (!out) return fail(MPA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (hipSetDevice(device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+        return fail(MPA_EDEVICE, "capture stream creation failed");
+    auto* g = new mpa_graph();
+    g->device = device;
+    int st = MPA_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        st = fail(MPA_EDEVICE, "hipStreamBeginCapture failed");
+    } else {
+        const int body_st = body(cs);
+        const hipError_t e = hipStreamEndCapture(cs, &g->graph);
+        if (body_st) st = body_st;
+        else if (e != hipSuccess || !g->graph) st = fail(MPA_EDEVICE, "hipStreamEndCapture failed");
+        else if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+            st = fail(MPA_EDEVICE, "hipGraphInstantiate failed");
+    }
+    (void)hipStreamDestroy(cs);
+    if (st) {
+        graph_free(g);
+        return st;
+    }
+    *out = g;
+    return MPA_OK;
+}
+
+int mpa_graph_capture(mpa_plan* p, void* field, double z0, double z1, mpa_graph** out) {
+    if (!p || !field) return fail(MPA_EINVAL, "NULL plan or field");
+    return capture(p->device, [&](hipStream_t cs) { return march(p, field, p->work, p->prm.n, z0, z1, cs, nullptr); },
+                   out);
+}
+
+int mpa_batch_graph_capture(mpa_batch_plan* b, void* fields, double z0, double z1, mpa_graph** out) {
+    if (!b || !fields) return fail(MPA_EINVAL, "NULL batch plan or fields");
+    return capture(b->base->device,
+                   [&](hipStream_t cs) { return march(b->base, fields, b->work, b->total, z0, z1, cs, &b->items); },
+                   out);
+}
+
+int mpa_graph_launch(mpa_graph* g, void* stream) {
+    if (!g) return fail(MPA_EINVAL, "NULL graph");
+    if (hipSetDevice(g->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
+    if (hipGraphLaunch(g->exec, (hipStream_t)stream) != hipSuccess) return fail(MPA_EDEVICE, "hipGraphLaunch failed");
+    return MPA_OK;
+}
+
+int mpa_graph_destroy(mpa_graph* g) {
+    graph_free(g);
     return MPA_OK;
 }
 

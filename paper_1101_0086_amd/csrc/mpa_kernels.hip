@@ -37,118 +37,100 @@ namespace mpa {
 
 constexpr int PTS = 8;   // points per thread in the block kernels
 
+
 template <typename T>
 __device__ __forceinline__ cx<double> widen(cx<T> a) { return {double(a.re), double(a.im)}; }
 
 template <typename T>
 __device__ __forceinline__ cx<T> narrow(cx<double> a) { return {T(a.re), T(a.im)}; }
 
+// Tables shared by every block of a plan (one span's rows).
+template <typename T>
+struct StepTables {
+    const cx<T>* __restrict__ phase;           // (M+1) x B node phasors e^{i beta_j}
+    const cx<double>* __restrict__ phase_last; // B FP64 node-M phasors times the block roll-off
+    const T* __restrict__ node_scale;          // 2 (M+1): c_j = e^{Gamma_j}/B, e_j = dz e^{-Gamma_j}
+    const cx<T>* __restrict__ tw;              // B twiddles exp(+2 pi i j / B)
+    const cx<double>* __restrict__ tw64;       // the same in FP64
+    const double* __restrict__ taper;          // B window weights
+};
+
+// One field: one workgroup per block.
 template <typename T, int B, int NIT>
 __global__ void __launch_bounds__(B / PTS)
-mpa_block_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long long n,
-                 int core, int halo, const cx<T>* __restrict__ phase,
-                 const cx<double>* __restrict__ phase_last, const T* __restrict__ node_scale,
-                 const cx<T>* __restrict__ tw, const cx<double>* __restrict__ tw64,
-                 const double* __restrict__ taper, int M, T d0, double out_scale) {
-    constexpr int R = PTS;
-    constexpr int NT = B / R;
+mpa_block_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long long n, int core,
+                 int halo, const cx<T>* __restrict__ phase, const cx<double>* __restrict__ phase_last,
+                 const T* __restrict__ node_scale, const cx<T>* __restrict__ tw,
+                 const cx<double>* __restrict__ tw64, const double* __restrict__ taper, int M, T sigma,
+                 double out_scale) {
     // one LDS exchange buffer, sized for FP64 and shared by both precisions
     __shared__ cx<double> lds64[lds_elems<B>()];
-    cx<T>* ldsT = reinterpret_cast<cx<T>*>(lds64);
-
-    const int tid = threadIdx.x;
     const long long c0 = (long long)blockIdx.x * core;
-    const long long w0 = c0 - halo;
+    const int thread = threadIdx.x;
+#include "long_step_body.inc"
+}
 
-    cx<double> psi0[R], S[NIT][R];
-    cx<T> cur[R], ph[R];
-
-    // gather the tapered window; node 0 needs |A_0|^2 A_0
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-        const int t = tid + NT * m;
-        long long g = w0 + t;
-        if (g < 0) g += n;
-        if (g >= n) g -= n;
-        const cx<double> a = scale(widen(in[g]), taper[t]);
-        psi0[m] = a;
-        cur[m] = narrow<T>(scale(a, norm2(a)));
+// Many fields of different lengths, concatenated: a fixed grid of
+// workgroups walks the static list of (instance, block) work items; every
+// workgroup leaves the loop once the list is exhausted.
+template <typename T, int B, int NIT>
+__global__ void __launch_bounds__(B / PTS)
+mpa_batch_kernel(const cx<T>* __restrict__ fin, cx<T>* __restrict__ fout,
+                 const int2* __restrict__ items, int n_items, const long long* __restrict__ offset,
+                 const long long* __restrict__ len, const double* __restrict__ sigma_scale, int core,
+                 int halo, const cx<T>* __restrict__ phase, const cx<double>* __restrict__ phase_last,
+                 const T* __restrict__ node_scale, const cx<T>* __restrict__ tw,
+                 const cx<double>* __restrict__ tw64, const double* __restrict__ taper, int M,
+                 double sigma_span, double out_scale) {
+    __shared__ cx<double> lds64[lds_elems<B>()];
+    for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+        const int2 it = items[w];
+        const cx<T>* __restrict__ in = fin + offset[it.x];
+        cx<T>* __restrict__ out = fout + offset[it.x];
+        const long long n = len[it.x];
+        const long long c0 = (long long)it.y * core;
+        const T sigma = T(sigma_span * sigma_scale[it.x]);
+        // the thread index, hidden from the optimiser for each work item: every
+        // address and table load derived from it is then computed inside the
+        // item loop instead of being hoisted out of it and spilled
+        int thread = threadIdx.x;
+        asm volatile("" : "+v"(thread));
+        __syncthreads();
+#include "long_step_body.inc"
     }
-    // step 1 and node 0: psi_0 = F[A_0] (FP64); U_0 = i sigma dz F[|A_0|^2 A_0]
-    block_fft<double, B, R, +1>(psi0, lds64, tw64, tid);
-    block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-        const cx<double> u0 = widen(rot<+1>(scale(cur[m], d0 * T(0.5))));
-#pragma unroll
-        for (int s = 0; s < NIT; ++s) S[s][m] = u0;
-    }
+}
 
-    for (int l = 1; l <= M; ++l) {
-        const cx<T>* __restrict__ phl = phase + (size_t)l * B;
-        const T cl = node_scale[2 * l];
-        const T dl = node_scale[2 * l + 1];
-#pragma unroll
-        for (int m = 0; m < R; ++m) {
-            ph[m] = phl[tid + NT * m];
-            cur[m] = narrow<T>(psi0[m]);
-        }
-        const bool last_node = (l == M);
-#pragma unroll
-        for (int s = 0; s < NIT; ++s) {
-            // steps 2-3: A = e^{Gamma_l} F^-1[psi e^{i beta_l}]
-#pragma unroll
-            for (int m = 0; m < R; ++m) cur[m] = cmul(cur[m], ph[m]);
-            block_fft<T, B, R, -1>(cur, ldsT, tw, tid);
-            // nonlinearity |A|^2 A
-#pragma unroll
-            for (int m = 0; m < R; ++m) {
-                const cx<T> a = scale(cur[m], cl);
-                cur[m] = scale(a, norm2(a));
-            }
-            // step 4: U = i sigma dz e^{-Gamma_l} e^{-i beta_l} F[|A|^2 A]
-            block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
-            const bool need_next = (s < NIT - 1) || last_node;
-            const bool final_sum = last_node && (s == NIT - 1);
-#pragma unroll
-            for (int m = 0; m < R; ++m) {
-                const cx<double> u = widen(rot<+1>(scale(cmulc(cur[m], ph[m]), dl)));
-                // step 5 (Eq. 6): psi^(s+1)_l = psi_0 + S^(s) + U/2, then S^(s) += U
-                if (need_next) {
-                    const cx<double> nxt = psi0[m] + (S[s][m] + scale(u, 0.5));
-                    if (final_sum) psi0[m] = nxt;      // psi^(n_iter)_M, kept in FP64
-                    else cur[m] = narrow<T>(nxt);
-                }
-                if (!last_node) S[s][m] = S[s][m] + u;
-            }
-        }
-    }
+template <typename T>
+__global__ void copy_field_kernel(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, long long count) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) dst[i] = src[i];
+}
 
-    // step 7: reconstruct A(z0 + L) from psi^(n_iter)_M in FP64
-    const cx<double>* __restrict__ phM = phase_last;
-#pragma unroll
-    for (int m = 0; m < R; ++m) psi0[m] = scale(cmul(psi0[m], phM[tid + NT * m]), out_scale);
-    block_fft<double, B, R, -1>(psi0, lds64, tw64, tid);
-
-    // scatter the core
-    const long long rest = n - c0;
-    const int clen = rest < core ? (int)rest : core;
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-        const int t = tid + NT * m;
-        if (t >= halo && t < halo + clen) out[c0 + (t - halo)] = narrow<T>(psi0[m]);
-    }
+template <typename T>
+static StepTables<T> tables_of(const BlockStepArgs& a) {
+    return StepTables<T>{static_cast<const cx<T>*>(a.phase), static_cast<const cx<double>*>(a.phase_last),
+                         static_cast<const T*>(a.node_scale), static_cast<const cx<T>*>(a.twiddle),
+                         static_cast<const cx<double>*>(a.twiddle64), static_cast<const double*>(a.taper)};
 }
 
 template <typename T, int B, int NIT>
 static hipError_t launch_typed(const BlockStepArgs& a) {
-    hipLaunchKernelGGL((mpa_block_kernel<T, B, NIT>), dim3(a.n_blocks), dim3(B / PTS), 0,
-                       a.stream, static_cast<const cx<T>*>(a.in), static_cast<cx<T>*>(a.out),
-                       (long long)a.n, a.core, a.halo, static_cast<const cx<T>*>(a.phase),
-                       static_cast<const cx<double>*>(a.phase_last),
-                       static_cast<const T*>(a.node_scale), static_cast<const cx<T>*>(a.twiddle),
-                       static_cast<const cx<double>*>(a.twiddle64),
-                       static_cast<const double*>(a.taper), a.M, T(a.d0), a.out_scale);
+    if (a.batch == nullptr) {
+        const StepTables<T> t = tables_of<T>(a);
+        hipLaunchKernelGGL((mpa_block_kernel<T, B, NIT>), dim3(a.n_blocks), dim3(B / PTS), 0, a.stream,
+                           static_cast<const cx<T>*>(a.in), static_cast<cx<T>*>(a.out), (long long)a.n,
+                           a.core, a.halo, t.phase, t.phase_last, t.node_scale, t.tw, t.tw64, t.taper, a.M,
+                           T(a.sigma), a.out_scale);
+    } else {
+        const StepTables<T> t = tables_of<T>(a);
+        const BatchItems& b = *a.batch;
+        hipLaunchKernelGGL((mpa_batch_kernel<T, B, NIT>), dim3(b.grid), dim3(B / PTS), 0, a.stream,
+                           static_cast<const cx<T>*>(a.in), static_cast<cx<T>*>(a.out),
+                           static_cast<const int2*>(b.items), b.n_items, static_cast<const long long*>(b.offset),
+                           static_cast<const long long*>(b.len), static_cast<const double*>(b.sigma_scale),
+                           a.core, a.halo, t.phase, t.phase_last, t.node_scale, t.tw, t.tw64, t.taper, a.M,
+                           a.sigma, a.out_scale);
+    }
     return hipGetLastError();
 }
 
@@ -185,6 +167,19 @@ int threads_per_block(int precision, int block) { return block / PTS; }
 hipError_t launch_block_step(const BlockStepArgs& a) {
     if (!block_step_supported(a.precision, a.block, a.n_iter)) return hipErrorInvalidValue;
     return a.precision == 0 ? launch_b<float>(a) : launch_b<double>(a);
+}
+
+hipError_t launch_copy_field(const void* src, void* dst, int64_t count, int precision, hipStream_t stream) {
+    const int tpb = 256;
+    const long long want = (count + tpb - 1) / tpb;
+    const unsigned grid = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+    if (precision == 0)
+        hipLaunchKernelGGL(copy_field_kernel<float>, dim3(grid), dim3(tpb), 0, stream,
+                           static_cast<const cx<float>*>(src), static_cast<cx<float>*>(dst), (long long)count);
+    else
+        hipLaunchKernelGGL(copy_field_kernel<double>, dim3(grid), dim3(tpb), 0, stream,
+                           static_cast<const cx<double>*>(src), static_cast<cx<double>*>(dst), (long long)count);
+    return hipGetLastError();
 }
 
 // ---- FP64 phase tables --------------------------------------------------------

@@ -65,7 +65,10 @@ def test_validation_status_codes():
     assert _validate(dmmap=dm_map(beta3=0.1, z_amp=1.0 / 3.0)) == L.MPA_EALIGN
     # a full-window plan needs no halo rule
     assert _validate(n=4096, block=0, halo=0, L=0.05) == L.MPA_OK
-    assert _validate(n=4096, block=4096, halo=8, L=0.05) == L.MPA_EINVAL
+    assert _validate(n=4096, block=4096, halo=0, L=0.05) == L.MPA_OK
+    assert _validate(n=4096, block=0, halo=8, L=0.05) == L.MPA_EINVAL
+    # block = n with a halo is a blocked run (two overlapping blocks), so the halo rule applies
+    assert _validate(n=4096, block=4096, halo=512, L=0.05) == L.MPA_EHALO
 
 
 def test_error_message_and_status_strings():
@@ -96,3 +99,22 @@ def test_python_binding_raises_on_invalid():
     with pytest.raises(P.MPAError) as e:
         P.validate(w.grid.n, w.grid.dt, w.dmmap, 1e-3, 2, 2, 4096, 512, P.MPA_C64, w.mpa.omega_band)
     assert e.value.status == -5
+
+
+def test_batch_validation():
+    L = _lib()
+    import ctypes as C
+    w = WORKLOADS["wdm8_n262144_f32"]
+    p = L.make_params(0, w.grid.dt, w.mpa.L, w.mpa.M, w.mpa.n_iter, w.mpa.block, w.mpa.halo, 0,
+                      w.mpa.omega_band)
+    m = L.MapStruct(w.dmmap)
+    ok = L.BatchDesc([1 << 14, 1 << 16, 4096], [1.0, 0.5, 2.0])
+    assert L.lib().mpa_batch_plan_validate(C.byref(p), C.byref(m.s), C.byref(ok.s)) == L.MPA_OK
+    small = L.BatchDesc([2048])                       # shorter than one block
+    assert L.lib().mpa_batch_plan_validate(C.byref(p), C.byref(m.s), C.byref(small.s)) == L.MPA_EINVAL
+    odd = L.BatchDesc([6000])
+    assert L.lib().mpa_batch_plan_validate(C.byref(p), C.byref(m.s), C.byref(odd.s)) == L.MPA_EINVAL
+    full = L.make_params(0, w.grid.dt, w.mpa.L, w.mpa.M, w.mpa.n_iter, 0, 0, 0, w.mpa.omega_band)
+    assert L.lib().mpa_batch_plan_validate(C.byref(full), C.byref(m.s), C.byref(ok.s)) == L.MPA_EINVAL
+    assert L.lib().mpa_batch_propagate(None, None, C.c_double(0), C.c_double(1), None) == L.MPA_EINVAL
+    assert L.lib().mpa_graph_launch(None, None) == L.MPA_EINVAL

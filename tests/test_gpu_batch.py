@@ -1,0 +1,101 @@
+"""Batched launches over instances of different lengths, and captured HIP
+graphs, through the C ABI.
+
+* every instance of a batch equals the same field run alone (bitwise: the
+  batch kernel does the same arithmetic per block, only the work list
+  differs), with a per-instance sigma;
+* an FP64 batch matches the oracle instance by instance;
+* a captured graph replayed several times, with eager work and
+  synchronisations between replays, matches the eager result every time.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.gpu_util import TOL_F64, rel_l2, say, to_dev, to_host
+from workloads import Grid, dm_map
+from workloads.wdm import _fast_wdm_field
+
+pytestmark = pytest.mark.gpu
+
+DT = 10.0 / 1024
+BAND = 145.0
+
+
+def _case(ns, seed=11, block=2048):
+    halo = block // 8
+    rate = O.halo_rate(BAND, 20.0, 0.1)
+    k = math.ceil(0.5 / (0.25 * halo * DT / rate))
+    L = 0.5 / k
+    fields = [_fast_wdm_field(Grid(n, DT), n // 1024, 8, "ook", np.random.default_rng(seed + i))
+              for i, n in enumerate(ns)]
+    return fields, block, halo, L
+
+
+def test_batch_equals_single_runs_bitwise():
+    import paper_1101_0086_amd as P
+    ns = [8192, 4096, 16384, 8192, 2048]
+    scales = [1.0, 0.5, 2.0, 1.3, 0.8]
+    fields, block, halo, L = _case(ns)
+    dmm = dm_map(beta3=0.1)
+    say("batch vs single", ns)
+    bp = P.MPABatchPlan(ns, DT, dmm, L, 2, 2, block, halo, P.MPA_C64, BAND, sigma_scale=scales)
+    assert bp.info()["work_items"] == sum(-(-n // (block - 2 * halo)) for n in ns)
+    x = to_dev(np.concatenate(fields), 0)
+    bp.propagate(x, 0.5 - 2 * L, 0.5 + 3 * L)
+    got = [to_host(v) for v in bp.split(x)]
+    bp.close()
+    for a, n, sc, g in zip(fields, ns, scales, got):
+        p = P.MPAPlan(n, DT, dmm.with_sigma(sc), L, 2, 2, block, halo, P.MPA_C64, BAND)
+        y = to_dev(a, 0)
+        p.propagate(y, 0.5 - 2 * L, 0.5 + 3 * L)
+        assert np.array_equal(to_host(y), g)
+        p.close()
+
+
+def test_batch_fp64_matches_oracle():
+    import paper_1101_0086_amd as P
+    ns = [4096, 8192, 2048]
+    scales = [1.0, 1.7, 0.6]
+    fields, block, halo, L = _case(ns, seed=21, block=1024)
+    dmm = dm_map(beta3=0.1)
+    say("batch fp64 vs oracle")
+    bp = P.MPABatchPlan(ns, DT, dmm, L, 2, 2, block, halo, P.MPA_C128, BAND, sigma_scale=scales)
+    x = to_dev(np.concatenate(fields), 1)
+    bp.propagate(x, 1.0 - 2 * L, 1.0 + L)
+    got = [to_host(v) for v in bp.split(x)]
+    bp.close()
+    for a, sc, g in zip(fields, scales, got):
+        ref = O.mpa_propagate(a, DT, dmm.with_sigma(sc), L, 2, 2, 1.0 - 2 * L, 1.0 + L, block, halo)
+        assert rel_l2(g, ref) < TOL_F64
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_graph_replays_match_eager(batched):
+    import torch
+    import paper_1101_0086_amd as P
+    ns = [8192, 4096]
+    fields, block, halo, L = _case(ns, seed=31)
+    dmm = dm_map(beta3=0.1)
+    z0, z1 = 0.5 - 2 * L, 0.5 + L          # odd number of long steps: ends with the copy kernel
+    if batched:
+        plan = P.MPABatchPlan(ns, DT, dmm, L, 2, 2, block, halo, P.MPA_C64, BAND)
+        a0 = np.concatenate(fields)
+    else:
+        plan = P.MPAPlan(ns[0], DT, dmm, L, 2, 2, block, halo, P.MPA_C64, BAND)
+        a0 = fields[0]
+    say("graph replay", batched)
+    g_buf = to_dev(a0, 0)
+    graph = plan.capture(g_buf, z0, z1)
+    e_buf = to_dev(a0, 0)
+    scratch = torch.zeros(1 << 16, device="cuda:0")
+    for rep in range(4):
+        graph.launch()
+        plan.propagate(e_buf, z0, z1)
+        scratch.add_(1.0)                    # eager work of the program between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(g_buf), to_host(e_buf)), rep
+    graph.close()
+    plan.close()

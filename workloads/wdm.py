@@ -136,33 +136,32 @@ def wdm_field(grid: Grid, n_bits: int, n_channels: int, modulation: str,
 def _fast_wdm_field(grid: Grid, n_bits: int, n_channels: int, modulation: str,
                     rng: np.random.Generator, sigma: float = 1.0) -> np.ndarray:
     """Same field as :func:`wdm_field` (same draws, same samples up to
-    rounding) built one bit slot at a time, for the large grids."""
+    rounding) for the large grids: each channel's envelope is the circular
+    convolution of its symbol comb (one symbol every slot) with the pulse of
+    slot 0, and its carrier (a whole number q of grid frequencies) is a
+    shift of that spectrum by q bins; one inverse FFT builds the field."""
     n, dt = grid.n, grid.dt
     window = n * dt
     t_bit = window / n_bits
     spb = n // n_bits                 # samples per bit slot (exact for all workloads)
     assert spb * n_bits == n
     dw = 2.0 * math.pi / window
-    # one slot's pulse shape, evaluated on the whole window around its centre
-    # (minimum image): the sample offset of slot b is b * spb.
     t = dt * np.arange(n)
     d0 = _periodic_offsets(t, 0.5 * t_bit, window)
-    g0 = np.exp(-d0 * d0 / (2.0 * TAU * TAU))
-    nz = np.nonzero(g0 > 1e-300)[0]
-    field = np.zeros(n, dtype=np.complex128)
+    g_hat = np.fft.fft(np.exp(-d0 * d0 / (2.0 * TAU * TAU)))
+    spec = np.zeros(n, dtype=np.complex128)
     for c in range(n_channels):
-        omega_c = (c - 0.5 * (n_channels - 1)) * CHANNEL_SPACING
-        omega_c = dw * round(omega_c / dw)
+        q = int(round((c - 0.5 * (n_channels - 1)) * CHANNEL_SPACING / dw))
         if modulation == "ook":
             sym = rng.integers(0, 2, size=n_bits).astype(np.complex128)
         else:
             k = rng.integers(0, 4, size=n_bits)
             sym = np.exp(1j * (math.pi / 4 + k * math.pi / 2))
-        env = np.zeros(n, dtype=np.complex128)
-        for b in np.nonzero(sym)[0]:
-            idx = (nz + b * spb) % n
-            env[idx] += sym[b] * g0[nz]
-        field += env * np.exp(-1j * omega_c * t)
+        # comb spectrum: the symbols' n_bits-point DFT repeated spb times
+        comb_hat = np.tile(np.fft.fft(sym), spb)
+        # exp(-i q dw t) shifts numpy's spectrum down by q bins
+        spec += np.roll(comb_hat * g_hat, -q)
+    field = np.fft.ifft(spec)
     p = 1.0 / (20.0 * sigma)
     cur = float(np.mean(np.abs(field) ** 2))
     if cur > 0:
