@@ -34,6 +34,31 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("paper_1101_0086_amd/csrc/mpa_kernels.hip", "paper_1101_0086_amd/csrc/long_step_body.inc",
+                  "paper_1101_0086_amd/csrc/block_fft.hpp", "paper_1101_0086_amd/csrc/cx.hpp")
+PMC_PROFILE = "profiles/mpa_block_kernel_wdm8_n262144_pmc.md"
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    PMC summary (FETCH_SIZE and WRITE_SIZE, calibrated on a copy of known
+    size), or None when the kernel sources changed since it was taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    try:
+        text = open(os.path.join(ROOT, PMC_PROFILE)).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("traffic_bytes_per_launch:", "kernel-source-sha256:")))
+    if fields.get("kernel-source-sha256", "").strip() != h.hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def flops_per_block(B: int, M: int, n_iter: int) -> float:
     """Algorithmic flops of one block in one long step: 5 B log2 B per
     transform for (3 + 2 n M) transforms (FP64 carry in and out, node 0, and
@@ -71,6 +96,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip accuracy and split-step comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-instance measurement")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="for rocprofv3 --pmc: a 64 MiB copy (counter calibration), then 20 long steps")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this implementation runs on one GPU; --gpus must be 1 "
@@ -94,6 +121,18 @@ def main():
     plan = P.MPAPlan(n, w.grid.dt, w.dmmap, s.L, s.M, s.n_iter, s.block, s.halo, prec, s.omega_band)
     info = plan.info()
     x = torch.from_numpy(a0).to(device="cuda:0", dtype=cdt)
+
+    if args.pmc_pass:
+        big = torch.zeros(1 << 23, dtype=torch.complex64, device="cuda:0")     # 64 MiB
+        torch.cuda.synchronize()
+        copy = big.clone()                  # one copy kernel: reads 64 MiB, writes 64 MiB
+        torch.cuda.synchronize()
+        plan.propagate(x, 0.0, 20 * s.L)
+        torch.cuda.synchronize()
+        del copy
+        print(json.dumps({"pmc_pass": True, "copy_bytes": 1 << 26, "launches": 20}), flush=True)
+        plan.close()
+        return
 
     z = 0.0
     for _ in range(args.warmup):
@@ -129,7 +168,8 @@ def main():
                    "step": f"one DM period = {launches_per_step} long steps",
                    "precision": "FP32 node work, FP64 phases and carry"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": measured_traffic() if w.name == "wdm8_n262144_f32" else None,
                      "kernel": "mpa_block_kernel", "launch_us": launch_s * 1e6,
                      "flops_per_launch": fl},
     }
@@ -138,6 +178,8 @@ def main():
         out.update(compare(w, a0, plan, x, torch, P))
     if not args.no_batch:
         out["batched"] = batched(torch, P)
+        out["autotune"] = autotune_table(w, a0, torch, P)
+        out["large"] = large(torch, P)
     plan.close()
     if not args.no_cpu:
         log("CPU oracle baseline ...")
@@ -184,6 +226,57 @@ def batched(torch, P, count=256, steps=200):
             "L": L, "M": M, "n_iter": nit, "block": 4096, "halo": 512, "long_steps": steps,
             "mode_steps_per_s_eager": ms / t_eager, "mode_steps_per_s_graph": ms / t_graph,
             "us_per_long_step_graph": t_graph / steps * 1e6}
+
+
+def autotune_table(w, a0, torch, P):
+    """Autotuner over (block, L, M) at the workload's dz (fixed accuracy)."""
+    from paper_1101_0086_amd.autotune import autotune
+    s = w.mpa
+    x = torch.from_numpy(a0).to(device="cuda:0", dtype=torch.complex64)
+    best, cands = autotune(x, w.grid.dt, w.dmmap, s.L / s.M, s.n_iter, s.omega_band)
+    rows = [{"block": c.block, "halo": c.halo, "L": c.L, "M": c.M,
+             "mode_steps_per_s": w.grid.n / (c.seconds_per_unit_z * (s.L / s.M))} for c in cands]
+    log("autotune: " + ", ".join(f"B={r['block']} L={r['L']:.2e} M={r['M']}: {r['mode_steps_per_s']:.3e}"
+                                 for r in rows))
+    return {"dz": s.L / s.M, "candidates": rows, "best_block": best.block}
+
+
+def large(torch, P, steps=200):
+    """The 32-channel QPSK workload (2^22 modes, 1366 blocks of 4096): MPA
+    (L = dz = 7.8125e-6, 2 sweeps) and split-step at the same dz, throughput
+    over `steps` long steps from the seeded field (no accuracy run: the
+    channel band reaches half the grid's Nyquist frequency)."""
+    from workloads import WORKLOADS
+    w = WORKLOADS["wdm32_n4194304_f32"]
+    s = w.mpa
+    a = w.field()
+    plan = P.MPAPlan(w.grid.n, w.grid.dt, w.dmmap, s.L, s.M, s.n_iter, s.block, s.halo, P.MPA_C64, s.omega_band)
+    x = torch.from_numpy(a).to(device="cuda:0", dtype=torch.complex64)
+    plan.propagate(x, 0.0, 4 * s.L)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.propagate(x, 0.0, steps * s.L)
+    torch.cuda.synchronize()
+    t_mpa = time.perf_counter() - t0
+    nb = plan.info()["n_blocks"]
+    plan.close()
+    dz = s.L / s.M
+    ss = P.SSPlan(w.grid.n, w.grid.dt, w.dmmap, dz, P.MPA_C64)
+    y = torch.from_numpy(a).to(device="cuda:0", dtype=torch.complex64)
+    ss.propagate(y, 0.0, 4 * dz)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ss.propagate(y, 0.0, steps * dz)
+    torch.cuda.synchronize()
+    t_ss = time.perf_counter() - t0
+    ss.close()
+    n = w.grid.n
+    r = {"workload": w.name, "n_modes": n, "n_blocks": nb, "dz": dz,
+         "mpa_mode_steps_per_s": n * s.M * steps / t_mpa, "mpa_us_per_launch": t_mpa / steps * 1e6,
+         "ss_f32_mode_steps_per_s": n * steps / t_ss}
+    log(f"large: MPA {r['mpa_mode_steps_per_s']:.3e} ({r['mpa_us_per_launch']:.0f} us/launch), "
+        f"split-step {r['ss_f32_mode_steps_per_s']:.3e} mode-steps/s")
+    return r
 
 
 def compare(w, a0, plan, x, torch, P):

@@ -1,0 +1,34 @@
+"""Candidate enumeration of the autotuner (host logic): every candidate
+satisfies the library's own validation, is a multiple of dz dividing the
+spans, and is the longest such long step for its block size."""
+import ctypes as C
+
+from workloads import WORKLOADS, dm_map
+
+
+def test_candidates_are_valid_and_maximal():
+    from paper_1101_0086_amd import _lib as L
+    from paper_1101_0086_amd.autotune import HALO_RULE, candidates
+    w = WORKLOADS["wdm8_n262144_f32"]
+    dz = 1.25e-4
+    cands = candidates(w.grid.n, w.grid.dt, w.dmmap, dz, w.mpa.omega_band)
+    # 512- and 1024-blocks cannot take even one dz inside the halo rule
+    assert [c.block for c in cands] == [2048, 4096]
+    rate = max(abs(b2) * w.mpa.omega_band + 0.5 * abs(b3) * w.mpa.omega_band ** 2
+               for b2, b3 in zip(w.dmmap.beta2, w.dmmap.beta3))
+    m = L.MapStruct(w.dmmap)
+    for c in cands:
+        assert abs(c.L - c.M * dz) < 1e-15 and c.halo == c.block // 8
+        p = L.make_params(w.grid.n, w.grid.dt, c.L, c.M, 2, c.block, c.halo, 0, w.mpa.omega_band)
+        assert L.lib().mpa_plan_validate(C.byref(p), C.byref(m.s)) == L.MPA_OK
+        # the next admissible multiple of dz breaks the halo rule
+        nxt = [k for k in range(c.M + 1, 4001) if 4000 % k == 0][0]
+        assert rate * nxt * dz > HALO_RULE * c.halo * w.grid.dt
+    # the 4096-block candidate is the benchmark's configuration
+    assert (cands[-1].L, cands[-1].M) == (w.mpa.L, w.mpa.M)
+
+
+def test_no_candidate_when_halo_rule_cannot_hold():
+    from paper_1101_0086_amd.autotune import candidates
+    dmm = dm_map(beta3=0.1)
+    assert candidates(1 << 16, 10 / 1024, dmm, 0.25, 145.0) == []

@@ -99,3 +99,20 @@ def test_graph_replays_match_eager(batched):
         assert np.array_equal(to_host(g_buf), to_host(e_buf)), rep
     graph.close()
     plan.close()
+
+
+def test_autotuner_picks_a_valid_plan():
+    import torch
+    import paper_1101_0086_amd as P
+    from paper_1101_0086_amd.autotune import autotune
+    n = 1 << 15
+    a = _fast_wdm_field(Grid(n, DT), 32, 8, "ook", np.random.default_rng(41))
+    x = to_dev(a, 0)
+    say("autotune")
+    dmm = dm_map(beta3=0.1)
+    best, cands = autotune(x, DT, dmm, 1.25e-4, 2, BAND, launches=8)
+    assert best in cands and all(c.seconds_per_unit_z > 0 for c in cands)
+    assert np.array_equal(to_host(x), to_host(to_dev(a, 0)))        # input left unchanged
+    plan = P.MPAPlan(n, DT, dmm, best.L, best.M, 2, best.block, best.halo, P.MPA_C64, BAND)
+    plan.propagate(x, 0.0, 2 * best.L)
+    plan.close()
