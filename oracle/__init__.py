@@ -26,18 +26,26 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
   kick; second order; unitarity; time reversibility.
 * ``mpa_propagate``: marching and resume identity; lumped gain restores the
   span loss exactly.
-* the FP32 compensated-sum behaviour of the GPU path has no oracle: FP32
-  results are judged against this FP64 oracle ("parity unpinned" for the
-  FP32 rounding pattern itself).
+* ``mpa_long_step_vjp`` / ``mpa_blocked_long_step_vjp`` /
+  ``mpa_propagate_vjp`` (module ``adjoint``): gradients of a real loss with
+  respect to the input field, sigma, beta2 and beta3 (per span), pinned by
+  central finite differences of the forward functions above, across a
+  span change, an amplifier and the dispersion-dependent roll-off.
+* the FP32 rounding pattern of the GPU path has no oracle: FP32 results
+  are judged against this FP64 oracle ("parity unpinned" for the FP32
+  rounding pattern itself).
 """
 from .nlse import (DMMapSpec, paper_fft, paper_ifft, omega_grid, beta_phase,
                    linear_step, mpa_long_step, mpa_blocked_long_step,
                    block_partition, block_taper, block_mask, halo_rate, mpa_step, mpa_propagate, ss_long_step,
                    ss_propagate, reference_propagate, if_trapezoid_long_step,
                    span_of_long_step, rel_l2)
+from .adjoint import (mpa_long_step_vjp, mpa_blocked_long_step_vjp, mpa_propagate_vjp,
+                      block_mask_grad)
 
 __all__ = ["DMMapSpec", "paper_fft", "paper_ifft", "omega_grid", "beta_phase",
            "linear_step", "mpa_long_step", "mpa_blocked_long_step",
            "block_partition", "block_taper", "block_mask", "halo_rate", "mpa_step", "mpa_propagate", "ss_long_step",
            "ss_propagate", "reference_propagate", "if_trapezoid_long_step",
-           "span_of_long_step", "rel_l2"]
+           "span_of_long_step", "rel_l2", "mpa_long_step_vjp", "mpa_blocked_long_step_vjp",
+           "mpa_propagate_vjp", "block_mask_grad"]
