@@ -142,6 +142,47 @@ int mpa_step(mpa_plan* plan, void* field, double z0, void* stream);
  * the state carried between long steps is the field alone.                  */
 int mpa_propagate(mpa_plan* plan, void* field, double z0, double z1, void* stream);
 
+/* ---- gradients (reverse pass) --------------------------------------------
+ *
+ * Gradients of a real loss l through mpa_propagate, obtained by running the
+ * adjoint of every operation of the long step (Eqs. 2 and 6, steps 1-7, the
+ * block taper, roll-off and core stitching, and the lumped gain) in reverse.
+ * A complex gradient is packed as G(A) = dl/dRe A + i dl/dIm A (the
+ * convention of torch's autograd for real losses), so dl = Re sum conj(G) dA.
+ *
+ * Checkpoints: the forward pass keeps the field at z0 and at the start of
+ * every map period inside (z0, z1); the reverse pass recomputes each period
+ * from its checkpoint, keeping the inputs of its long steps in device memory
+ * (all of them when they fit in MPA_ADJOINT_STORE_BYTES, else one inner
+ * checkpoint every ceil(sqrt(steps)) long steps, recomputed in turn).       */
+#define MPA_ADJOINT_STORE_BYTES ((int64_t)4 << 30)
+
+/* *count receives the number of checkpoints mpa_propagate_checkpointed
+ * writes for [z0, z1] (0 when z1 == z0).                                    */
+int mpa_checkpoint_count(const mpa_plan* plan, double z0, double z1, int64_t* count);
+
+/* mpa_propagate that also writes the checkpoints: `checkpoints` is a device
+ * buffer of count x N complex samples (plan precision, caller-owned);
+ * checkpoint k is the field at the start of the k-th map period segment of
+ * [z0, z1].  The field result is bitwise that of mpa_propagate.             */
+int mpa_propagate_checkpointed(mpa_plan* plan, void* field, double z0, double z1,
+                               void* checkpoints, void* stream);
+
+/* Reverse pass over [z0, z1].  `checkpoints`: as written by
+ * mpa_propagate_checkpointed for the same plan, z0 and z1 (read only).
+ * `grad`: device buffer of N complex samples (plan precision); on entry
+ * G(A(z1)), on exit G(A(z0)); carried between long steps in FP64.
+ * `param_grad`: device buffer of 3 x n_seg doubles, overwritten with
+ * dl/dsigma, dl/dbeta2 and dl/dbeta3 of every span of the map (in that order,
+ * n_seg entries each; the derivative of the block roll-off with respect to
+ * beta2 and beta3 is included).  `store_steps`: the most long-step inputs
+ * kept at once (0: the automatic rule above).  The first call allocates a
+ * workspace of n_blocks x (3 n_iter M + 2) x B complex samples plus the
+ * kept step inputs, held by the plan until it is destroyed.  Deterministic:
+ * per-block partial sums are added in a fixed order.                        */
+int mpa_adjoint(mpa_plan* plan, const void* checkpoints, void* grad, double z0, double z1,
+                double* param_grad, int64_t store_steps, void* stream);
+
 /* ---- batches of independent fields (one launch per long step for all) ----
  *
  * Instances share dt, L, M, n_iter, block, halo, precision and the map (so

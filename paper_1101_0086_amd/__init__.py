@@ -41,6 +41,8 @@ class MPAPlan:
                  omega_band=0.0, device=0):
         self.n, self.precision, self.device = int(n), int(precision), int(device)
         self.L = float(L)
+        self.n_seg = len(dmmap.seg_len)
+        self.coefficients = tuple(tuple(float(v) for v in getattr(dmmap, f)) for f in ("sigma", "beta2", "beta3"))
         p = _lib.make_params(n, dt, L, M, n_iter, block, halo, precision, omega_band)
         m = _lib.MapStruct(dmmap)
         h = C.c_void_p()
@@ -63,6 +65,37 @@ class MPAPlan:
         _lib.check(_lib.lib().mpa_propagate(self._h, C.c_void_p(field.data_ptr()), float(z0),
                                             float(z1), _stream_handle(torch, field.device)))
         return field
+
+    def checkpoint_count(self, z0, z1):
+        c = C.c_int64()
+        _lib.check(_lib.lib().mpa_checkpoint_count(self._h, float(z0), float(z1), C.byref(c)))
+        return c.value
+
+    def propagate_checkpointed(self, field, z0, z1):
+        """mpa_propagate_checkpointed: marches `field` in place and returns the
+        checkpoints (one field per map period segment of [z0, z1])."""
+        torch = _check_field(field, self.precision, self.n)
+        k = self.checkpoint_count(z0, z1)
+        ckpt = torch.empty((k, self.n), dtype=field.dtype, device=field.device)
+        _lib.check(_lib.lib().mpa_propagate_checkpointed(
+            self._h, C.c_void_p(field.data_ptr()), float(z0), float(z1),
+            C.c_void_p(ckpt.data_ptr() if k else 0), _stream_handle(torch, field.device)))
+        return ckpt
+
+    def adjoint(self, checkpoints, grad, z0, z1, store_steps=0):
+        """mpa_adjoint: turns G(A(z1)) in `grad` into G(A(z0)) in place and
+        returns dl/d(sigma, beta2, beta3) per span as a (3, n_seg) FP64 tensor
+        on the field's device."""
+        torch = _check_field(grad, self.precision, self.n)
+        k = self.checkpoint_count(z0, z1)
+        if checkpoints.shape != (k, self.n) or checkpoints.dtype != grad.dtype or not checkpoints.is_contiguous():
+            raise ValueError(f"checkpoints must be a contiguous ({k}, {self.n}) {grad.dtype} tensor")
+        pg = torch.empty((3, self.n_seg), dtype=torch.float64, device=grad.device)
+        _lib.check(_lib.lib().mpa_adjoint(
+            self._h, C.c_void_p(checkpoints.data_ptr() if k else 0), C.c_void_p(grad.data_ptr()),
+            float(z0), float(z1), C.c_void_p(pg.data_ptr()), int(store_steps),
+            _stream_handle(torch, grad.device)))
+        return pg
 
     def close(self):
         if getattr(self, "_h", None):

@@ -27,7 +27,8 @@ EXPORTED = ("mpa_plan_create", "mpa_plan_destroy", "mpa_plan_get_info", "mpa_pla
             "mpa_step", "mpa_propagate", "mpa_batch_plan_validate", "mpa_batch_plan_create",
             "mpa_batch_plan_destroy", "mpa_batch_get_info", "mpa_batch_propagate",
             "mpa_graph_capture", "mpa_batch_graph_capture", "mpa_graph_launch", "mpa_graph_destroy",
-            "ss_plan_create", "ss_plan_destroy", "ss_propagate", "mpa_status_string", "mpa_last_error")
+            "ss_plan_create", "ss_plan_destroy", "ss_propagate", "mpa_status_string", "mpa_last_error",
+            "mpa_checkpoint_count", "mpa_propagate_checkpointed", "mpa_adjoint")
 
 
 class mpa_map(C.Structure):
@@ -94,6 +95,9 @@ def lib() -> C.CDLL:
     h.ss_plan_create.argtypes = [C.POINTER(mpa_map), C.c_int64, dp, dp, C.c_int32, C.c_int, C.POINTER(vp)]
     h.ss_plan_destroy.argtypes = [vp]
     h.ss_propagate.argtypes = [vp, vp, dp, dp, vp]
+    h.mpa_checkpoint_count.argtypes = [vp, dp, dp, C.POINTER(C.c_int64)]
+    h.mpa_propagate_checkpointed.argtypes = [vp, vp, dp, dp, vp, vp]
+    h.mpa_adjoint.argtypes = [vp, vp, vp, dp, dp, vp, C.c_int64, vp]
     h.mpa_status_string.argtypes = [C.c_int]
     h.mpa_status_string.restype = C.c_char_p
     h.mpa_last_error.argtypes = [C.c_char_p, C.c_int]

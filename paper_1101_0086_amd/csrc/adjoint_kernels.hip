@@ -1,0 +1,414 @@
+// Reverse pass of the fused MPA long step (gradients of a real loss).
+//
+// Gradients of a real loss l with respect to a complex array z are carried as
+// G(z) = dl/dRe z + i dl/dIm z, so that dl = Re sum conj(G(z)) dz.  The rules
+// follow from the forward operations of one block (Eqs. 2 and 6, steps 1-7):
+//   y = c z, c fixed             G(z) = conj(c) G(y)
+//   unnormalised transforms      the adjoint of F (kernel e^{+i omega t}) is
+//                                the unnormalised inverse, and vice versa
+//   n = |A|^2 A                  G(A) = 2 |A|^2 G(n) + A^2 conj(G(n))
+//   cumulative trapezoid (Eq. 6) G(U_j) = G(psi_j) / 2 + sum_{l > j} G(psi_l),
+//                                G(U_0) = sum_{l >= 1} G(psi_l) / 2,
+//                                G(psi_0) += sum_{l >= 1} G(psi_l)
+// and the parameters enter as U proportional to sigma and phases
+// e^{+-i beta_j} with d beta_j / d beta2 = omega^2 z_j / 2,
+// d beta_j / d beta3 = omega^3 z_j / 6 (z_j = j dz from the long step start).
+//
+// One workgroup per block, as in the forward kernel.  The kernel first
+// repeats the block's forward long step with the same operations and keeps,
+// for every sweep s and node l >= 1, the node's time field A, its spectrum
+// y = psi e^{i beta_l} and the sigma-free increment U / sigma in a per-block
+// store in device memory (written and read back by the same workgroup).  The
+// reverse pass then visits the nodes from M down to 1 and, at each node, the
+// sweeps from last to first: the gradient of psi^(s+1)_l is then complete
+// when node (s, l) is processed, and the reverse trapezoid sums are one
+// running sum per sweep, kept in registers like the forward sums.
+#include "block_fft.hpp"
+#include "launch.hpp"
+
+namespace mpa {
+
+namespace {
+
+constexpr int PTS = 8;
+
+template <typename T>
+__device__ __forceinline__ cx<double> widen(cx<T> a) { return {double(a.re), double(a.im)}; }
+
+template <typename T>
+__device__ __forceinline__ cx<T> narrow(cx<double> a) { return {T(a.re), T(a.im)}; }
+
+// Re(conj(g) x) and Re(conj(g) i x)
+__device__ __forceinline__ double re_dot(cx<double> g, cx<double> x) { return g.re * x.re + g.im * x.im; }
+__device__ __forceinline__ double re_dot_i(cx<double> g, cx<double> x) { return g.im * x.re - g.re * x.im; }
+
+// a^2 conj(g)
+template <typename T>
+__device__ __forceinline__ cx<T> sq_conj(cx<T> a, cx<T> g) {
+    const cx<T> a2 = {a.re * a.re - a.im * a.im, T(2) * a.re * a.im};
+    return cmulc(a2, g);
+}
+
+__device__ __forceinline__ long long wrap(long long g, long long n) {
+    if (g < 0) g += n;
+    if (g >= n) g -= n;
+    return g;
+}
+
+}  // namespace
+
+template <typename T, int B, int NIT>
+__global__ void __launch_bounds__(B / PTS)
+mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restrict__ g_out,
+                         cx<double>* __restrict__ g_blk, double* __restrict__ partial,
+                         cx<T>* __restrict__ node_store, cx<double>* __restrict__ last_store, long long n,
+                         int core, int halo, const cx<T>* __restrict__ phase,
+                         const cx<double>* __restrict__ phase_last, const T* __restrict__ node_scale,
+                         const cx<T>* __restrict__ tw, const cx<double>* __restrict__ tw64,
+                         const double* __restrict__ taper, const cx<double>* __restrict__ mask_grad, int M,
+                         T sigma, double out_scale, double w1, double dz) {
+    constexpr int R = PTS;
+    constexpr int NT = B / R;
+    __shared__ cx<double> lds64[lds_elems<B>()];
+    cx<T>* ldsT = reinterpret_cast<cx<T>*>(lds64);
+    const int tid = threadIdx.x;
+    const long long c0 = (long long)blockIdx.x * core;
+    const long long w0 = c0 - halo;
+    cx<T>* __restrict__ store = node_store + (size_t)blockIdx.x * NIT * M * 3 * B;
+    cx<double>* __restrict__ last = last_store + (size_t)blockIdx.x * B;
+
+    // ---- forward recompute of the block's long step, keeping node values ----
+    {
+        cx<double> psi0[R], S[NIT][R];
+        cx<T> cur[R], ph[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int t = tid + NT * m;
+            const cx<double> a = scale(widen(in[wrap(w0 + t, n)]), taper[t]);
+            psi0[m] = a;
+            cur[m] = narrow<T>(scale(a, norm2(a)));
+        }
+        block_fft<double, B, R, +1>(psi0, lds64, tw64, tid);
+        block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
+        const T d0 = sigma * node_scale[1];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const cx<double> u0 = widen(rot<+1>(scale(cur[m], d0 * T(0.5))));
+#pragma unroll
+            for (int s = 0; s < NIT; ++s) S[s][m] = u0;
+        }
+        for (int l = 1; l <= M; ++l) {
+            const T cl = node_scale[2 * l];
+            const T el = node_scale[2 * l + 1];
+            const T dl = sigma * el;
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                ph[m] = phase[(size_t)l * B + tid + NT * m];
+                cur[m] = narrow<T>(psi0[m]);
+            }
+            const bool last_node = (l == M);
+#pragma unroll
+            for (int s = 0; s < NIT; ++s) {
+                cx<T>* __restrict__ slot = store + (size_t)((s * M + l - 1) * 3) * B;
+#pragma unroll
+                for (int m = 0; m < R; ++m) {
+                    cur[m] = cmul(cur[m], ph[m]);
+                    slot[B + tid + NT * m] = cur[m];                       // y
+                }
+                block_fft<T, B, R, -1>(cur, ldsT, tw, tid);
+#pragma unroll
+                for (int m = 0; m < R; ++m) {
+                    const cx<T> a = scale(cur[m], cl);
+                    slot[tid + NT * m] = a;                                // A
+                    cur[m] = scale(a, norm2(a));
+                }
+                block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
+                const bool need_next = (s < NIT - 1) || last_node;
+                const bool final_sum = last_node && (s == NIT - 1);
+#pragma unroll
+                for (int m = 0; m < R; ++m) {
+                    const cx<T> v = cmulc(cur[m], ph[m]);
+                    slot[2 * B + tid + NT * m] = rot<+1>(scale(v, el));    // U / sigma
+                    const cx<double> u = widen(rot<+1>(scale(v, dl)));
+                    if (need_next) {
+                        const cx<double> nxt = psi0[m] + (S[s][m] + scale(u, 0.5));
+                        if (final_sum) psi0[m] = nxt;
+                        else cur[m] = narrow<T>(nxt);
+                    }
+                    if (!last_node) S[s][m] = S[s][m] + u;
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < R; ++m) last[tid + NT * m] = psi0[m];         // psi^(n_iter)_M
+    }
+
+    // ---- reverse pass ----
+    double d_sigma = 0.0, d_beta2 = 0.0, d_beta3 = 0.0;
+    cx<double> gp0[R], Rs[NIT][R], gn[R];
+    cx<T> cur[R], ph[R];
+    const double zM = M * dz;
+    {
+        // step 7: out = out_scale F^-1[psi_M e^{i beta_M} mask]; only the core is output
+        const long long rest = n - c0;
+        const int clen = rest < core ? (int)rest : core;
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int t = tid + NT * m;
+            gn[m] = (t >= halo && t < halo + clen) ? g_out[c0 + (t - halo)] : cx<double>{0.0, 0.0};
+        }
+        block_fft<double, B, R, +1>(gn, lds64, tw64, tid);
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int k = tid + NT * m;
+            const double om = w1 * double(k < B / 2 ? k : k - B);
+            const cx<double> gx = scale(gn[m], out_scale);
+            const cx<double> psiM = last[k];
+            const cx<double> pl = phase_last[k];
+            const double r = re_dot_i(gx, cmul(psiM, pl));
+            d_beta2 += r * (0.5 * om * om * zM);
+            d_beta3 += r * (om * om * om * zM / 6.0);
+            if (mask_grad) {
+                d_beta2 += re_dot(gx, cmul(psiM, mask_grad[k]));
+                d_beta3 += re_dot(gx, cmul(psiM, mask_grad[B + k]));
+            }
+            gn[m] = cmulc(gx, pl);                                          // G(psi^(n_iter)_M)
+            gp0[m] = {0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < NIT; ++s) Rs[s][m] = {0.0, 0.0};
+        }
+    }
+    for (int l = M; l >= 1; --l) {
+        const T cl = node_scale[2 * l];
+        const T dl = sigma * node_scale[2 * l + 1];
+        const double zl = l * dz;
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            ph[m] = phase[(size_t)l * B + tid + NT * m];
+            if (l < M) gn[m] = {0.0, 0.0};
+        }
+#pragma unroll
+        for (int s = NIT - 1; s >= 0; --s) {
+            const cx<T>* __restrict__ slot = store + (size_t)((s * M + l - 1) * 3) * B;
+            // trapezoid adjoint, then U = i dl e^{-i beta_l} F[n]
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const int k = tid + NT * m;
+                const double om = w1 * double(k < B / 2 ? k : k - B);
+                const cx<double> gu = scale(gn[m], 0.5) + Rs[s][m];
+                Rs[s][m] = Rs[s][m] + gn[m];
+                const cx<double> up = widen(slot[2 * B + k]);
+                d_sigma += re_dot(gu, up);
+                const double r = -re_dot_i(gu, up) * double(sigma);
+                d_beta2 += r * (0.5 * om * om * zl);
+                d_beta3 += r * (om * om * om * zl / 6.0);
+                cur[m] = rot<-1>(scale(cmul(narrow<T>(gu), ph[m]), dl));     // G(F[n])
+            }
+            block_fft<T, B, R, -1>(cur, ldsT, tw, tid);                      // G(n)
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const cx<T> a = slot[tid + NT * m];
+                const cx<T> g = cur[m];
+                cur[m] = scale(g, T(2) * norm2(a)) + sq_conj(a, g);           // G(A)
+            }
+            block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const int k = tid + NT * m;
+                const double om = w1 * double(k < B / 2 ? k : k - B);
+                const cx<T> gy = scale(cur[m], cl);                           // G(y)
+                const double r = re_dot_i(widen(gy), widen(slot[B + k]));
+                d_beta2 += r * (0.5 * om * om * zl);
+                d_beta3 += r * (om * om * om * zl / 6.0);
+                const cx<double> gps = widen(cmulc(gy, ph[m]));               // G(psi^(s)_l)
+                if (s > 0) gn[m] = gps;
+                else gp0[m] = gp0[m] + gps;
+            }
+        }
+    }
+
+    // node 0 (U_0 = i sigma dz F[|A_0|^2 A_0], shared by every sweep) and psi_0 = F[A_0]
+    const T e0 = node_scale[1];
+    const T d0 = sigma * e0;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        cx<double> tot = {0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < NIT; ++s) tot = tot + Rs[s][m];
+        gp0[m] = gp0[m] + tot;
+        gn[m] = scale(tot, 0.5);                                              // G(U_0)
+        const int t = tid + NT * m;
+        const cx<double> a = scale(widen(in[wrap(w0 + t, n)]), taper[t]);
+        cur[m] = narrow<T>(scale(a, norm2(a)));
+    }
+    block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        d_sigma += re_dot(gn[m], widen(rot<+1>(scale(cur[m], e0))));
+        cur[m] = rot<-1>(scale(narrow<T>(gn[m]), d0));
+    }
+    block_fft<T, B, R, -1>(cur, ldsT, tw, tid);                              // G(n_0)
+    block_fft<double, B, R, -1>(gp0, lds64, tw64, tid);                      // G(A_0) via psi_0
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int t = tid + NT * m;
+        const cx<double> a = scale(widen(in[wrap(w0 + t, n)]), taper[t]);
+        const cx<double> g = widen(cur[m]);
+        const cx<double> ga = gp0[m] + scale(g, 2.0 * norm2(a)) + sq_conj(a, g);
+        g_blk[(size_t)blockIdx.x * B + t] = scale(ga, taper[t]);
+    }
+
+    // workgroup sums of the parameter derivatives (fixed order)
+    double* red = reinterpret_cast<double*>(lds64);
+    __syncthreads();
+    red[tid] = d_sigma;
+    red[NT + tid] = d_beta2;
+    red[2 * NT + tid] = d_beta3;
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        __syncthreads();
+        if (tid < h) {
+            red[tid] += red[tid + h];
+            red[NT + tid] += red[NT + tid + h];
+            red[2 * NT + tid] += red[2 * NT + tid + h];
+        }
+    }
+    __syncthreads();
+    if (tid < 3) partial[(size_t)blockIdx.x * 3 + tid] = red[tid * NT];
+}
+
+// g_in[i] = sum over the windows b containing sample i of g_blk[b][i - (b C - H) mod N];
+// workgroup 0 also adds the per-block parameter derivatives (in block order)
+// to param_grad[q * n_seg + span], q = 0 (sigma), 1 (beta2), 2 (beta3).
+__global__ void adjoint_gather_kernel(const cx<double>* __restrict__ g_blk, cx<double>* __restrict__ g_in,
+                                      long long n, int B, int core, int halo, int n_blocks,
+                                      const double* __restrict__ partial, double* __restrict__ param_grad,
+                                      int n_seg, int span) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        cx<double> acc = {0.0, 0.0};
+        for (int k = -1; k <= 1; ++k) {
+            const long long ip = i + k * n;           // the sample's position relative to the windows
+            // windows b with b C - H <= ip < b C - H + B
+            long long hi = ip + halo;
+            long long lo = ip + halo - B;
+            hi = hi >= 0 ? hi / core : -((-hi + core - 1) / core);
+            lo = (lo >= 0 ? lo / core : -((-lo + core - 1) / core)) + 1;
+            if (lo < 0) lo = 0;
+            if (hi > n_blocks - 1) hi = n_blocks - 1;
+            for (long long b = lo; b <= hi; ++b) {
+                const long long t = ip - (b * core - halo);
+                acc = acc + g_blk[b * B + t];
+            }
+        }
+        g_in[i] = acc;
+    }
+    if (blockIdx.x == 0) {
+        __shared__ double red[3][256];
+        const int tid = threadIdx.x;
+        double s[3] = {0.0, 0.0, 0.0};
+        for (int b = tid; b < n_blocks; b += blockDim.x)
+            for (int q = 0; q < 3; ++q) s[q] += partial[(size_t)b * 3 + q];
+        for (int q = 0; q < 3; ++q) red[q][tid] = s[q];
+        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+            __syncthreads();
+            if (tid < h)
+                for (int q = 0; q < 3; ++q) red[q][tid] += red[q][tid + h];
+        }
+        __syncthreads();
+        if (tid < 3) param_grad[tid * n_seg + span] += red[tid][0];
+    }
+}
+
+template <typename S, typename D>
+__global__ void convert_kernel(const cx<S>* __restrict__ src, cx<D>* __restrict__ dst, long long count) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        dst[i] = cx<D>{D(src[i].re), D(src[i].im)};
+}
+
+__global__ void zero_kernel(double* __restrict__ p, long long count) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0.0;
+}
+
+template <typename T, int B, int NIT>
+static hipError_t adjoint_typed(const AdjointStepArgs& a) {
+    hipLaunchKernelGGL((mpa_adjoint_block_kernel<T, B, NIT>), dim3(a.n_blocks), dim3(B / PTS), 0, a.stream,
+                       static_cast<const cx<T>*>(a.in), static_cast<const cx<double>*>(a.g_out),
+                       static_cast<cx<double>*>(a.g_blk), a.partial, static_cast<cx<T>*>(a.node_store),
+                       static_cast<cx<double>*>(a.last_store), (long long)a.n, a.core, a.halo,
+                       static_cast<const cx<T>*>(a.phase), static_cast<const cx<double>*>(a.phase_last),
+                       static_cast<const T*>(a.node_scale), static_cast<const cx<T>*>(a.twiddle),
+                       static_cast<const cx<double>*>(a.twiddle64), static_cast<const double*>(a.taper),
+                       static_cast<const cx<double>*>(a.mask_grad), a.M, T(a.sigma), a.out_scale, a.w1, a.dz);
+    return hipGetLastError();
+}
+
+template <typename T, int B>
+static hipError_t adjoint_nit(const AdjointStepArgs& a) {
+    switch (a.n_iter) {
+        case 1: return adjoint_typed<T, B, 1>(a);
+        case 2: return adjoint_typed<T, B, 2>(a);
+        case 3: return adjoint_typed<T, B, 3>(a);
+        case 4: return adjoint_typed<T, B, 4>(a);
+        case 5: return adjoint_typed<T, B, 5>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+static hipError_t adjoint_b(const AdjointStepArgs& a) {
+    switch (a.block) {
+        case 512: return adjoint_nit<T, 512>(a);
+        case 1024: return adjoint_nit<T, 1024>(a);
+        case 2048: return adjoint_nit<T, 2048>(a);
+        case 4096: return adjoint_nit<T, 4096>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_adjoint_step(const AdjointStepArgs& a) {
+    if (!block_step_supported(a.precision, a.block, a.n_iter)) return hipErrorInvalidValue;
+    return a.precision == 0 ? adjoint_b<float>(a) : adjoint_b<double>(a);
+}
+
+hipError_t launch_adjoint_gather(const void* g_blk, void* g_in, int64_t n, int block, int core, int halo,
+                                 int n_blocks, const double* partial, double* param_grad, int n_seg, int span,
+                                 hipStream_t stream) {
+    const int tpb = 256;
+    const long long want = (n + tpb - 1) / tpb;
+    const unsigned grid = (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+    hipLaunchKernelGGL(adjoint_gather_kernel, dim3(grid), dim3(tpb), 0, stream,
+                       static_cast<const cx<double>*>(g_blk), static_cast<cx<double>*>(g_in), (long long)n, block,
+                       core, halo, n_blocks, partial, param_grad, n_seg, span);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(const void* src, int src_precision, void* dst, int dst_precision, int64_t count,
+                          hipStream_t stream) {
+    const int tpb = 256;
+    const long long want = (count + tpb - 1) / tpb;
+    const unsigned grid = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+    if (src_precision == 0 && dst_precision == 1)
+        hipLaunchKernelGGL((convert_kernel<float, double>), dim3(grid), dim3(tpb), 0, stream,
+                           static_cast<const cx<float>*>(src), static_cast<cx<double>*>(dst), (long long)count);
+    else if (src_precision == 1 && dst_precision == 0)
+        hipLaunchKernelGGL((convert_kernel<double, float>), dim3(grid), dim3(tpb), 0, stream,
+                           static_cast<const cx<double>*>(src), static_cast<cx<float>*>(dst), (long long)count);
+    else if (src_precision == 1 && dst_precision == 1)
+        hipLaunchKernelGGL((convert_kernel<double, double>), dim3(grid), dim3(tpb), 0, stream,
+                           static_cast<const cx<double>*>(src), static_cast<cx<double>*>(dst), (long long)count);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double* p, int64_t count, hipStream_t stream) {
+    const int tpb = 256;
+    const long long want = (count + tpb - 1) / tpb;
+    const unsigned grid = (unsigned)(want < 1024 ? (want > 0 ? want : 1) : 1024);
+    hipLaunchKernelGGL(zero_kernel, dim3(grid), dim3(tpb), 0, stream, p, (long long)count);
+    return hipGetLastError();
+}
+
+}  // namespace mpa

@@ -43,6 +43,42 @@ int threads_per_block(int precision, int block);
 hipError_t launch_block_step(const BlockStepArgs& a);
 hipError_t launch_copy_field(const void* src, void* dst, int64_t count, int precision, hipStream_t stream);
 
+// Reverse pass of one long step over every block of one field.
+struct AdjointStepArgs {
+    const void* in;          // field at z0 of the long step (plan precision)
+    const void* g_out;       // FP64 complex N: gradient with respect to the field at z0 + L
+    void* g_blk;             // FP64 complex n_blocks x B: each window's input gradient (tapered)
+    double* partial;         // n_blocks x 3: d/dsigma, d/dbeta2, d/dbeta3 of each block
+    void* node_store;        // n_blocks x n_iter x M x 3 x B complex (plan precision)
+    void* last_store;        // n_blocks x B FP64 complex
+    int64_t n;
+    int32_t block, halo, core, n_blocks;
+    const void* phase;
+    const void* phase_last;
+    const void* node_scale;
+    const void* twiddle;
+    const void* twiddle64;
+    const void* taper;
+    const void* mask_grad;   // 2 x B FP64 complex: e^{i beta_M} d(roll-off)/d beta2, .../d beta3; or nullptr
+    int32_t M, n_iter;
+    double sigma, out_scale;
+    double w1;               // 2 pi / (B dt): block frequency spacing
+    double dz;               // L / M
+    int32_t precision;
+    hipStream_t stream;
+};
+
+hipError_t launch_adjoint_step(const AdjointStepArgs& a);
+// g_in[i] = sum of g_blk over the windows containing sample i; adds the
+// blocks' parameter derivatives to param_grad[q * n_seg + span].
+hipError_t launch_adjoint_gather(const void* g_blk, void* g_in, int64_t n, int block, int core, int halo,
+                                 int n_blocks, const double* partial, double* param_grad, int n_seg, int span,
+                                 hipStream_t stream);
+// complex conversion between precisions (0: FP32, 1: FP64); FP32 -> FP32 is not offered
+hipError_t launch_convert(const void* src, int src_precision, void* dst, int dst_precision, int64_t count,
+                          hipStream_t stream);
+hipError_t launch_zero(double* p, int64_t count, hipStream_t stream);
+
 // FP64 phase table: rows r = 0..rows-1, column k = 0..B-1,
 // turns = c2[r] k'^2 + c3[r] k'^3 (k' the signed harmonic index),
 // table[r][k] = (cos 2 pi frac(turns), sin 2 pi frac(turns)) stored in the

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <functional>
 #include <string>
 #include <vector>
@@ -136,13 +137,27 @@ struct mpa_plan {
     void* taper = nullptr;              // B FP64 reals
     void* work = nullptr;               // N complex
     int64_t table_bytes = 0;
+    // reverse-pass workspace, allocated by the first mpa_adjoint call
+    void* adj_node = nullptr;           // n_blocks x n_iter x M x 3 x B complex
+    void* adj_last = nullptr;           // n_blocks x B FP64 complex
+    void* adj_gblk = nullptr;           // n_blocks x B FP64 complex
+    void* adj_partial = nullptr;        // n_blocks x 3 doubles
+    void* adj_ga = nullptr;             // N FP64 complex (gradient carried between long steps)
+    void* adj_gb = nullptr;             // N FP64 complex
+    void* adj_mask = nullptr;           // n_seg x 2 x B FP64 complex (blocked plans)
+    void* adj_inputs = nullptr;         // adj_inputs_cap fields: inputs of the long steps being reversed
+    int64_t adj_inputs_cap = 0;
+    void* adj_subs = nullptr;           // adj_subs_cap fields: inner checkpoints of a long map period
+    int64_t adj_subs_cap = 0;
 };
 
 static void plan_free(mpa_plan* p) {
     if (!p) return;
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
-    for (void* q : {p->phase, p->phase_last, p->node_scale, p->twiddle, p->twiddle64, p->taper, p->work})
+    for (void* q : {p->phase, p->phase_last, p->node_scale, p->twiddle, p->twiddle64, p->taper, p->work,
+                    p->adj_node, p->adj_last, p->adj_gblk, p->adj_partial, p->adj_ga, p->adj_gb, p->adj_mask,
+                    p->adj_inputs, p->adj_subs})
         if (q) (void)hipFree(q);
     delete p;
 }
@@ -410,6 +425,264 @@ int mpa_propagate(mpa_plan* p, void* field, double z0, double z1, void* stream) 
     if (!p || !field) return fail(MPA_EINVAL, "NULL plan or field");
     if (hipSetDevice(p->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
     return march(p, field, p->work, p->prm.n, z0, z1, (hipStream_t)stream, nullptr);
+}
+
+// ---- reverse pass (gradients) ----------------------------------------------------
+
+// Segments of [m0, m1) that start at m0 or at a period start of the map.
+static std::vector<int64_t> segment_starts(const mpa_plan* p, int64_t m0, int64_t m1) {
+    std::vector<int64_t> out;
+    if (m1 <= m0) return out;
+    out.push_back(m0);
+    const int64_t P = p->sched.period_steps;
+    int64_t q = m0 / P;
+    if (q * P > m0) --q;                           // floor
+    for (int64_t b = (q + 1) * P; b < m1; b += P) out.push_back(b);
+    return out;
+}
+
+static int grid_range(const mpa_plan* p, double z0, double z1, int64_t* m0, int64_t* m1) {
+    *m0 = grid_index(z0, p->prm.L);
+    *m1 = grid_index(z1, p->prm.L);
+    if (*m0 == INT64_MIN || *m1 == INT64_MIN)
+        return fail(MPA_EALIGN, "z0 = %g or z1 = %g is not a multiple of L = %g", z0, z1, p->prm.L);
+    if (*m1 < *m0) return fail(MPA_EINVAL, "z1 < z0");
+    return MPA_OK;
+}
+
+// Grow-only device buffer of `count` fields.
+static int reserve_fields(mpa_plan* p, void** buf, int64_t* cap, int64_t count) {
+    if (count <= *cap) return MPA_OK;
+    if (*buf) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(*buf);
+        *buf = nullptr;
+        *cap = 0;
+    }
+    if (hipMalloc(buf, (size_t)count * p->prm.n * p->elem) != hipSuccess) {
+        *buf = nullptr;
+        return fail(MPA_ENOMEM, "adjoint: allocation of %lld fields failed", (long long)count);
+    }
+    *cap = count;
+    return MPA_OK;
+}
+
+// Fixed part of the reverse-pass workspace and the roll-off derivative tables.
+static int adjoint_setup(mpa_plan* p) {
+    if (p->adj_node) return MPA_OK;
+    const int B = p->block, M = p->prm.M, nit = p->prm.n_iter, S = (int)p->beta2.size();
+    const size_t nb = (size_t)p->n_blocks;
+    const bool ok = hipMalloc(&p->adj_node, nb * nit * M * 3 * B * p->elem) == hipSuccess &&
+                    hipMalloc(&p->adj_last, nb * B * 16) == hipSuccess &&
+                    hipMalloc(&p->adj_gblk, nb * B * 16) == hipSuccess &&
+                    hipMalloc(&p->adj_partial, nb * 3 * sizeof(double)) == hipSuccess &&
+                    hipMalloc(&p->adj_ga, (size_t)p->prm.n * 16) == hipSuccess &&
+                    hipMalloc(&p->adj_gb, (size_t)p->prm.n * 16) == hipSuccess;
+    if (!ok) {
+        for (void** q : {&p->adj_node, &p->adj_last, &p->adj_gblk, &p->adj_partial, &p->adj_ga, &p->adj_gb})
+            if (*q) {
+                (void)hipFree(*q);
+                *q = nullptr;
+            }
+        return fail(MPA_ENOMEM, "adjoint: workspace allocation failed");
+    }
+    if (p->halo > 0) {
+        // e^{i beta_M(omega)} times the derivatives of the block roll-off with respect to
+        // beta2 and beta3: the roll-off is d((g - 0.35) / 0.15) d((q - 0.8) / 0.1) with
+        // g = |u| L / (halo dt), u = beta2 omega + beta3 omega^2 / 2, q = |omega| dt / pi,
+        // d(x) = (1 + cos pi x) / 2 on (0, 1), so d' = -(pi / 2) sin(pi x) there.
+        const double pi = 3.14159265358979323846;
+        const double bdt = B * p->prm.dt;
+        const double w1 = 2.0 * pi / bdt;
+        const double hd = p->prm.L / (p->halo * p->prm.dt);
+        std::vector<double> t((size_t)S * 4 * B);
+        auto drop = [&](double x) { return x <= 0 ? 1.0 : (x >= 1 ? 0.0 : 0.5 * (1.0 + std::cos(pi * x))); };
+        auto slope = [&](double x) { return (x > 0 && x < 1) ? -0.5 * pi * std::sin(pi * x) : 0.0; };
+        for (int s = 0; s < S; ++s) {
+            const double c2 = pi * p->beta2[s] * p->prm.L / (bdt * bdt);
+            const double c3 = (2.0 * pi * pi / 3.0) * p->beta3[s] * p->prm.L / (bdt * bdt * bdt);
+            for (int k = 0; k < B; ++k) {
+                const double kp = k < B / 2 ? k : k - B;
+                const double om = w1 * kp;
+                const double u = p->beta2[s] * om + 0.5 * p->beta3[s] * om * om;
+                const double sg = (u > 0) - (u < 0);
+                const double x1 = (std::fabs(u) * hd - 0.35) / 0.15;
+                const double dm_dg = slope(x1) / 0.15 * drop((2.0 * std::fabs(kp) / B - 0.8) / 0.1);
+                const double dm2 = dm_dg * sg * om * hd, dm3 = dm_dg * sg * 0.5 * om * om * hd;
+                const double turns = c2 * kp * kp + c3 * kp * kp * kp;
+                const double f = turns - std::nearbyint(turns);
+                const double c = std::cos(2.0 * pi * f), sn = std::sin(2.0 * pi * f);
+                double* row = t.data() + (size_t)s * 4 * B;
+                row[2 * k] = dm2 * c;
+                row[2 * k + 1] = dm2 * sn;
+                row[2 * B + 2 * k] = dm3 * c;
+                row[2 * B + 2 * k + 1] = dm3 * sn;
+            }
+        }
+        if (hipMalloc(&p->adj_mask, t.size() * 8) != hipSuccess ||
+            hipMemcpy(p->adj_mask, t.data(), t.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(MPA_EDEVICE, "adjoint: roll-off derivative table upload failed");
+    }
+    return MPA_OK;
+}
+
+// Reverse pass of long step m: g_in (FP64) from g_out (FP64), adding the
+// step's parameter derivatives to param_grad.
+static int adjoint_long_step(mpa_plan* p, const void* in, const void* g_out, void* g_in, int64_t m,
+                             double* param_grad, hipStream_t stream) {
+    const int s = p->sched.span_of(m);
+    const int M = p->prm.M;
+    const double gain = p->sched.amp_after(m) ? std::exp(p->gamma * p->z_amp) : 1.0;
+    mpa::AdjointStepArgs a;
+    a.in = in;
+    a.g_out = g_out;
+    a.g_blk = p->adj_gblk;
+    a.partial = (double*)p->adj_partial;
+    a.node_store = p->adj_node;
+    a.last_store = p->adj_last;
+    a.n = p->prm.n;
+    a.block = p->block;
+    a.halo = p->halo;
+    a.core = p->core;
+    a.n_blocks = p->n_blocks;
+    a.phase = (const char*)p->phase + (size_t)s * (M + 1) * p->block * p->elem;
+    a.phase_last = (const char*)p->phase_last + (size_t)s * p->block * 16;
+    a.node_scale = (const char*)p->node_scale + (size_t)s * 2 * (M + 1) * (p->elem / 2);
+    a.twiddle = p->twiddle;
+    a.twiddle64 = p->twiddle64;
+    a.taper = p->taper;
+    a.mask_grad = p->adj_mask ? (const char*)p->adj_mask + (size_t)s * 2 * p->block * 16 : nullptr;
+    a.M = M;
+    a.n_iter = p->prm.n_iter;
+    a.sigma = p->sigma[s];
+    a.out_scale = std::exp(-p->gamma * p->prm.L) / p->block * gain;
+    a.w1 = 2.0 * 3.14159265358979323846 / (p->block * p->prm.dt);
+    a.dz = p->prm.L / M;
+    a.precision = p->prm.precision;
+    a.stream = stream;
+    hipError_t e = mpa::launch_adjoint_step(a);
+    if (e != hipSuccess) return fail(MPA_EDEVICE, "adjoint step launch failed: %s", hipGetErrorString(e));
+    e = mpa::launch_adjoint_gather(p->adj_gblk, g_in, p->prm.n, p->block, p->core, p->halo, p->n_blocks,
+                                   (const double*)p->adj_partial, param_grad, (int)p->beta2.size(), s, stream);
+    if (e != hipSuccess) return fail(MPA_EDEVICE, "adjoint gather launch failed: %s", hipGetErrorString(e));
+    return MPA_OK;
+}
+
+static void* field_at(const mpa_plan* p, const void* base, int64_t i) {
+    return (char*)base + (size_t)i * p->prm.n * p->elem;
+}
+
+// Run `count` long steps from m, reading `src` and leaving the result in `dst`,
+// using inputs slots 0.. as intermediates (src may be slot 0).
+static int advance(mpa_plan* p, const void* src, void* dst, int64_t m, int64_t count, hipStream_t stream) {
+    const void* cur = src;
+    for (int64_t i = 0; i < count; ++i) {
+        void* out = (i == count - 1) ? dst : field_at(p, p->adj_inputs, (i + 1) % 2);
+        int st = launch_long_step(p, cur, out, m + i, stream);
+        if (st) return st;
+        cur = out;
+    }
+    return MPA_OK;
+}
+
+int mpa_checkpoint_count(const mpa_plan* p, double z0, double z1, int64_t* count) {
+    if (!p || !count) return fail(MPA_EINVAL, "NULL plan or count");
+    int64_t m0, m1;
+    int st = grid_range(p, z0, z1, &m0, &m1);
+    if (st) return st;
+    *count = (int64_t)segment_starts(p, m0, m1).size();
+    return MPA_OK;
+}
+
+int mpa_propagate_checkpointed(mpa_plan* p, void* field, double z0, double z1, void* checkpoints,
+                               void* stream) {
+    if (!p || !field) return fail(MPA_EINVAL, "NULL plan or field");
+    int64_t m0, m1;
+    int st = grid_range(p, z0, z1, &m0, &m1);
+    if (st) return st;
+    const std::vector<int64_t> seg = segment_starts(p, m0, m1);
+    if (!seg.empty() && !checkpoints) return fail(MPA_EINVAL, "NULL checkpoints");
+    if (hipSetDevice(p->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+    for (size_t k = 0; k < seg.size(); ++k) {
+        const int64_t a = seg[k], b = (k + 1 < seg.size()) ? seg[k + 1] : m1;
+        if (mpa::launch_copy_field(field, field_at(p, checkpoints, (int64_t)k), p->prm.n, p->prm.precision, s) !=
+            hipSuccess)
+            return fail(MPA_EDEVICE, "checkpoint copy failed");
+        st = march(p, field, p->work, p->prm.n, a * p->prm.L, b * p->prm.L, s, nullptr);
+        if (st) return st;
+    }
+    return MPA_OK;
+}
+
+int mpa_adjoint(mpa_plan* p, const void* checkpoints, void* grad, double z0, double z1, double* param_grad,
+                int64_t store_steps, void* stream) {
+    if (!p || !grad || !param_grad) return fail(MPA_EINVAL, "NULL plan, grad or param_grad");
+    if (store_steps < 0) return fail(MPA_EINVAL, "store_steps must be >= 0");
+    int64_t m0, m1;
+    int st = grid_range(p, z0, z1, &m0, &m1);
+    if (st) return st;
+    const std::vector<int64_t> seg = segment_starts(p, m0, m1);
+    if (!seg.empty() && !checkpoints) return fail(MPA_EINVAL, "NULL checkpoints");
+    if (hipSetDevice(p->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+    const int n_seg = (int)p->beta2.size();
+    if (mpa::launch_zero(param_grad, 3 * (int64_t)n_seg, s) != hipSuccess)
+        return fail(MPA_EDEVICE, "param_grad clear failed");
+    if (seg.empty()) return MPA_OK;
+    st = adjoint_setup(p);
+    if (st) return st;
+
+    // the longest segment decides how many step inputs are kept at once
+    int64_t longest = 0;
+    for (size_t k = 0; k < seg.size(); ++k)
+        longest = std::max(longest, ((k + 1 < seg.size()) ? seg[k + 1] : m1) - seg[k]);
+    const int64_t field_bytes = p->prm.n * (int64_t)p->elem;
+    int64_t Q = store_steps;
+    if (Q == 0) Q = longest * field_bytes <= MPA_ADJOINT_STORE_BYTES ? longest : (int64_t)std::ceil(std::sqrt((double)longest));
+    Q = std::max<int64_t>(1, std::min(Q, longest));
+    st = reserve_fields(p, &p->adj_inputs, &p->adj_inputs_cap, std::max<int64_t>(Q, 2));
+    if (st) return st;
+    const int64_t n_sub = (longest + Q - 1) / Q;
+    if (n_sub > 1) {
+        st = reserve_fields(p, &p->adj_subs, &p->adj_subs_cap, n_sub);
+        if (st) return st;
+    }
+
+    void* ga = p->adj_ga;
+    void* gb = p->adj_gb;
+    if (mpa::launch_convert(grad, p->prm.precision, ga, MPA_C128, p->prm.n, s) != hipSuccess)
+        return fail(MPA_EDEVICE, "gradient conversion failed");
+    for (int64_t k = (int64_t)seg.size() - 1; k >= 0; --k) {
+        const int64_t a = seg[k], b = (k + 1 < (int64_t)seg.size()) ? seg[k + 1] : m1;
+        const void* ck = field_at(p, checkpoints, k);
+        const int64_t P = b - a, subs = (P + Q - 1) / Q;
+        // inner checkpoints at a + j Q (j >= 1) when the segment is longer than Q
+        for (int64_t j = 1; j < subs; ++j) {
+            st = advance(p, j == 1 ? ck : field_at(p, p->adj_subs, j - 1), field_at(p, p->adj_subs, j),
+                         a + (j - 1) * Q, Q, s);
+            if (st) return st;
+        }
+        for (int64_t j = subs - 1; j >= 0; --j) {
+            const int64_t s0 = a + j * Q, q = std::min(Q, b - s0);
+            const void* start = j == 0 ? ck : field_at(p, p->adj_subs, j);
+            // inputs of steps s0 .. s0 + q - 1 in slots 0 .. q - 1
+            if (mpa::launch_copy_field(start, p->adj_inputs, p->prm.n, p->prm.precision, s) != hipSuccess)
+                return fail(MPA_EDEVICE, "copy failed");
+            for (int64_t i = 0; i + 1 < q; ++i) {
+                st = launch_long_step(p, field_at(p, p->adj_inputs, i), field_at(p, p->adj_inputs, i + 1), s0 + i, s);
+                if (st) return st;
+            }
+            for (int64_t i = q - 1; i >= 0; --i) {
+                st = adjoint_long_step(p, field_at(p, p->adj_inputs, i), ga, gb, s0 + i, param_grad, s);
+                if (st) return st;
+                std::swap(ga, gb);
+            }
+        }
+    }
+    if (mpa::launch_convert(ga, MPA_C128, grad, p->prm.precision, p->prm.n, s) != hipSuccess)
+        return fail(MPA_EDEVICE, "gradient conversion failed");
+    return MPA_OK;
 }
 
 // ---- batches of independent fields -------------------------------------------------
