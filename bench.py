@@ -39,10 +39,12 @@ KERNEL_SOURCES = ("paper_1101_0086_amd/csrc/mpa_kernels.hip", "paper_1101_0086_a
 PMC_PROFILE = "profiles/mpa_block_kernel_wdm8_n262144_pmc.md"
 
 
-def measured_traffic():
+def measured_traffic(config: str):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     PMC summary (FETCH_SIZE and WRITE_SIZE, calibrated on a copy of known
-    size), or None when the kernel sources changed since it was taken."""
+    size), or None when the kernel sources or the launch configuration
+    (`config`, e.g. "B=4096 H=512 L=0.00025 M=4 n_iter=2") changed since it
+    was taken."""
     import hashlib
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
@@ -53,8 +55,10 @@ def measured_traffic():
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines()
-                  if line.startswith(("traffic_bytes_per_launch:", "kernel-source-sha256:")))
+                  if line.startswith(("traffic_bytes_per_launch:", "kernel-source-sha256:", "launch-config:")))
     if fields.get("kernel-source-sha256", "").strip() != h.hexdigest():
+        return None
+    if fields.get("launch-config", "").strip() != config:
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -96,6 +100,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip accuracy and split-step comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-instance measurement")
+    ap.add_argument("--no-grad", action="store_true", help="skip the gradient (reverse pass) measurement")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="for rocprofv3 --pmc: a 64 MiB copy (counter calibration), then 20 long steps")
     args = ap.parse_args()
@@ -169,7 +174,8 @@ def main():
                    "precision": "FP32 node work, FP64 phases and carry"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": measured_traffic() if w.name == "wdm8_n262144_f32" else None,
+                     "traffic": measured_traffic(f"B={s.block} H={s.halo} L={s.L:g} M={s.M} n_iter={s.n_iter}")
+                     if w.name == "wdm8_n262144_f32" else None,
                      "kernel": "mpa_block_kernel", "launch_us": launch_s * 1e6,
                      "flops_per_launch": fl},
     }
@@ -180,6 +186,8 @@ def main():
         out["batched"] = batched(torch, P)
         out["autotune"] = autotune_table(w, a0, torch, P)
         out["large"] = large(torch, P)
+    if not args.no_grad:
+        out["gradient"] = gradient(torch, P)
     plan.close()
     if not args.no_cpu:
         log("CPU oracle baseline ...")
@@ -276,6 +284,65 @@ def large(torch, P, steps=200):
          "ss_f32_mode_steps_per_s": n * steps / t_ss}
     log(f"large: MPA {r['mpa_mode_steps_per_s']:.3e} ({r['mpa_us_per_launch']:.0f} us/launch), "
         f"split-step {r['ss_f32_mode_steps_per_s']:.3e} mode-steps/s")
+    return r
+
+
+def adjoint_flops_per_block(B: int, M: int, n_iter: int) -> float:
+    """Algorithmic flops of the reverse pass of one block and long step:
+    4 n_iter M + 7 transforms (recomputed forward and reverse) of 5 B log2 B
+    flops, and about 100 n_iter M + 60 flops per point of elementwise work."""
+    return 5.0 * B * math.log2(B) * (4 * n_iter * M + 7) + B * (100.0 * n_iter * M + 60)
+
+
+def gradient(torch, P, periods=20):
+    """Gradient workload: 2^16 modes, 4 OOK channels, 20 map periods
+    (80000 long steps, B = 2048, H = 256, L = 2.5e-4, M = 2, 2 sweeps, FP32
+    node work), loss = sum |A(z1) - target|^2: the plain forward, the
+    checkpointed forward (one checkpoint per period) and the reverse pass
+    (which recomputes each period from its checkpoint), timed separately
+    after a warm-up."""
+    from workloads import WORKLOADS
+    w = WORKLOADS["wdm4_n65536_f32"]
+    s = w.mpa
+    a = w.field()
+    plan = P.MPAPlan(w.grid.n, w.grid.dt, w.dmmap, s.L, s.M, s.n_iter, s.block, s.halo, P.MPA_C64, s.omega_band)
+    x0 = torch.from_numpy(a).to(device="cuda:0", dtype=torch.complex64)
+    target = torch.from_numpy(w.field(seed=w.seed + 100)).to(device="cuda:0", dtype=torch.complex64)
+    z1 = float(periods)
+    steps = int(round(z1 / s.L))
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    x = x0.clone()
+    ck = plan.propagate_checkpointed(x, 0.0, 20 * s.L)            # warm-up, workspace
+    plan.adjoint(ck, (2 * x).contiguous(), 0.0, 20 * s.L)
+    x = x0.clone()
+    t_fwd, _ = timed(lambda: plan.propagate(x, 0.0, z1))
+    x = x0.clone()
+    t_ck, ck = timed(lambda: plan.propagate_checkpointed(x, 0.0, z1))
+    g = (2 * (x - target)).contiguous()
+    t_adj, pg = timed(lambda: plan.adjoint(ck, g, 0.0, z1))
+    nb = plan.info()["n_blocks"]
+    plan.close()
+    t_rev_kernels = t_adj - t_fwd                                   # the reverse pass re-runs the forward once
+    fl = adjoint_flops_per_block(s.block, s.M, s.n_iter) * nb
+    pgc = pg.cpu().numpy()
+    r = {"workload": w.name, "n_modes": w.grid.n, "periods": periods, "long_steps": steps, "block": s.block,
+         "halo": s.halo, "L": s.L, "M": s.M, "n_iter": s.n_iter, "n_blocks": nb, "checkpoints": int(ck.shape[0]),
+         "forward_s": t_fwd, "checkpointed_forward_s": t_ck, "reverse_s": t_adj,
+         "gradient_over_forward": (t_ck + t_adj) / t_fwd,
+         "gradient_mode_steps_per_s": w.grid.n * s.M * steps / (t_ck + t_adj),
+         "adjoint_step_us": t_rev_kernels / steps * 1e6,
+         "adjoint_flops_per_launch": fl,
+         "adjoint_tflops": fl * steps / t_rev_kernels / 1e12 if t_rev_kernels > 0 else None,
+         "dl_dsigma": pgc[0].tolist(), "dl_dbeta2": pgc[1].tolist(), "dl_dbeta3": pgc[2].tolist()}
+    log(f"gradient ({periods} periods): forward {t_fwd:.2f} s, checkpointed {t_ck:.2f} s, reverse {t_adj:.2f} s "
+        f"({r['gradient_over_forward']:.2f}x forward), reverse step {r['adjoint_step_us']:.1f} us")
     return r
 
 

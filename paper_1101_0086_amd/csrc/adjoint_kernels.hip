@@ -22,7 +22,10 @@
 // reverse pass then visits the nodes from M down to 1 and, at each node, the
 // sweeps from last to first: the gradient of psi^(s+1)_l is then complete
 // when node (s, l) is processed, and the reverse trapezoid sums are one
-// running sum per sweep, kept in registers like the forward sums.
+// running sum per sweep, kept in registers like the forward sums.  The
+// gradient of psi^(n_iter)_M is the only one of the size of the field's
+// gradient and stays FP64; the others carry a factor sigma dz and are kept
+// in the node precision.
 #include "block_fft.hpp"
 #include "launch.hpp"
 
@@ -144,9 +147,17 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
     }
 
     // ---- reverse pass ----
+    // Only the gradient of psi^(n_iter)_M (from the output) is of the size of
+    // the field's gradient; it reaches psi_0 with weight 1 and every U of the
+    // last sweep with weight 1/2 or 1, and is kept in FP64 (`big`).  Every
+    // other gradient in the block passes through a node evaluation (a factor
+    // sigma dz) and is kept in the node precision T: the running reverse
+    // trapezoid sums Rs of the earlier sweeps, the carried G(psi^(s+1)_l) and
+    // the sweep-0 part of G(psi_0).
     double d_sigma = 0.0, d_beta2 = 0.0, d_beta3 = 0.0;
-    cx<double> gp0[R], Rs[NIT][R], gn[R];
-    cx<T> cur[R], ph[R];
+    cx<double> big[R];
+    cx<T> gp0[R], gn[R], cur[R], ph[R];
+    cx<T> Rs[NIT > 1 ? NIT - 1 : 1][R];
     const double zM = M * dz;
     {
         // step 7: out = out_scale F^-1[psi_M e^{i beta_M} mask]; only the core is output
@@ -155,14 +166,14 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
 #pragma unroll
         for (int m = 0; m < R; ++m) {
             const int t = tid + NT * m;
-            gn[m] = (t >= halo && t < halo + clen) ? g_out[c0 + (t - halo)] : cx<double>{0.0, 0.0};
+            big[m] = (t >= halo && t < halo + clen) ? g_out[c0 + (t - halo)] : cx<double>{0.0, 0.0};
         }
-        block_fft<double, B, R, +1>(gn, lds64, tw64, tid);
+        block_fft<double, B, R, +1>(big, lds64, tw64, tid);
 #pragma unroll
         for (int m = 0; m < R; ++m) {
             const int k = tid + NT * m;
             const double om = w1 * double(k < B / 2 ? k : k - B);
-            const cx<double> gx = scale(gn[m], out_scale);
+            const cx<double> gx = scale(big[m], out_scale);
             const cx<double> psiM = last[k];
             const cx<double> pl = phase_last[k];
             const double r = re_dot_i(gx, cmul(psiM, pl));
@@ -172,10 +183,10 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
                 d_beta2 += re_dot(gx, cmul(psiM, mask_grad[k]));
                 d_beta3 += re_dot(gx, cmul(psiM, mask_grad[B + k]));
             }
-            gn[m] = cmulc(gx, pl);                                          // G(psi^(n_iter)_M)
-            gp0[m] = {0.0, 0.0};
+            big[m] = cmulc(gx, pl);                                         // G(psi^(n_iter)_M)
+            gp0[m] = {T(0), T(0)};
 #pragma unroll
-            for (int s = 0; s < NIT; ++s) Rs[s][m] = {0.0, 0.0};
+            for (int s = 0; s + 1 < NIT; ++s) Rs[s][m] = {T(0), T(0)};
         }
     }
     for (int l = M; l >= 1; --l) {
@@ -183,20 +194,23 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
         const T dl = sigma * node_scale[2 * l + 1];
         const double zl = l * dz;
 #pragma unroll
-        for (int m = 0; m < R; ++m) {
-            ph[m] = phase[(size_t)l * B + tid + NT * m];
-            if (l < M) gn[m] = {0.0, 0.0};
-        }
+        for (int m = 0; m < R; ++m) ph[m] = phase[(size_t)l * B + tid + NT * m];
 #pragma unroll
         for (int s = NIT - 1; s >= 0; --s) {
             const cx<T>* __restrict__ slot = store + (size_t)((s * M + l - 1) * 3) * B;
-            // trapezoid adjoint, then U = i dl e^{-i beta_l} F[n]
+            // trapezoid adjoint: G(U^(s)_l) = G(psi^(s+1)_l) / 2 + sum_{l' > l} G(psi^(s+1)_l')
 #pragma unroll
             for (int m = 0; m < R; ++m) {
-                const int k = tid + NT * m;
+                int k = tid + NT * m;
+                asm volatile("" : "+v"(k));      // recomputed per node: keeps omega out of registers
                 const double om = w1 * double(k < B / 2 ? k : k - B);
-                const cx<double> gu = scale(gn[m], 0.5) + Rs[s][m];
-                Rs[s][m] = Rs[s][m] + gn[m];
+                cx<double> gu;
+                if (s == NIT - 1) {
+                    gu = (l == M) ? scale(big[m], 0.5) : big[m];
+                } else {
+                    gu = widen(scale(gn[m], T(0.5)) + Rs[s][m]);
+                    Rs[s][m] = Rs[s][m] + gn[m];
+                }
                 const cx<double> up = widen(slot[2 * B + k]);
                 d_sigma += re_dot(gu, up);
                 const double r = -re_dot_i(gu, up) * double(sigma);
@@ -214,13 +228,14 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
             block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
 #pragma unroll
             for (int m = 0; m < R; ++m) {
-                const int k = tid + NT * m;
+                int k = tid + NT * m;
+                asm volatile("" : "+v"(k));
                 const double om = w1 * double(k < B / 2 ? k : k - B);
                 const cx<T> gy = scale(cur[m], cl);                           // G(y)
                 const double r = re_dot_i(widen(gy), widen(slot[B + k]));
                 d_beta2 += r * (0.5 * om * om * zl);
                 d_beta3 += r * (om * om * om * zl / 6.0);
-                const cx<double> gps = widen(cmulc(gy, ph[m]));               // G(psi^(s)_l)
+                const cx<T> gps = cmulc(gy, ph[m]);                           // G(psi^(s)_l)
                 if (s > 0) gn[m] = gps;
                 else gp0[m] = gp0[m] + gps;
             }
@@ -230,13 +245,16 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
     // node 0 (U_0 = i sigma dz F[|A_0|^2 A_0], shared by every sweep) and psi_0 = F[A_0]
     const T e0 = node_scale[1];
     const T d0 = sigma * e0;
+    cx<double> g0[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        cx<double> tot = {0.0, 0.0};
+        // sum over l >= 1 of G(psi^(s+1)_l) for every sweep: the last sweep's is big
+        cx<T> small = {T(0), T(0)};
 #pragma unroll
-        for (int s = 0; s < NIT; ++s) tot = tot + Rs[s][m];
-        gp0[m] = gp0[m] + tot;
-        gn[m] = scale(tot, 0.5);                                              // G(U_0)
+        for (int s = 0; s + 1 < NIT; ++s) small = small + Rs[s][m];
+        const cx<double> tot = big[m] + widen(small);
+        g0[m] = tot + widen(gp0[m]);                                          // G(psi_0)
+        big[m] = scale(tot, 0.5);                                             // G(U_0)
         const int t = tid + NT * m;
         const cx<double> a = scale(widen(in[wrap(w0 + t, n)]), taper[t]);
         cur[m] = narrow<T>(scale(a, norm2(a)));
@@ -244,17 +262,17 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
     block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        d_sigma += re_dot(gn[m], widen(rot<+1>(scale(cur[m], e0))));
-        cur[m] = rot<-1>(scale(narrow<T>(gn[m]), d0));
+        d_sigma += re_dot(big[m], widen(rot<+1>(scale(cur[m], e0))));
+        cur[m] = rot<-1>(scale(narrow<T>(big[m]), d0));
     }
     block_fft<T, B, R, -1>(cur, ldsT, tw, tid);                              // G(n_0)
-    block_fft<double, B, R, -1>(gp0, lds64, tw64, tid);                      // G(A_0) via psi_0
+    block_fft<double, B, R, -1>(g0, lds64, tw64, tid);                       // G(A_0) via psi_0
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const int t = tid + NT * m;
         const cx<double> a = scale(widen(in[wrap(w0 + t, n)]), taper[t]);
         const cx<double> g = widen(cur[m]);
-        const cx<double> ga = gp0[m] + scale(g, 2.0 * norm2(a)) + sq_conj(a, g);
+        const cx<double> ga = g0[m] + scale(g, 2.0 * norm2(a)) + sq_conj(a, g);
         g_blk[(size_t)blockIdx.x * B + t] = scale(ga, taper[t]);
     }
 

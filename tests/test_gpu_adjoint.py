@@ -121,7 +121,7 @@ def test_sweeps_and_nodes(nit):
 
 @pytest.mark.parametrize("prec", [1, 0])
 def test_c5_full_size_two_long_steps_against_oracle(prec):
-    """2^16 modes, 4 OOK channels, B = 4096, H = 512, L = 5e-4, M = 4, two
+    """2^16 modes, 4 OOK channels, B = 2048, H = 256, L = 2.5e-4, M = 2, two
     sweeps, beta3 = 0.1: the launch configuration of the gradient workload."""
     w = WORKLOADS["wdm4_n65536_f32"]
     s = w.mpa
@@ -137,7 +137,7 @@ def test_c5_full_size_two_long_steps_against_oracle(prec):
 
 
 def test_c5_full_period_finite_differences():
-    """Directional derivatives over one whole map period (2000 long steps,
+    """Directional derivatives over one whole map period (4000 long steps,
     FP64 plan) against central differences of the GPU forward: the field
     along a random direction, and sigma, beta2, beta3 of both spans."""
     import torch

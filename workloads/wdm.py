@@ -207,7 +207,7 @@ WORKLOADS = {
     "wdm8_n262144_f32": Workload(
         "wdm8_n262144_f32", Grid(1 << 18, T_BIT / 1024), 256, 8, "ook",
         dm_map(beta3=0.1), 100,
-        MPASettings(L=2.5e-4, M=2, n_iter=2, block=4096, halo=512,
+        MPASettings(L=2.5e-4, M=4, n_iter=2, block=4096, halo=512,
                     omega_band=_omega_sig(8)),
         "f32", 2, _omega_sig(8)),
     # 32-channel QPSK WDM, 2^22 modes
@@ -221,7 +221,7 @@ WORKLOADS = {
     "wdm4_n65536_f32": Workload(
         "wdm4_n65536_f32", Grid(1 << 16, T_BIT / 1024), 64, 4, "ook",
         dm_map(beta3=0.1), 20,
-        MPASettings(L=5e-4, M=4, n_iter=2, block=4096, halo=512,
+        MPASettings(L=2.5e-4, M=2, n_iter=2, block=2048, halo=256,
                     omega_band=_omega_sig(4)),
         "f32", 5, _omega_sig(4)),
 }
