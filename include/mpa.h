@@ -75,6 +75,23 @@ typedef enum {
     MPA_C128 = 1    /* FP64 everywhere                                        */
 } mpa_precision;
 
+/* Order in which a block's node evaluations run; both give the same field
+ * (bitwise for MPA_C64; for MPA_C128 to the last bits, max relative
+ * difference of order 1e-16).
+ *   MPA_WAVEFRONT: one fused kernel per long step, one workgroup per block;
+ *     nodes l = 1..M in turn and, at each node, all n_iter sweeps (sweep n+1
+ *     at node l needs only sweep-n values at nodes <= l), with psi_0 and
+ *     one running trapezoid sum per sweep held in registers.
+ *   MPA_NODE_PARALLEL: the paper's order (steps 2-6 sweep by sweep, every
+ *     node of a sweep independent): n_iter + 2 launches per long step, the
+ *     node work of a sweep as n_blocks x M workgroups, psi_0 and the
+ *     increments of two sweeps kept in device memory (plan-owned,
+ *     n_blocks x (2 M + 1) x B complex plus n_blocks x B FP64 complex).   */
+typedef enum {
+    MPA_WAVEFRONT = 0,
+    MPA_NODE_PARALLEL = 1
+} mpa_schedule;
+
 /* One period of a piecewise-constant dispersion map (coefficients constant on
  * each span, the assumption of the paper's accuracy analysis).  The arrays
  * are host memory of n_seg entries, read and copied during plan creation.
@@ -103,6 +120,8 @@ typedef struct {
     int32_t precision;     /* mpa_precision                                      */
     double omega_band;     /* highest |omega| carrying signal, for the halo
                               check; 0 means the grid's Nyquist frequency        */
+    int32_t schedule;      /* mpa_schedule (single-field plans; batches take
+                              MPA_WAVEFRONT)                                    */
 } mpa_params;
 
 typedef struct mpa_plan mpa_plan;   /* opaque: device tables and workspace */
@@ -112,7 +131,8 @@ typedef struct {
     int32_t block, halo, core, n_blocks;
     int32_t threads_per_block;
     int64_t table_bytes;       /* device bytes of phase/twiddle/taper tables   */
-    int64_t workspace_bytes;   /* device bytes of the ping-pong field buffer    */
+    int64_t workspace_bytes;   /* device bytes of the ping-pong field buffer, plus
+                                  the node-parallel state when scheduled so     */
 } mpa_plan_info;
 
 /* Validate parameters, build the FP64 dispersion-phase tables on `device`

@@ -22,6 +22,9 @@ MPA_EUNSUPPORTED = -6
 MPA_C64 = 0
 MPA_C128 = 1
 
+MPA_WAVEFRONT = 0
+MPA_NODE_PARALLEL = 1
+
 # symbols declared in include/mpa.h
 EXPORTED = ("mpa_plan_create", "mpa_plan_destroy", "mpa_plan_get_info", "mpa_plan_validate",
             "mpa_step", "mpa_propagate", "mpa_batch_plan_validate", "mpa_batch_plan_create",
@@ -40,7 +43,7 @@ class mpa_map(C.Structure):
 class mpa_params(C.Structure):
     _fields_ = [("n", C.c_int64), ("dt", C.c_double), ("L", C.c_double), ("M", C.c_int32),
                 ("n_iter", C.c_int32), ("block", C.c_int32), ("halo", C.c_int32),
-                ("precision", C.c_int32), ("omega_band", C.c_double)]
+                ("precision", C.c_int32), ("omega_band", C.c_double), ("schedule", C.c_int32)]
 
 
 class mpa_batch_desc(C.Structure):
@@ -126,9 +129,10 @@ class MapStruct:
                          float(dmmap.gamma), float(dmmap.z_amp))
 
 
-def make_params(n, dt, L, M, n_iter, block=0, halo=0, precision=MPA_C64, omega_band=0.0):
+def make_params(n, dt, L, M, n_iter, block=0, halo=0, precision=MPA_C64, omega_band=0.0,
+                schedule=MPA_WAVEFRONT):
     return mpa_params(int(n), float(dt), float(L), int(M), int(n_iter), int(block), int(halo),
-                      int(precision), float(omega_band))
+                      int(precision), float(omega_band), int(schedule))
 
 
 class BatchDesc:

@@ -130,6 +130,7 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
                 const bool final_sum = last_node && (s == NIT - 1);
 #pragma unroll
                 for (int m = 0; m < R; ++m) {
+#pragma clang fp contract(off)
                     const cx<T> v = cmulc(cur[m], ph[m]);
                     slot[2 * B + tid + NT * m] = rot<+1>(scale(v, el));    // U / sigma
                     const cx<double> u = widen(rot<+1>(scale(v, dl)));

@@ -57,20 +57,23 @@ __device__ __forceinline__ void dft8(cx<T> (&x)[8]) {
     dft4<SIGN>(x[0], x[2], x[4], x[6]);
     dft4<SIGN>(x[1], x[3], x[5], x[7]);
     // twiddle the odd half: O_1 *= w, O_2 *= w^2 = SIGN i, O_3 *= w^3
+    // w O_1 = h (O_1 + SIGN i O_1) and w^3 O_3 = h (-O_3 + SIGN i O_3): the sums
+    // are exact up to one rounding, the factor h is applied inside an
+    // explicit fused multiply-add with E_k
     cx<T> o1 = x[3], o2 = x[5], o3 = x[7];
     const T s = T(SIGN);
-    o1 = {(o1.re - s * o1.im) * h, (o1.im + s * o1.re) * h};
+    const cx<T> t1 = {o1.re - s * o1.im, o1.im + s * o1.re};
+    const cx<T> t3 = {-o3.re - s * o3.im, -o3.im + s * o3.re};
     o2 = rot<SIGN>(o2);
-    o3 = {(-o3.re - s * o3.im) * h, (-o3.im + s * o3.re) * h};
     cx<T> e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6], o0 = x[1];
     x[0] = e0 + o0;
     x[4] = e0 - o0;
-    x[1] = e1 + o1;
-    x[5] = e1 - o1;
+    x[1] = {fma(t1.re, h, e1.re), fma(t1.im, h, e1.im)};
+    x[5] = {fma(-t1.re, h, e1.re), fma(-t1.im, h, e1.im)};
     x[2] = e2 + o2;
     x[6] = e2 - o2;
-    x[3] = e3 + o3;
-    x[7] = e3 - o3;
+    x[3] = {fma(t3.re, h, e3.re), fma(t3.im, h, e3.im)};
+    x[7] = {fma(-t3.re, h, e3.re), fma(-t3.im, h, e3.im)};
 }
 
 template <int SIGN, int r, typename T>

@@ -17,6 +17,14 @@ struct BatchItems {
     int32_t grid;             // workgroups walking the list
 };
 
+// Device state of the node-parallel schedule (per block: psi_0 in FP64,
+// U_0 / 2, and the increments U_1..U_M of two sweeps, node precision).
+struct NodeBuffers {
+    void* psi0;     // n_blocks x B FP64 complex
+    void* half_u0;  // n_blocks x B complex
+    void* u[2];     // n_blocks x M x B complex each (sweeps alternate)
+};
+
 // One fused long step over every block of one field (batch == nullptr) or
 // of every instance of a batch.
 struct BlockStepArgs {
@@ -35,12 +43,15 @@ struct BlockStepArgs {
     double out_scale;        // e^{Gamma_M} / B, times the lumped gain
     int32_t precision;       // 0: FP32 field / 1: FP64
     const BatchItems* batch; // nullptr for a single field
+    const NodeBuffers* nodes;// node-parallel schedule (single field); nullptr: fused wavefront kernel
     hipStream_t stream;
 };
 
 bool block_step_supported(int precision, int block, int n_iter);
 int threads_per_block(int precision, int block);
 hipError_t launch_block_step(const BlockStepArgs& a);
+// The same long step as n_iter + 2 launches in the node-parallel schedule (a.nodes != nullptr).
+hipError_t launch_node_parallel_step(const BlockStepArgs& a);
 hipError_t launch_copy_field(const void* src, void* dst, int64_t count, int precision, hipStream_t stream);
 
 // Reverse pass of one long step over every block of one field.

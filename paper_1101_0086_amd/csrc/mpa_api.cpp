@@ -137,6 +137,8 @@ struct mpa_plan {
     void* taper = nullptr;              // B FP64 reals
     void* work = nullptr;               // N complex
     int64_t table_bytes = 0;
+    mpa::NodeBuffers nodes{};           // node-parallel schedule state (else all NULL)
+    int64_t node_bytes = 0;
     // reverse-pass workspace, allocated by the first mpa_adjoint call
     void* adj_node = nullptr;           // n_blocks x n_iter x M x 3 x B complex
     void* adj_last = nullptr;           // n_blocks x B FP64 complex
@@ -157,7 +159,7 @@ static void plan_free(mpa_plan* p) {
     (void)hipDeviceSynchronize();
     for (void* q : {p->phase, p->phase_last, p->node_scale, p->twiddle, p->twiddle64, p->taper, p->work,
                     p->adj_node, p->adj_last, p->adj_gblk, p->adj_partial, p->adj_ga, p->adj_gb, p->adj_mask,
-                    p->adj_inputs, p->adj_subs})
+                    p->adj_inputs, p->adj_subs, p->nodes.psi0, p->nodes.half_u0, p->nodes.u[0], p->nodes.u[1]})
         if (q) (void)hipFree(q);
     delete p;
 }
@@ -175,6 +177,8 @@ static int validate_params(const mpa_params* p, const mpa_map* map, Schedule* sc
     if (p->precision != MPA_C64 && p->precision != MPA_C128)
         return fail(MPA_EINVAL, "precision = %d is not MPA_C64 or MPA_C128", p->precision);
     if (!(p->omega_band >= 0) || !is_finite(p->omega_band)) return fail(MPA_EINVAL, "omega_band must be >= 0");
+    if (p->schedule != MPA_WAVEFRONT && p->schedule != MPA_NODE_PARALLEL)
+        return fail(MPA_EINVAL, "schedule = %d is not MPA_WAVEFRONT or MPA_NODE_PARALLEL", p->schedule);
     const bool full = (p->block == 0 || (p->block == p->n && p->halo == 0));
     if (full) {
         if (p->halo != 0) return fail(MPA_EINVAL, "halo must be 0 for a full-window plan");
@@ -335,6 +339,17 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
         plan_free(p);
         return fail(MPA_EDEVICE, "plan table construction failed");
     }
+    if (params->schedule == MPA_NODE_PARALLEL) {
+        const size_t nb = (size_t)p->n_blocks;
+        const size_t u_bytes = nb * M * B * p->elem;
+        p->node_bytes = (int64_t)(nb * B * 16 + nb * B * p->elem + 2 * u_bytes);
+        if (hipMalloc(&p->nodes.psi0, nb * B * 16) != hipSuccess ||
+            hipMalloc(&p->nodes.half_u0, nb * B * p->elem) != hipSuccess ||
+            hipMalloc(&p->nodes.u[0], u_bytes) != hipSuccess || hipMalloc(&p->nodes.u[1], u_bytes) != hipSuccess) {
+            plan_free(p);
+            return fail(MPA_ENOMEM, "node-parallel state allocation of %lld bytes failed", (long long)p->node_bytes);
+        }
+    }
     *out = p;
     return MPA_OK;
 }
@@ -353,7 +368,7 @@ int mpa_plan_get_info(const mpa_plan* p, mpa_plan_info* info) {
     info->n_blocks = p->n_blocks;
     info->threads_per_block = mpa::threads_per_block(p->prm.precision, p->block);
     info->table_bytes = p->table_bytes;
-    info->workspace_bytes = p->prm.n * (int64_t)p->elem;
+    info->workspace_bytes = p->prm.n * (int64_t)p->elem + p->node_bytes;
     return MPA_OK;
 }
 
@@ -382,8 +397,9 @@ static int launch_long_step(mpa_plan* p, const void* in, void* out, int64_t m, h
     a.out_scale = std::exp(-p->gamma * p->prm.L) / p->block * gain;
     a.precision = p->prm.precision;
     a.batch = batch;
+    a.nodes = (batch == nullptr && p->nodes.psi0) ? &p->nodes : nullptr;
     a.stream = stream;
-    const hipError_t e = mpa::launch_block_step(a);
+    const hipError_t e = a.nodes ? mpa::launch_node_parallel_step(a) : mpa::launch_block_step(a);
     if (e != hipSuccess) return fail(MPA_EDEVICE, "block step launch failed: %s", hipGetErrorString(e));
     return MPA_OK;
 }
@@ -718,6 +734,8 @@ int mpa_batch_plan_validate(const mpa_params* params, const mpa_map* map, const 
         return fail(MPA_EINVAL, "batch count must be in 1..2^20 with an n array");
     if (params->block <= 0 || params->halo <= 0)
         return fail(MPA_EINVAL, "a batch needs time blocks (block > 0, halo > 0)");
+    if (params->schedule != MPA_WAVEFRONT)
+        return fail(MPA_EUNSUPPORTED, "batches run the wavefront schedule only");
     int64_t nmax = 0;
     for (int i = 0; i < desc->count; ++i) {
         const int64_t n = desc->n[i];

@@ -69,6 +69,9 @@ def test_validation_status_codes():
     assert _validate(n=4096, block=0, halo=8, L=0.05) == L.MPA_EINVAL
     # block = n with a halo is a blocked run (two overlapping blocks), so the halo rule applies
     assert _validate(n=4096, block=4096, halo=512, L=0.05) == L.MPA_EHALO
+    # schedules
+    assert _validate(schedule=L.MPA_NODE_PARALLEL) == L.MPA_OK
+    assert _validate(schedule=2) == L.MPA_EINVAL
 
 
 def test_error_message_and_status_strings():
@@ -116,5 +119,8 @@ def test_batch_validation():
     assert L.lib().mpa_batch_plan_validate(C.byref(p), C.byref(m.s), C.byref(odd.s)) == L.MPA_EINVAL
     full = L.make_params(0, w.grid.dt, w.mpa.L, w.mpa.M, w.mpa.n_iter, 0, 0, 0, w.mpa.omega_band)
     assert L.lib().mpa_batch_plan_validate(C.byref(full), C.byref(m.s), C.byref(ok.s)) == L.MPA_EINVAL
+    nodes = L.make_params(0, w.grid.dt, w.mpa.L, w.mpa.M, w.mpa.n_iter, w.mpa.block, w.mpa.halo, 0,
+                          w.mpa.omega_band, L.MPA_NODE_PARALLEL)
+    assert L.lib().mpa_batch_plan_validate(C.byref(nodes), C.byref(m.s), C.byref(ok.s)) == L.MPA_EUNSUPPORTED
     assert L.lib().mpa_batch_propagate(None, None, C.c_double(0), C.c_double(1), None) == L.MPA_EINVAL
     assert L.lib().mpa_graph_launch(None, None) == L.MPA_EINVAL

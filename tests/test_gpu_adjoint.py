@@ -24,12 +24,16 @@ pytestmark = pytest.mark.gpu
 # with the oracle to rounding (1e-10 as for the forward).  FP32 plans: the
 # node evaluations (transforms and nonlinearity) of both the recomputed
 # forward and the reverse pass run in FP32 (unit roundoff 6e-8, FFT error
-# about 2e-7 relative), while the carried gradient and the sums are FP64;
-# over the short ranges here the relative error stays within 1e-5 for the
-# field gradient and 1e-4 for the parameter derivatives, which are sums of
-# products that cancel partly.
+# about 2e-7 relative), the output-sized gradient and the carry in FP64.  The
+# field gradient stays within 1e-5.  The parameter derivatives are compared
+# as one vector (sigma, beta2, beta3 of every span) relative to its norm,
+# within 1e-3: the beta2 and beta3 derivatives weight every frequency by
+# omega^2 z / 2 and omega^3 z / 6, which amplifies the FP32 rounding noise
+# of the nearly empty spectrum up to |omega| = pi / dt (a beta3 derivative
+# of 0.16 is off by 7e-4 on the 4096-mode case, 0.5 %, while the FP64 plan
+# matches to 1e-9).
 TOL_G = {1: 1e-10, 0: 1e-5}
-TOL_P = {1: 1e-9, 0: 1e-4}
+TOL_P = {1: 1e-9, 0: 1e-3}
 
 
 def _plan(grid, dmmap, L, M, nit, block, halo, prec, band=0.0):
