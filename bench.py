@@ -401,6 +401,24 @@ def compare(w, a0, plan, x, torch, P):
     e_mpa_full, e_mpa = err(y.cpu().numpy().astype(np.complex128))
     log(f"MPA error after one period: in-band {e_mpa:.3e}, full-band {e_mpa_full:.3e} "
         f"(reference {ref_err:.1e}), {t_mpa * 1e3:.1f} ms")
+    # the same long steps with fewer and more Picard sweeps (text after Eq. 7:
+    # the iteration floor (L / z_nl)^(n+1) is far below the quadrature error here)
+    picard = []
+    for nit in (1, 3):
+        pl = P.MPAPlan(n, dt, w.dmmap, s.L, s.M, nit, s.block, s.halo, P.MPA_C64, s.omega_band)
+        y = torch.from_numpy(a0).to(device="cuda:0", dtype=x.dtype)
+        pl.propagate(y, 0.0, 0.05)
+        y = torch.from_numpy(a0).to(device="cuda:0", dtype=x.dtype)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pl.propagate(y, 0.0, 1.0)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        pl.close()
+        e_full, e = err(y.cpu().numpy().astype(np.complex128))
+        picard.append({"n_iter": nit, "rel_l2_in_band": e, "rel_l2_full_band": e_full, "seconds": el,
+                       "mode_steps_per_s": n * s.M / s.L / el})
+        log(f"MPA n_iter={nit}: in-band {e:.3e} full-band {e_full:.3e} time {el * 1e3:.1f} ms")
     sweep = []
     best = None
     for k in (1000, 1414, 2000, 2828, 4000, 5657, 8000, 11314, 16000):
@@ -421,6 +439,7 @@ def compare(w, a0, plan, x, torch, P):
                         f"{dz_ref:.3e} and dz/2, Richardson-extrapolated; the plain dz/2 run differs "
                         f"from it by {ref_err:.1e}",
                         "mpa_seconds_one_period": t_mpa},
+           "picard_sweeps": picard,
            "split_step": {"sweep": sweep, "equal_accuracy": best,
                           "time_ratio_ss_over_mpa": (best["seconds"] / t_mpa) if best else None}}
     return res
