@@ -91,7 +91,7 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
             psi0[m] = a;
             cur[m] = narrow<T>(scale(a, norm2(a)));
         }
-        block_fft<double, B, R, +1>(psi0, lds64, tw64, tid);
+        block_fft<double, B, R, +1, true>(psi0, lds64, tw64, tid);
         block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
         const T d0 = sigma * node_scale[1];
 #pragma unroll
@@ -169,7 +169,7 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
             const int t = tid + NT * m;
             big[m] = (t >= halo && t < halo + clen) ? g_out[c0 + (t - halo)] : cx<double>{0.0, 0.0};
         }
-        block_fft<double, B, R, +1>(big, lds64, tw64, tid);
+        block_fft<double, B, R, +1, true>(big, lds64, tw64, tid);
 #pragma unroll
         for (int m = 0; m < R; ++m) {
             const int k = tid + NT * m;
@@ -267,7 +267,7 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
         cur[m] = rot<-1>(scale(narrow<T>(big[m]), d0));
     }
     block_fft<T, B, R, -1>(cur, ldsT, tw, tid);                              // G(n_0)
-    block_fft<double, B, R, -1>(g0, lds64, tw64, tid);                       // G(A_0) via psi_0
+    block_fft<double, B, R, -1, true>(g0, lds64, tw64, tid);                       // G(A_0) via psi_0
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const int t = tid + NT * m;

@@ -90,7 +90,7 @@ __device__ __forceinline__ void dft(cx<T> (&x)[r]) {
 
 // ---- one Stockham pass ------------------------------------------------------
 
-template <typename T, int B, int R, int r, int p, int SIGN, bool FROM_LDS, bool TO_LDS>
+template <typename T, int B, int R, int r, int p, int SIGN, bool FROM_LDS, bool TO_LDS, bool COLD>
 __device__ __forceinline__ void fft_pass(cx<T> (&v)[R], cx<T>* lds,
                                          const cx<T>* __restrict__ tw, int tid) {
     constexpr int NT = B / R;
@@ -104,7 +104,8 @@ __device__ __forceinline__ void fft_pass(cx<T> (&v)[R], cx<T>* lds,
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         const int i = tid + u * NT;
-        const int k = i & (p - 1);
+        int k = i & (p - 1);
+        if constexpr (COLD) asm volatile("" : "+v"(k));   // twiddles loaded here, not kept live
         cx<T> x[r];
 #pragma unroll
         for (int q = 0; q < r; ++q) x[q] = v[u + q * NB];
@@ -141,25 +142,29 @@ constexpr int pass_radix() {
     }
 }
 
-template <typename T, int B, int R, int SIGN, int P>
+template <typename T, int B, int R, int SIGN, int P, bool COLD>
 __device__ __forceinline__ void fft_from(cx<T> (&v)[R], cx<T>* lds,
                                          const cx<T>* __restrict__ tw, int tid) {
     constexpr int r = pass_radix<B, P>();
     constexpr bool first = (P == 1);
     constexpr bool last = (P * r == B);
     static_assert(R % r == 0, "points per thread must be a multiple of every radix");
-    fft_pass<T, B, R, r, P, SIGN, !first, !last>(v, lds, tw, tid);
-    if constexpr (!last) fft_from<T, B, R, SIGN, P * r>(v, lds, tw, tid);
+    fft_pass<T, B, R, r, P, SIGN, !first, !last, COLD>(v, lds, tw, tid);
+    if constexpr (!last) fft_from<T, B, R, SIGN, P * r, COLD>(v, lds, tw, tid);
 }
 
 // B-point transform of the workgroup's registers (see the file comment).
 // `tw` holds exp(+2 pi i j / B), j = 0..B-1.  Must be called by every
-// thread of the workgroup (it contains barriers).
-template <typename T, int B, int R, int SIGN>
+// thread of the workgroup (it contains barriers).  COLD: the twiddle index
+// is hidden from the optimiser, so the twiddles are loaded inside each pass
+// instead of being kept in registers across the caller's code; for
+// transforms outside the hot loop, whose twiddles would otherwise hold
+// registers for the whole kernel.
+template <typename T, int B, int R, int SIGN, bool COLD = false>
 __device__ __forceinline__ void block_fft(cx<T> (&v)[R], cx<T>* lds,
                                           const cx<T>* __restrict__ tw, int tid) {
     static_assert((B & (B - 1)) == 0 && B >= 64, "power-of-two block");
-    fft_from<T, B, R, SIGN, 1>(v, lds, tw, tid);
+    fft_from<T, B, R, SIGN, 1, COLD>(v, lds, tw, tid);
 }
 
 }  // namespace mpa
