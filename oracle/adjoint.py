@@ -54,7 +54,7 @@ def block_mask_grad(omega_b, beta2, beta3, L, halo, dt):
 
 
 def mpa_long_step_vjp(a_z0, omega, beta2, beta3, sigma, gamma, L, M, n_iter, g_out,
-                      out_mask=None, mask_grad=None):
+                      out_mask=None, mask_grad=None, int_g=None):
     """Gradient of l through one long step of ``nlse.mpa_long_step``.
 
     Returns (G(a_z0), dl/dsigma, dl/dbeta2, dl/dbeta3) given G(out) = g_out.
@@ -64,7 +64,7 @@ def mpa_long_step_vjp(a_z0, omega, beta2, beta3, sigma, gamma, L, M, n_iter, g_o
     dz = L / M
     zj = dz * np.arange(M + 1)
     beta = np.outer(zj, omega ** 2 / 2.0 * beta2 + omega ** 3 / 6.0 * beta3)
-    int_g = -gamma * zj
+    int_g = -gamma * zj if int_g is None else np.asarray(int_g, dtype=float)
     to_a = np.exp(1j * beta + int_g[:, None])
     to_psi = np.exp(-1j * beta - int_g[:, None])
     k2 = np.outer(zj, omega ** 2 / 2.0)          # d theta_j / d beta2
@@ -131,14 +131,14 @@ def mpa_long_step_vjp(a_z0, omega, beta2, beta3, sigma, gamma, L, M, n_iter, g_o
 
 
 def mpa_blocked_long_step_vjp(a_z0, dt, block, halo, beta2, beta3, sigma, gamma, L, M,
-                              n_iter, g_out):
+                              n_iter, g_out, int_g=None):
     """VJP of ``nlse.mpa_blocked_long_step`` (tapered windows, roll-off,
     cores stitched): window gradients are the core of g_out, zero elsewhere;
     the input gradient adds every window's contribution."""
     n = a_z0.shape[0]
     if block == 0 or (block == n and halo == 0):
         return mpa_long_step_vjp(a_z0, omega_grid(n, dt), beta2, beta3, sigma, gamma, L, M,
-                                 n_iter, g_out)
+                                 n_iter, g_out, int_g=int_g)
     omega_b = omega_grid(block, dt)
     taper = block_taper(block, halo)
     mask = block_mask(omega_b, beta2, beta3, L, halo, dt) if halo > 0 else None
@@ -151,7 +151,7 @@ def mpa_blocked_long_step_vjp(a_z0, dt, block, halo, beta2, beta3, sigma, gamma,
         gw[halo:halo + clen] = g_out[c0:c0 + clen]
         ga, s_, b2_, b3_ = mpa_long_step_vjp(a_z0[idx] * taper, omega_b, beta2, beta3, sigma,
                                              gamma, L, M, n_iter, gw, out_mask=mask,
-                                             mask_grad=mask_grad)
+                                             mask_grad=mask_grad, int_g=int_g)
         np.add.at(g_in, idx, taper * ga)
         ds += s_
         d2 += b2_
@@ -163,7 +163,7 @@ def mpa_propagate_vjp(a, dt, dmmap, L, M, n_iter, z0, z1, g_out, block=0, halo=0
     """Gradient through ``nlse.mpa_propagate``: returns (G(a), dl/dsigma per
     span, dl/dbeta2 per span, dl/dbeta3 per span).  The forward is re-run storing the input of
     every long step."""
-    from .nlse import _grid_index, mpa_step
+    from .nlse import _grid_index, long_step_gain, lumped_gain, mpa_step
     m0, m1 = _grid_index(z0, L), _grid_index(z1, L)
     inputs = []
     for m in range(m0, m1):
@@ -178,10 +178,10 @@ def mpa_propagate_vjp(a, dt, dmmap, L, M, n_iter, z0, z1, g_out, block=0, halo=0
     for m in range(m1 - 1, m0 - 1, -1):
         s = span_of_long_step(dmmap, L, m)
         if every and (m + 1) % every == 0:
-            g = g * math.exp(dmmap.gamma * dmmap.z_amp)
+            g = g * lumped_gain(dmmap)
         g, ds, d2, d3 = mpa_blocked_long_step_vjp(
             inputs[m - m0], dt, block or len(a), halo, dmmap.beta2[s], dmmap.beta3[s],
-            dmmap.sigma[s], dmmap.gamma, L, M, n_iter, g)
+            dmmap.sigma[s], dmmap.gamma, L, M, n_iter, g, int_g=long_step_gain(dmmap, L, M, m))
         g_sigma[s] += ds
         g_beta2[s] += d2
         g_beta3[s] += d3

@@ -77,18 +77,20 @@ def rel_l2(a: np.ndarray, ref: np.ndarray) -> float:
 
 def mpa_long_step(a_z0: np.ndarray, omega: np.ndarray, beta2: float, beta3: float,
                   sigma: float, gamma: float, L: float, M: int, n_iter: int,
-                  return_iterates: bool = False, out_mask=None):
+                  return_iterates: bool = False, out_mask=None, int_g=None):
     """Advance A(t, z0) to A(t, z0 + L) by n_iter Picard sweeps of the
     discretised integral equation, Eq. 6, in the order of MPA steps 1-7.
 
     Nodes z_j = z0 + j dz, dz = L/M, j = 0..M.  The Jacobi form of the paper
     is kept: every sweep evaluates all nodes from the previous sweep's
-    psi^(n)_j, then the trapezoid sums are formed for every l.
+    psi^(n)_j, then the trapezoid sums are formed for every l.  ``int_g``
+    (M + 1 values of int_{z0}^{z_j} G) replaces -gamma (z_j - z0) when G
+    is not constant (distributed gain, :func:`gain_integral`).
     """
     dz = L / M
     zj = dz * np.arange(M + 1)                                    # z_j - z0
     beta = np.outer(zj, omega ** 2 / 2.0 * beta2 + omega ** 3 / 6.0 * beta3)
-    int_g = -gamma * zj                                           # int_{z0}^{z_j} G
+    int_g = -gamma * zj if int_g is None else np.asarray(int_g, dtype=float)   # int_{z0}^{z_j} G
     to_a = np.exp(1j * beta + int_g[:, None])                     # e^{+i beta + int G}
     to_psi = np.exp(-1j * beta - int_g[:, None])                  # e^{-i beta - int G}
 
@@ -230,7 +232,7 @@ def block_mask(omega_b: np.ndarray, beta2: float, beta3: float, L: float, halo: 
 
 def mpa_blocked_long_step(a_z0: np.ndarray, dt: float, block: int, halo: int,
                           beta2: float, beta3: float, sigma: float, gamma: float,
-                          L: float, M: int, n_iter: int) -> np.ndarray:
+                          L: float, M: int, n_iter: int, int_g=None) -> np.ndarray:
     """One MPA long step run independently on every periodic block window
     (frequency grid of the block: omega^B = 2 pi fftfreq(block, dt)), keeping
     each block's core.  Each window is multiplied by :func:`block_taper`
@@ -238,7 +240,7 @@ def mpa_blocked_long_step(a_z0: np.ndarray, dt: float, block: int, halo: int,
     n = a_z0.shape[0]
     if block == 0 or (block == n and halo == 0):
         return mpa_long_step(a_z0, omega_grid(n, dt), beta2, beta3, sigma, gamma,
-                             L, M, n_iter)
+                             L, M, n_iter, int_g=int_g)
     omega_b = omega_grid(block, dt)
     taper = block_taper(block, halo)
     mask = block_mask(omega_b, beta2, beta3, L, halo, dt) if halo > 0 else None
@@ -246,7 +248,7 @@ def mpa_blocked_long_step(a_z0: np.ndarray, dt: float, block: int, halo: int,
     for w0, c0, clen in block_partition(n, block, halo):
         idx = (w0 + np.arange(block)) % n
         res = mpa_long_step(a_z0[idx] * taper, omega_b, beta2, beta3, sigma, gamma,
-                            L, M, n_iter, out_mask=mask)
+                            L, M, n_iter, out_mask=mask, int_g=int_g)
         out[c0:c0 + clen] = res[halo:halo + clen]
     return out
 
@@ -285,17 +287,60 @@ def _amp_every(dmmap, h: float) -> int:
     return _steps_per(dmmap.z_amp, h, "amplifier spacing")
 
 
+def _raman(dmmap):
+    g0 = float(getattr(dmmap, "raman_g0", 0.0) or 0.0)
+    return g0, float(getattr(dmmap, "raman_alpha", 0.0) or 0.0)
+
+
+def gain_integral(dmmap, zeta0: float, h) -> np.ndarray:
+    """int_{z0}^{z0 + h} G(z) dz for a start z0 whose position inside its
+    amplifier period is zeta0 (0 <= zeta0 < z_a), for offsets h >= 0 that stay
+    inside that period.
+
+    G(z) = -gamma + g(z) (Eq. 1 allows any G): the loss plus an optional
+    distributed, backward-pumped gain rising towards each amplifier,
+    g = g0 exp(-alpha (z_a - zeta)) at position zeta of the amplifier period,
+    whose integral is (g0 / alpha) (exp(-alpha (z_a - zeta0 - h)) -
+    exp(-alpha (z_a - zeta0)))."""
+    h = np.asarray(h, dtype=float)
+    out = -dmmap.gamma * h
+    g0, alpha = _raman(dmmap)
+    if g0 > 0:
+        za = dmmap.z_amp
+        out = out + (g0 / alpha) * (np.exp(-alpha * (za - zeta0 - h)) - np.exp(-alpha * (za - zeta0)))
+    return out
+
+
+def lumped_gain(dmmap) -> float:
+    """Amplitude factor of a lumped amplifier: it makes up what the span
+    loss and the distributed gain leave over one amplifier period,
+    exp(gamma z_a - int_0^{z_a} g), so that the link is transparent."""
+    g0, alpha = _raman(dmmap)
+    dist = (g0 / alpha) * (1.0 - math.exp(-alpha * dmmap.z_amp)) if g0 > 0 else 0.0
+    return math.exp(dmmap.gamma * dmmap.z_amp - dist)
+
+
+def long_step_gain(dmmap, L: float, M: int, m: int):
+    """int_{mL}^{mL + j dz} G for j = 0..M (None when G = -gamma throughout)."""
+    g0, _ = _raman(dmmap)
+    if g0 <= 0:
+        return None
+    every = _amp_every(dmmap, L)
+    zeta0 = (m % every) * L
+    return gain_integral(dmmap, zeta0, (L / M) * np.arange(M + 1))
+
+
 def mpa_step(a: np.ndarray, dt: float, dmmap, L: float, M: int, n_iter: int,
              m: int, block: int = 0, halo: int = 0) -> np.ndarray:
-    """Long step m ([m L, (m+1) L]), then the lumped gain exp(gamma z_a) if an
-    amplifier sits at (m+1) L."""
+    """Long step m ([m L, (m+1) L]), then the lumped gain if an amplifier
+    sits at (m+1) L (exp(gamma z_a) without distributed gain)."""
     s = span_of_long_step(dmmap, L, m)
     out = mpa_blocked_long_step(a, dt, block or a.shape[0], halo, dmmap.beta2[s],
                                 dmmap.beta3[s], dmmap.sigma[s], dmmap.gamma,
-                                L, M, n_iter)
+                                L, M, n_iter, int_g=long_step_gain(dmmap, L, M, m))
     every = _amp_every(dmmap, L)
     if every and (m + 1) % every == 0:
-        out = out * math.exp(dmmap.gamma * dmmap.z_amp)
+        out = out * lumped_gain(dmmap)
     return out
 
 

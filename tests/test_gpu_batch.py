@@ -116,3 +116,26 @@ def test_autotuner_picks_a_valid_plan():
     plan = P.MPAPlan(n, DT, dmm, best.L, best.M, 2, best.block, best.halo, P.MPA_C64, BAND)
     plan.propagate(x, 0.0, 2 * best.L)
     plan.close()
+
+
+def test_picard_sweeps_chosen_from_the_residual():
+    """choose_n_iter: the returned sweep count is the smallest within tol of
+    the 5-sweep result; the distances shrink with every sweep until FP64
+    rounding; a field 16 times more powerful (nonlinear length 16 times
+    shorter) is farther from the fixed point after the same sweeps (the
+    floor (L / z_nl)^(n+1)) and never needs fewer sweeps."""
+    from paper_1101_0086_amd.autotune import choose_n_iter
+    n = 1 << 15
+    a = _fast_wdm_field(Grid(n, DT), 32, 8, "ook", np.random.default_rng(42))
+    dmm = dm_map(beta3=0.1)
+    picks, dists = [], []
+    for amp in (1.0, 4.0):
+        say("choose_n_iter", amp)
+        x = to_dev(amp * a, 1)
+        nit, dist = choose_n_iter(x, DT, dmm, 2.5e-4, 2, 4096, 512, BAND, precision=1, tol=1e-12, steps=40)
+        assert dist[nit] <= 1e-12 and all(dist[k] > 1e-12 for k in dist if k < nit)
+        assert all(dist[k + 1] < dist[k] for k in range(1, 4) if dist[k + 1] > 1e-13)
+        picks.append(nit)
+        dists.append(dist)
+    assert picks[1] >= picks[0]
+    assert dists[1][1] > 10 * dists[0][1]

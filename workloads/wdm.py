@@ -38,7 +38,9 @@ class DMMap:
 
     ``seg_len[i]``, ``beta2[i]``, ``beta3[i]``, ``sigma[i]`` hold span ``i``;
     ``gamma`` is the amplitude loss rate and ``z_amp`` the amplifier spacing
-    (0 disables amplifiers).  The period is ``sum(seg_len)``.
+    (0 disables amplifiers); ``raman_g0``, ``raman_alpha`` add a distributed
+    gain g0 exp(-alpha (z_a - zeta)) at position zeta of each amplifier
+    period.  The period is ``sum(seg_len)``.
     """
     seg_len: tuple
     beta2: tuple
@@ -46,6 +48,8 @@ class DMMap:
     sigma: tuple
     gamma: float = 0.0
     z_amp: float = 0.0
+    raman_g0: float = 0.0       # distributed gain g0 exp(-alpha (z_a - zeta)) (0: none)
+    raman_alpha: float = 0.0
 
     @property
     def period(self) -> float:
