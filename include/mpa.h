@@ -103,9 +103,18 @@ typedef struct {
     const double* beta3;     /* third-order dispersion beta3 per span             */
     const double* sigma;     /* nonlinear coefficient per span                    */
     double gamma;            /* amplitude loss rate, G = -gamma (>= 0)            */
-    double z_amp;            /* amplifier spacing z_a (0: no amplifiers); gain
-                                exp(gamma z_a) is applied at z = k z_a           */
+    double z_amp;            /* amplifier spacing z_a (0: no amplifiers)       */
+    double raman_g0;         /* distributed gain (0: none; needs z_amp > 0):   */
+    double raman_alpha;      /* G = -gamma + g0 exp(-alpha (z_a - zeta)) at
+                                position zeta of each amplifier period (a
+                                backward-pumped profile; Eq. 1 allows any G)    */
 } mpa_map;
+/* The lumped amplifier at z = k z_a multiplies A by
+ *   exp(gamma z_a - (g0 / alpha) (1 - exp(-alpha z_a))),
+ * what loss and distributed gain leave over one amplifier period (exp(gamma
+ * z_a) without distributed gain), so that every amplifier period is
+ * transparent.  MPA plans take the distributed gain into int G at every
+ * node; split-step plans reject it (MPA_EUNSUPPORTED).                      */
 
 /* MPA plan parameters. */
 typedef struct {

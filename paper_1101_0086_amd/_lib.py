@@ -37,7 +37,8 @@ EXPORTED = ("mpa_plan_create", "mpa_plan_destroy", "mpa_plan_get_info", "mpa_pla
 class mpa_map(C.Structure):
     _fields_ = [("n_seg", C.c_int32), ("seg_len", C.POINTER(C.c_double)),
                 ("beta2", C.POINTER(C.c_double)), ("beta3", C.POINTER(C.c_double)),
-                ("sigma", C.POINTER(C.c_double)), ("gamma", C.c_double), ("z_amp", C.c_double)]
+                ("sigma", C.POINTER(C.c_double)), ("gamma", C.c_double), ("z_amp", C.c_double),
+                ("raman_g0", C.c_double), ("raman_alpha", C.c_double)]
 
 
 class mpa_params(C.Structure):
@@ -126,7 +127,8 @@ class MapStruct:
         arr = C.c_double * n
         self._a = [arr(*map(float, getattr(dmmap, f))) for f in ("seg_len", "beta2", "beta3", "sigma")]
         self.s = mpa_map(n, self._a[0], self._a[1], self._a[2], self._a[3],
-                         float(dmmap.gamma), float(dmmap.z_amp))
+                         float(dmmap.gamma), float(dmmap.z_amp),
+                         float(getattr(dmmap, "raman_g0", 0.0)), float(getattr(dmmap, "raman_alpha", 0.0)))
 
 
 def make_params(n, dt, L, M, n_iter, block=0, halo=0, precision=MPA_C64, omega_band=0.0,

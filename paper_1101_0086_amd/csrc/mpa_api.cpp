@@ -59,6 +59,10 @@ int validate_map(const mpa_map* map) {
     }
     if (!(map->gamma >= 0) || !is_finite(map->gamma)) return fail(MPA_EINVAL, "gamma must be finite and >= 0");
     if (!(map->z_amp >= 0) || !is_finite(map->z_amp)) return fail(MPA_EINVAL, "z_amp must be finite and >= 0");
+    if (!(map->raman_g0 >= 0) || !is_finite(map->raman_g0) || !is_finite(map->raman_alpha))
+        return fail(MPA_EINVAL, "raman_g0 must be finite and >= 0, raman_alpha finite");
+    if (map->raman_g0 > 0 && (!(map->raman_alpha > 0) || !(map->z_amp > 0)))
+        return fail(MPA_EINVAL, "distributed gain needs raman_alpha > 0 and z_amp > 0");
     return MPA_OK;
 }
 
@@ -127,7 +131,12 @@ struct mpa_plan {
     int block = 0, halo = 0, core = 0, n_blocks = 0;
     size_t elem = 8;                    // bytes per complex sample
     std::vector<double> beta2, beta3, sigma;
-    double gamma = 0, z_amp = 0;
+    double gamma = 0, z_amp = 0, raman_g0 = 0, raman_alpha = 0;
+    // node scalars: one row per span, or one per long step of an amplifier
+    // period with distributed gain (int G then depends on the position)
+    bool gain_rows = false;
+    std::vector<double> row_out;        // e^{Gamma_M} of every row
+    double lumped = 1.0;                // amplitude factor of a lumped amplifier
     Schedule sched;
     void* phase = nullptr;              // n_seg x (M+1) x B complex (plan precision)
     void* phase_last = nullptr;         // n_seg x B FP64 complex: node M (reconstruction)
@@ -241,12 +250,21 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
     p->sigma.assign(map->sigma, map->sigma + map->n_seg);
     p->gamma = map->gamma;
     p->z_amp = map->z_amp;
+    p->raman_g0 = map->raman_g0;
+    p->raman_alpha = map->raman_alpha;
+    p->gain_rows = map->raman_g0 > 0;
+    {
+        const double dist = p->gain_rows ? map->raman_g0 / map->raman_alpha * (1.0 - std::exp(-map->raman_alpha * map->z_amp))
+                                         : 0.0;
+        p->lumped = std::exp(map->gamma * map->z_amp - dist);
+    }
+    const int NSR = p->gain_rows ? (int)sched.amp_steps : map->n_seg;   // node-scale rows
 
     const int B = p->block, M = params->M, S = map->n_seg;
     const bool f32 = params->precision == MPA_C64;
     const size_t rsz = f32 ? 4 : 8;
     const size_t phase_bytes = (size_t)S * (M + 1) * B * p->elem;
-    const size_t ns_bytes = (size_t)S * 2 * (M + 1) * rsz;
+    const size_t ns_bytes = (size_t)NSR * 2 * (M + 1) * rsz;
     const size_t last_bytes = (size_t)S * B * 16;
     const size_t tw_bytes = (size_t)B * p->elem;
     const size_t tw64_bytes = (size_t)B * 16;
@@ -274,14 +292,23 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
             coef[(size_t)s * (M + 1) + j] = pi * p->beta2[s] * z / (bdt * bdt);
             coef[rows + (size_t)s * (M + 1) + j] = (2.0 * pi * pi / 3.0) * p->beta3[s] * z / (bdt * bdt * bdt);
         }
-    // node scalars: c_j = e^{Gamma_j} / B, e_j = dz e^{-Gamma_j}, Gamma_j = -gamma j dz
-    // (sigma multiplies e_j in the kernel, so batches can scale it per instance)
-    std::vector<double> ns((size_t)S * 2 * (M + 1));
-    for (int s = 0; s < S; ++s)
+    // node scalars: c_j = e^{Gamma_j} / B, e_j = dz e^{-Gamma_j}, Gamma_j = int_{z0}^{z0 + j dz} G
+    // (sigma multiplies e_j in the kernel, so batches can scale it per instance).  G = -gamma
+    // gives the same row for every span; with distributed gain row r is the long step starting
+    // at zeta0 = r L inside the amplifier period:
+    //   Gamma_j = -gamma j dz + (g0 / alpha) (exp(-alpha (z_a - zeta0 - j dz)) - exp(-alpha (z_a - zeta0)))
+    std::vector<double> ns((size_t)NSR * 2 * (M + 1));
+    p->row_out.assign(NSR, 1.0);
+    for (int r = 0; r < NSR; ++r)
         for (int j = 0; j <= M; ++j) {
-            const double g = -p->gamma * j * dz;
-            ns[(size_t)s * 2 * (M + 1) + 2 * j] = std::exp(g) / B;
-            ns[(size_t)s * 2 * (M + 1) + 2 * j + 1] = dz * std::exp(-g);
+            double g = -p->gamma * j * dz;
+            if (p->gain_rows) {
+                const double zeta0 = r * params->L, a = p->raman_alpha;
+                g += p->raman_g0 / a * (std::exp(-a * (p->z_amp - zeta0 - j * dz)) - std::exp(-a * (p->z_amp - zeta0)));
+            }
+            ns[(size_t)r * 2 * (M + 1) + 2 * j] = std::exp(g) / B;
+            ns[(size_t)r * 2 * (M + 1) + 2 * j + 1] = dz * std::exp(-g);
+            if (j == M) p->row_out[r] = std::exp(g);
         }
     // twiddles exp(+2 pi i j / B) and the erf taper over the outer halo/2 samples
     std::vector<double> tw(2 * (size_t)B), tp((size_t)B, 1.0);
@@ -372,11 +399,19 @@ int mpa_plan_get_info(const mpa_plan* p, mpa_plan_info* info) {
     return MPA_OK;
 }
 
+// Row of the node-scale table for long step m in span s.
+static int gain_row(const mpa_plan* p, int64_t m, int s) {
+    if (!p->gain_rows) return s;
+    int64_t r = m % p->sched.amp_steps;
+    if (r < 0) r += p->sched.amp_steps;
+    return (int)r;
+}
+
 static int launch_long_step(mpa_plan* p, const void* in, void* out, int64_t m, hipStream_t stream,
                             const mpa::BatchItems* batch = nullptr) {
     const int s = p->sched.span_of(m);
     const int M = p->prm.M;
-    const double gain = p->sched.amp_after(m) ? std::exp(p->gamma * p->z_amp) : 1.0;
+    const double gain = p->sched.amp_after(m) ? p->lumped : 1.0;
     mpa::BlockStepArgs a;
     a.in = in;
     a.out = out;
@@ -388,13 +423,13 @@ static int launch_long_step(mpa_plan* p, const void* in, void* out, int64_t m, h
     a.phase = (const char*)p->phase + (size_t)s * (M + 1) * p->block * p->elem;
     a.phase_last = (const char*)p->phase_last + (size_t)s * p->block * 16;
     a.twiddle64 = p->twiddle64;
-    a.node_scale = (const char*)p->node_scale + (size_t)s * 2 * (M + 1) * (p->elem / 2);
+    a.node_scale = (const char*)p->node_scale + (size_t)gain_row(p, m, s) * 2 * (M + 1) * (p->elem / 2);
     a.twiddle = p->twiddle;
     a.taper = p->taper;
     a.M = M;
     a.n_iter = p->prm.n_iter;
     a.sigma = p->sigma[s];
-    a.out_scale = std::exp(-p->gamma * p->prm.L) / p->block * gain;
+    a.out_scale = p->row_out[gain_row(p, m, s)] / p->block * gain;
     a.precision = p->prm.precision;
     a.batch = batch;
     a.nodes = (batch == nullptr && p->nodes.psi0) ? &p->nodes : nullptr;
@@ -548,7 +583,7 @@ static int adjoint_long_step(mpa_plan* p, const void* in, const void* g_out, voi
                              double* param_grad, hipStream_t stream) {
     const int s = p->sched.span_of(m);
     const int M = p->prm.M;
-    const double gain = p->sched.amp_after(m) ? std::exp(p->gamma * p->z_amp) : 1.0;
+    const double gain = p->sched.amp_after(m) ? p->lumped : 1.0;
     mpa::AdjointStepArgs a;
     a.in = in;
     a.g_out = g_out;
@@ -563,7 +598,7 @@ static int adjoint_long_step(mpa_plan* p, const void* in, const void* g_out, voi
     a.n_blocks = p->n_blocks;
     a.phase = (const char*)p->phase + (size_t)s * (M + 1) * p->block * p->elem;
     a.phase_last = (const char*)p->phase_last + (size_t)s * p->block * 16;
-    a.node_scale = (const char*)p->node_scale + (size_t)s * 2 * (M + 1) * (p->elem / 2);
+    a.node_scale = (const char*)p->node_scale + (size_t)gain_row(p, m, s) * 2 * (M + 1) * (p->elem / 2);
     a.twiddle = p->twiddle;
     a.twiddle64 = p->twiddle64;
     a.taper = p->taper;
@@ -571,7 +606,7 @@ static int adjoint_long_step(mpa_plan* p, const void* in, const void* g_out, voi
     a.M = M;
     a.n_iter = p->prm.n_iter;
     a.sigma = p->sigma[s];
-    a.out_scale = std::exp(-p->gamma * p->prm.L) / p->block * gain;
+    a.out_scale = p->row_out[gain_row(p, m, s)] / p->block * gain;
     a.w1 = 2.0 * 3.14159265358979323846 / (p->block * p->prm.dt);
     a.dz = p->prm.L / M;
     a.precision = p->prm.precision;

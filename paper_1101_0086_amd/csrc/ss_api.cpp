@@ -90,6 +90,7 @@ int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz, int32_t 
     *out = nullptr;
     int st = validate_map_c(map);
     if (st) return st;
+    if (map->raman_g0 > 0) return fail_status(MPA_EUNSUPPORTED, "split-step plans do not model distributed gain");
     if (n < 64 || (n & (n - 1)) != 0 || n > (int64_t(1) << 30))
         return fail_status(MPA_EINVAL, "n must be a power of two in [64, 2^30]");
     if (!(dt > 0) || !std::isfinite(dt) || !(dz > 0) || !std::isfinite(dz))

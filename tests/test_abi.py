@@ -63,6 +63,14 @@ def test_validation_status_codes():
     assert _validate(halo=64) == L.MPA_EHALO
     assert _validate(block=1 << 14, halo=2048) == L.MPA_EUNSUPPORTED
     assert _validate(dmmap=dm_map(beta3=0.1, z_amp=1.0 / 3.0)) == L.MPA_EALIGN
+    # distributed gain: needs a positive profile rate and amplifiers
+    from workloads.wdm import DMMap
+    base_map = dm_map(beta3=0.1)
+    raman = lambda **kw: DMMap(**{**base_map.__dict__, **kw})
+    assert _validate(dmmap=raman(raman_g0=0.2, raman_alpha=3.0)) == L.MPA_OK
+    assert _validate(dmmap=raman(raman_g0=0.2, raman_alpha=0.0)) == L.MPA_EINVAL
+    assert _validate(dmmap=raman(raman_g0=0.2, raman_alpha=3.0, z_amp=0.0)) == L.MPA_EINVAL
+    assert _validate(dmmap=raman(raman_g0=-0.1, raman_alpha=3.0)) == L.MPA_EINVAL
     # a full-window plan needs no halo rule
     assert _validate(n=4096, block=0, halo=0, L=0.05) == L.MPA_OK
     assert _validate(n=4096, block=4096, halo=0, L=0.05) == L.MPA_OK
