@@ -77,7 +77,8 @@ def rel_l2(a: np.ndarray, ref: np.ndarray) -> float:
 
 def mpa_long_step(a_z0: np.ndarray, omega: np.ndarray, beta2: float, beta3: float,
                   sigma: float, gamma: float, L: float, M: int, n_iter: int,
-                  return_iterates: bool = False, out_mask=None, int_g=None):
+                  return_iterates: bool = False, out_mask=None, int_g=None,
+                  node_beta=None, node_sigma=None):
     """Advance A(t, z0) to A(t, z0 + L) by n_iter Picard sweeps of the
     discretised integral equation, Eq. 6, in the order of MPA steps 1-7.
 
@@ -85,11 +86,19 @@ def mpa_long_step(a_z0: np.ndarray, omega: np.ndarray, beta2: float, beta3: floa
     is kept: every sweep evaluates all nodes from the previous sweep's
     psi^(n)_j, then the trapezoid sums are formed for every l.  ``int_g``
     (M + 1 values of int_{z0}^{z_j} G) replaces -gamma (z_j - z0) when G
-    is not constant (distributed gain, :func:`gain_integral`).
+    is not constant (distributed gain, :func:`gain_integral`).  When the
+    long step crosses a span boundary, ``node_beta`` = (int_{z0}^{z_j} beta2,
+    int_{z0}^{z_j} beta3) for j = 0..M replaces (beta2, beta3) (z_j - z0)
+    in beta(omega, z_j), and ``node_sigma`` (M + 1 values) replaces sigma at
+    the nodes (:func:`step_coefficients`).
     """
     dz = L / M
     zj = dz * np.arange(M + 1)                                    # z_j - z0
-    beta = np.outer(zj, omega ** 2 / 2.0 * beta2 + omega ** 3 / 6.0 * beta3)
+    if node_beta is None:
+        beta = np.outer(zj, omega ** 2 / 2.0 * beta2 + omega ** 3 / 6.0 * beta3)
+    else:
+        beta = (np.outer(node_beta[0], omega ** 2 / 2.0) + np.outer(node_beta[1], omega ** 3 / 6.0))
+    sig = sigma if node_sigma is None else np.asarray(node_sigma, dtype=float)[:, None]
     int_g = -gamma * zj if int_g is None else np.asarray(int_g, dtype=float)   # int_{z0}^{z_j} G
     to_a = np.exp(1j * beta + int_g[:, None])                     # e^{+i beta + int G}
     to_psi = np.exp(-1j * beta - int_g[:, None])                  # e^{-i beta - int G}
@@ -101,7 +110,7 @@ def mpa_long_step(a_z0: np.ndarray, omega: np.ndarray, beta2: float, beta3: floa
     for _ in range(n_iter):
         a_hat = psi * to_a                                        # step 2
         a_t = paper_ifft(a_hat, axis=1)                           # step 3
-        v = sigma * paper_fft(np.abs(a_t) ** 2 * a_t, axis=1) * dz * to_psi   # step 4, V_j of Eq. 6
+        v = sig * paper_fft(np.abs(a_t) ** 2 * a_t, axis=1) * dz * to_psi     # step 4, V_j of Eq. 6
         # step 5: trapezoid rule, Eq. 6, saving the partial integral at every node:
         # psi_l = psi_0 + i (V_0/2 + sum_{j=1}^{l-1} V_j + V_l/2), l = 1..M
         csum = np.cumsum(v, axis=0)                               # sum_{j=0}^{l} V_j
@@ -232,7 +241,8 @@ def block_mask(omega_b: np.ndarray, beta2: float, beta3: float, L: float, halo: 
 
 def mpa_blocked_long_step(a_z0: np.ndarray, dt: float, block: int, halo: int,
                           beta2: float, beta3: float, sigma: float, gamma: float,
-                          L: float, M: int, n_iter: int, int_g=None) -> np.ndarray:
+                          L: float, M: int, n_iter: int, int_g=None, node_beta=None,
+                          node_sigma=None) -> np.ndarray:
     """One MPA long step run independently on every periodic block window
     (frequency grid of the block: omega^B = 2 pi fftfreq(block, dt)), keeping
     each block's core.  Each window is multiplied by :func:`block_taper`
@@ -240,15 +250,18 @@ def mpa_blocked_long_step(a_z0: np.ndarray, dt: float, block: int, halo: int,
     n = a_z0.shape[0]
     if block == 0 or (block == n and halo == 0):
         return mpa_long_step(a_z0, omega_grid(n, dt), beta2, beta3, sigma, gamma,
-                             L, M, n_iter, int_g=int_g)
+                             L, M, n_iter, int_g=int_g, node_beta=node_beta, node_sigma=node_sigma)
     omega_b = omega_grid(block, dt)
     taper = block_taper(block, halo)
+    if node_beta is not None:      # the step's group delay: integrated coefficients over L
+        beta2, beta3 = node_beta[0][-1] / L, node_beta[1][-1] / L
     mask = block_mask(omega_b, beta2, beta3, L, halo, dt) if halo > 0 else None
     out = np.empty_like(a_z0)
     for w0, c0, clen in block_partition(n, block, halo):
         idx = (w0 + np.arange(block)) % n
         res = mpa_long_step(a_z0[idx] * taper, omega_b, beta2, beta3, sigma, gamma,
-                            L, M, n_iter, out_mask=mask, int_g=int_g)
+                            L, M, n_iter, out_mask=mask, int_g=int_g, node_beta=node_beta,
+                            node_sigma=node_sigma)
         out[c0:c0 + clen] = res[halo:halo + clen]
     return out
 
@@ -279,6 +292,48 @@ def span_of_long_step(dmmap, h: float, m: int) -> int:
             return i
         r -= c
     raise AssertionError
+
+
+def long_step_spans(dmmap, L: float, m: int):
+    """Spans overlapped by long step m ([mL, (m+1)L]) when L divides the map
+    period but not necessarily every span."""
+    period = float(sum(dmmap.seg_len))
+    steps = _steps_per(period, L, "map period")
+    z0 = (m % steps) * L
+    bounds = np.concatenate([[0.0], np.cumsum(dmmap.seg_len)])
+    eps = 1e-12 * period
+    return [i for i in range(len(dmmap.seg_len))
+            if bounds[i] < z0 + L - eps and bounds[i + 1] > z0 + eps]
+
+
+def step_coefficients(dmmap, L: float, M: int, m: int):
+    """For long step m: int_{z0}^{z_j} beta2 and beta3 (exact integrals of the
+    piecewise-constant map) and sigma at the nodes z_j, j = 0..M.  A node on a
+    span boundary takes the mean of the two spans' sigma: the trapezoid rule
+    then equals the trapezoid rule applied on each side of the boundary."""
+    period = float(sum(dmmap.seg_len))
+    steps = _steps_per(period, L, "map period")
+    z0 = (m % steps) * L
+    zj = z0 + (L / M) * np.arange(M + 1)
+    bounds = np.concatenate([[0.0], np.cumsum(dmmap.seg_len)])
+    b2 = np.zeros(M + 1)
+    b3 = np.zeros(M + 1)
+    for i in range(len(dmmap.seg_len)):
+        lo, hi = bounds[i], bounds[i + 1]
+        seg = np.clip(zj, lo, hi) - np.clip(z0, lo, hi)         # length of [z0, z_j] inside span i
+        b2 += dmmap.beta2[i] * seg
+        b3 += dmmap.beta3[i] * seg
+    eps = 1e-12 * period
+    nseg = len(dmmap.seg_len)
+    sig = np.empty(M + 1)
+    for j, z in enumerate(zj):
+        k = int(np.argmin(np.abs(bounds - z)))
+        if abs(bounds[k] - z) <= eps:                          # on a boundary (periodic map)
+            left, right = (k - 1) % nseg, k % nseg
+            sig[j] = 0.5 * (dmmap.sigma[left] + dmmap.sigma[right])
+        else:
+            sig[j] = dmmap.sigma[int(np.searchsorted(bounds, z, side="right")) - 1]
+    return (b2, b3), sig
 
 
 def _amp_every(dmmap, h: float) -> int:
@@ -334,10 +389,18 @@ def mpa_step(a: np.ndarray, dt: float, dmmap, L: float, M: int, n_iter: int,
              m: int, block: int = 0, halo: int = 0) -> np.ndarray:
     """Long step m ([m L, (m+1) L]), then the lumped gain if an amplifier
     sits at (m+1) L (exp(gamma z_a) without distributed gain)."""
-    s = span_of_long_step(dmmap, L, m)
-    out = mpa_blocked_long_step(a, dt, block or a.shape[0], halo, dmmap.beta2[s],
-                                dmmap.beta3[s], dmmap.sigma[s], dmmap.gamma,
-                                L, M, n_iter, int_g=long_step_gain(dmmap, L, M, m))
+    spans = long_step_spans(dmmap, L, m)
+    if len(spans) == 1:
+        s = spans[0]
+        out = mpa_blocked_long_step(a, dt, block or a.shape[0], halo, dmmap.beta2[s],
+                                    dmmap.beta3[s], dmmap.sigma[s], dmmap.gamma,
+                                    L, M, n_iter, int_g=long_step_gain(dmmap, L, M, m))
+    else:
+        # the step crosses a span boundary: exact beta integrals, sigma sampled at the nodes
+        node_beta, node_sigma = step_coefficients(dmmap, L, M, m)
+        out = mpa_blocked_long_step(a, dt, block or a.shape[0], halo, 0.0, 0.0, 0.0, dmmap.gamma,
+                                    L, M, n_iter, int_g=long_step_gain(dmmap, L, M, m),
+                                    node_beta=node_beta, node_sigma=node_sigma)
     every = _amp_every(dmmap, L)
     if every and (m + 1) % every == 0:
         out = out * lumped_gain(dmmap)
