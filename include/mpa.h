@@ -120,7 +120,14 @@ typedef struct {
 typedef struct {
     int64_t n;             /* modes N: power of two                              */
     double dt;             /* sample spacing (> 0)                               */
-    double L;              /* long step; must divide every span and z_amp        */
+    double L;              /* long step; must divide the map period and z_amp.
+                              A step that crosses a span boundary (L need not
+                              divide the spans) takes beta(omega, z_j) as the
+                              exact integral of the piecewise-constant beta2,
+                              beta3 and sigma sampled at the nodes (the mean of
+                              both spans on a node that lies on a boundary);
+                              such plans have no reverse pass and cannot be
+                              combined with distributed gain (MPA_EUNSUPPORTED) */
     int32_t M;             /* quadrature intervals per long step (>= 1)          */
     int32_t n_iter;        /* Picard sweeps per long step (1..5)                 */
     int32_t block;         /* B: power of two <= N; 0 (or N with halo 0) for one

@@ -66,14 +66,28 @@ int validate_map(const mpa_map* map) {
     return MPA_OK;
 }
 
-// Span schedule on a step grid h: steps per span and per amplifier.
+// Span schedule on a step grid h: steps per span and per amplifier.  When h
+// divides the map period but not every span (MPA plans only), some steps
+// cross a span boundary; each such step of the period gets a table of its
+// own, numbered n_seg, n_seg + 1, ... (`table_of_step`, one entry per step of
+// the period), with the exact integrals of beta2 and beta3 from the step's
+// start to each node and sigma sampled at the nodes (the mean of the two
+// spans on a node that lies on a boundary).
+struct Straddle {
+    int64_t step;                      // step index within the period
+    std::vector<double> b2, b3, sig;   // per node j = 0..M (filled at plan creation)
+};
+
 struct Schedule {
-    std::vector<int64_t> span_steps;   // steps in each span
+    std::vector<int64_t> span_steps;   // steps in each span (aligned case)
     int64_t period_steps = 0;
     int64_t amp_steps = 0;             // 0: no amplifiers
+    std::vector<int32_t> table_of_step;  // non-empty when some step crosses a boundary
+    std::vector<Straddle> straddles;
     int span_of(int64_t m) const {
         int64_t r = m % period_steps;
         if (r < 0) r += period_steps;
+        if (!table_of_step.empty()) return table_of_step[(size_t)r];
         for (size_t i = 0; i < span_steps.size(); ++i) {
             if (r < span_steps[i]) return (int)i;
             r -= span_steps[i];
@@ -83,15 +97,48 @@ struct Schedule {
     bool amp_after(int64_t m) const { return amp_steps > 0 && ((m + 1) % amp_steps) == 0; }
 };
 
-int make_schedule(const mpa_map* map, double h, const char* what, Schedule* s) {
+int make_schedule(const mpa_map* map, double h, const char* what, Schedule* s, bool allow_straddle = false) {
     s->span_steps.clear();
+    s->table_of_step.clear();
+    s->straddles.clear();
     s->period_steps = 0;
+    bool aligned = true;
     for (int i = 0; i < map->n_seg; ++i) {
         const int64_t k = steps_per(map->seg_len[i], h);
-        if (k < 0) return fail(MPA_EALIGN, "%s %g does not divide span %d of length %g", what, h, i,
-                               map->seg_len[i]);
+        if (k < 0) {
+            if (!allow_straddle)
+                return fail(MPA_EALIGN, "%s %g does not divide span %d of length %g", what, h, i, map->seg_len[i]);
+            aligned = false;
+        }
         s->span_steps.push_back(k);
         s->period_steps += k;
+    }
+    if (!aligned) {
+        double period = 0;
+        for (int i = 0; i < map->n_seg; ++i) period += map->seg_len[i];
+        const int64_t P = steps_per(period, h);
+        if (P < 0) return fail(MPA_EALIGN, "%s %g does not divide the map period %g", what, h, period);
+        if (P > (int64_t(1) << 26)) return fail(MPA_EINVAL, "%lld steps per map period", (long long)P);
+        s->period_steps = P;
+        std::vector<double> bnd(map->n_seg + 1, 0.0);
+        for (int i = 0; i < map->n_seg; ++i) bnd[i + 1] = bnd[i] + map->seg_len[i];
+        const double eps = 1e-12 * period;
+        s->table_of_step.assign((size_t)P, 0);
+        for (int64_t r = 0; r < P; ++r) {
+            const double z0 = r * h;
+            int first = -1, count = 0;
+            for (int i = 0; i < map->n_seg; ++i)
+                if (bnd[i] < z0 + h - eps && bnd[i + 1] > z0 + eps) {
+                    if (first < 0) first = i;
+                    ++count;
+                }
+            if (count <= 1) {
+                s->table_of_step[(size_t)r] = first < 0 ? 0 : first;
+            } else {
+                s->table_of_step[(size_t)r] = map->n_seg + (int32_t)s->straddles.size();
+                s->straddles.push_back(Straddle{r, {}, {}, {}});
+            }
+        }
     }
     s->amp_steps = 0;
     if (map->z_amp > 0) {
@@ -101,6 +148,37 @@ int make_schedule(const mpa_map* map, double h, const char* what, Schedule* s) {
         s->amp_steps = k;
     }
     return MPA_OK;
+}
+
+// Node coefficients of a boundary-crossing step (see Straddle).
+void fill_straddle(const mpa_map* map, double h, int M, Straddle* st) {
+    double period = 0;
+    for (int i = 0; i < map->n_seg; ++i) period += map->seg_len[i];
+    std::vector<double> bnd(map->n_seg + 1, 0.0);
+    for (int i = 0; i < map->n_seg; ++i) bnd[i + 1] = bnd[i] + map->seg_len[i];
+    const double eps = 1e-12 * period, z0 = st->step * h, dz = h / M;
+    st->b2.assign(M + 1, 0.0);
+    st->b3.assign(M + 1, 0.0);
+    st->sig.assign(M + 1, 0.0);
+    for (int j = 0; j <= M; ++j) {
+        const double zj = z0 + j * dz;
+        for (int i = 0; i < map->n_seg; ++i) {
+            const double len = std::fmin(std::fmax(zj, bnd[i]), bnd[i + 1]) - std::fmin(std::fmax(z0, bnd[i]), bnd[i + 1]);
+            st->b2[j] += map->beta2[i] * len;
+            st->b3[j] += map->beta3[i] * len;
+        }
+        int on = -1;
+        for (int k = 0; k <= map->n_seg; ++k)
+            if (std::fabs(bnd[k] - zj) <= eps) on = k;
+        if (on >= 0) {
+            const int left = (on - 1 + map->n_seg) % map->n_seg, right = on % map->n_seg;
+            st->sig[j] = 0.5 * (map->sigma[left] + map->sigma[right]);
+        } else {
+            int i = 0;
+            while (i + 1 < map->n_seg && zj >= bnd[i + 1]) ++i;
+            st->sig[j] = map->sigma[i];
+        }
+    }
 }
 
 int check_device(int device) {
@@ -197,8 +275,10 @@ static int validate_params(const mpa_params* p, const mpa_map* map, Schedule* sc
         if (p->halo < 0 || 2 * (int64_t)p->halo >= p->block)
             return fail(MPA_EINVAL, "halo = %d must satisfy 0 <= 2 halo < block", p->halo);
     }
-    st = make_schedule(map, p->L, "long step L", sched);
+    st = make_schedule(map, p->L, "long step L", sched, true);
     if (st) return st;
+    if (!sched->straddles.empty() && map->raman_g0 > 0)
+        return fail(MPA_EUNSUPPORTED, "long steps across span boundaries with distributed gain are not supported");
     if (!full) {
         const double pi = 3.14159265358979323846;
         const double w = p->omega_band > 0 ? p->omega_band : pi / p->dt;
@@ -258,14 +338,17 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
                                          : 0.0;
         p->lumped = std::exp(map->gamma * map->z_amp - dist);
     }
-    const int NSR = p->gain_rows ? (int)sched.amp_steps : map->n_seg;   // node-scale rows
-
     const int B = p->block, M = params->M, S = map->n_seg;
+    // tables: one per span, then one per boundary-crossing step of the period
+    for (auto& st : p->sched.straddles) fill_straddle(map, params->L, M, &st);
+    const int TT = S + (int)p->sched.straddles.size();
+    const int NSR = p->gain_rows ? (int)sched.amp_steps : TT;   // node-scale rows
+
     const bool f32 = params->precision == MPA_C64;
     const size_t rsz = f32 ? 4 : 8;
-    const size_t phase_bytes = (size_t)S * (M + 1) * B * p->elem;
+    const size_t phase_bytes = (size_t)TT * (M + 1) * B * p->elem;
     const size_t ns_bytes = (size_t)NSR * 2 * (M + 1) * rsz;
-    const size_t last_bytes = (size_t)S * B * 16;
+    const size_t last_bytes = (size_t)TT * B * 16;
     const size_t tw_bytes = (size_t)B * p->elem;
     const size_t tw64_bytes = (size_t)B * 16;
     const size_t tp_bytes = (size_t)B * 8;
@@ -284,13 +367,16 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
     const double bdt = (double)B * params->dt;
     // phase coefficients in turns: beta/(2 pi) = c2 k'^2 + c3 k'^3 with
     // omega = 2 pi k' / (B dt): c2 = pi beta2 z / (B dt)^2, c3 = (2 pi^2 / 3) beta3 z / (B dt)^3
-    const int rows = S * (M + 1);
+    // (beta2 z, beta3 z) are the integrals of beta2, beta3 from the step's start to node j:
+    // beta_s (j dz) within span s, the exact piecewise integrals for a boundary-crossing step
+    const int rows = TT * (M + 1);
     std::vector<double> coef(2 * (size_t)rows);
-    for (int s = 0; s < S; ++s)
+    for (int t = 0; t < TT; ++t)
         for (int j = 0; j <= M; ++j) {
-            const double z = j * dz;
-            coef[(size_t)s * (M + 1) + j] = pi * p->beta2[s] * z / (bdt * bdt);
-            coef[rows + (size_t)s * (M + 1) + j] = (2.0 * pi * pi / 3.0) * p->beta3[s] * z / (bdt * bdt * bdt);
+            const double i2 = t < S ? p->beta2[t] * (j * dz) : p->sched.straddles[t - S].b2[j];
+            const double i3 = t < S ? p->beta3[t] * (j * dz) : p->sched.straddles[t - S].b3[j];
+            coef[(size_t)t * (M + 1) + j] = pi * i2 / (bdt * bdt);
+            coef[rows + (size_t)t * (M + 1) + j] = (2.0 * pi * pi / 3.0) * i3 / (bdt * bdt * bdt);
         }
     // node scalars: c_j = e^{Gamma_j} / B, e_j = dz e^{-Gamma_j}, Gamma_j = int_{z0}^{z0 + j dz} G
     // (sigma multiplies e_j in the kernel, so batches can scale it per instance).  G = -gamma
@@ -306,8 +392,10 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
                 const double zeta0 = r * params->L, a = p->raman_alpha;
                 g += p->raman_g0 / a * (std::exp(-a * (p->z_amp - zeta0 - j * dz)) - std::exp(-a * (p->z_amp - zeta0)));
             }
+            // a boundary-crossing step carries sigma(z_j) here (its kernel sigma is 1)
+            const double sj = (!p->gain_rows && r >= S) ? p->sched.straddles[r - S].sig[j] : 1.0;
             ns[(size_t)r * 2 * (M + 1) + 2 * j] = std::exp(g) / B;
-            ns[(size_t)r * 2 * (M + 1) + 2 * j + 1] = dz * std::exp(-g);
+            ns[(size_t)r * 2 * (M + 1) + 2 * j + 1] = sj * dz * std::exp(-g);
             if (j == M) p->row_out[r] = std::exp(g);
         }
     // twiddles exp(+2 pi i j / B) and the erf taper over the outer halo/2 samples
@@ -327,15 +415,18 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
 
     // the node-M rows again, in FP64, times the block roll-off (blocked plans):
     // g = |beta2 omega + beta3 omega^2 / 2| L / (H dt) with omega = 2 pi k' / (B dt)
-    std::vector<double> coef_last(2 * (size_t)S), mask_last(2 * (size_t)S);
-    for (int s = 0; s < S; ++s) {
-        coef_last[s] = coef[(size_t)s * (M + 1) + M];
-        coef_last[S + s] = coef[rows + (size_t)s * (M + 1) + M];
+    // (for a boundary-crossing step, beta2 L and beta3 L are the integrals over the step)
+    std::vector<double> coef_last(2 * (size_t)TT), mask_last(2 * (size_t)TT);
+    for (int t = 0; t < TT; ++t) {
+        coef_last[t] = coef[(size_t)t * (M + 1) + M];
+        coef_last[TT + t] = coef[rows + (size_t)t * (M + 1) + M];
         if (p->halo > 0) {
             const double w1 = 2.0 * pi / bdt;
-            const double hd = params->L / (p->halo * params->dt);
-            mask_last[s] = p->beta2[s] * w1 * hd;
-            mask_last[S + s] = 0.5 * p->beta3[s] * w1 * w1 * hd;
+            const double hdt = 1.0 / (p->halo * params->dt);
+            const double i2 = t < S ? p->beta2[t] * params->L : p->sched.straddles[t - S].b2[M];
+            const double i3 = t < S ? p->beta3[t] * params->L : p->sched.straddles[t - S].b3[M];
+            mask_last[t] = i2 * w1 * hdt;
+            mask_last[TT + t] = 0.5 * i3 * w1 * w1 * hdt;
         }
     }
     DevBuf dcoef, dlast, dmask;
@@ -349,7 +440,7 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
                   hipSuccess;
     if (ok) ok = mpa::launch_phase_table(p->phase, params->precision, B, rows, (const double*)dcoef.p, nullptr, 0) ==
                  hipSuccess;
-    if (ok) ok = mpa::launch_phase_table(p->phase_last, MPA_C128, B, S, (const double*)dlast.p,
+    if (ok) ok = mpa::launch_phase_table(p->phase_last, MPA_C128, B, TT, (const double*)dlast.p,
                                          p->halo > 0 ? (const double*)dmask.p : nullptr, 0) == hipSuccess;
     auto upload_real = [&](void* dst, const std::vector<double>& v) {
         if (f32) {
@@ -428,7 +519,7 @@ static int launch_long_step(mpa_plan* p, const void* in, void* out, int64_t m, h
     a.taper = p->taper;
     a.M = M;
     a.n_iter = p->prm.n_iter;
-    a.sigma = p->sigma[s];
+    a.sigma = s < (int)p->sigma.size() ? p->sigma[s] : 1.0;   // boundary-crossing steps: sigma in the table
     a.out_scale = p->row_out[gain_row(p, m, s)] / p->block * gain;
     a.precision = p->prm.precision;
     a.batch = batch;
@@ -605,7 +696,7 @@ static int adjoint_long_step(mpa_plan* p, const void* in, const void* g_out, voi
     a.mask_grad = p->adj_mask ? (const char*)p->adj_mask + (size_t)s * 2 * p->block * 16 : nullptr;
     a.M = M;
     a.n_iter = p->prm.n_iter;
-    a.sigma = p->sigma[s];
+    a.sigma = s < (int)p->sigma.size() ? p->sigma[s] : 1.0;   // boundary-crossing steps: sigma in the table
     a.out_scale = p->row_out[gain_row(p, m, s)] / p->block * gain;
     a.w1 = 2.0 * 3.14159265358979323846 / (p->block * p->prm.dt);
     a.dz = p->prm.L / M;
@@ -669,6 +760,8 @@ int mpa_propagate_checkpointed(mpa_plan* p, void* field, double z0, double z1, v
 int mpa_adjoint(mpa_plan* p, const void* checkpoints, void* grad, double z0, double z1, double* param_grad,
                 int64_t store_steps, void* stream) {
     if (!p || !grad || !param_grad) return fail(MPA_EINVAL, "NULL plan, grad or param_grad");
+    if (!p->sched.straddles.empty())
+        return fail(MPA_EUNSUPPORTED, "the reverse pass needs long steps that stay within one span");
     if (store_steps < 0) return fail(MPA_EINVAL, "store_steps must be >= 0");
     int64_t m0, m1;
     int st = grid_range(p, z0, z1, &m0, &m1);

@@ -71,6 +71,11 @@ def test_validation_status_codes():
     assert _validate(dmmap=raman(raman_g0=0.2, raman_alpha=0.0)) == L.MPA_EINVAL
     assert _validate(dmmap=raman(raman_g0=0.2, raman_alpha=3.0, z_amp=0.0)) == L.MPA_EINVAL
     assert _validate(dmmap=raman(raman_g0=-0.1, raman_alpha=3.0)) == L.MPA_EINVAL
+    # long steps may cross span boundaries when they divide the map period
+    assert _validate(n=4096, block=0, halo=0, L=1.0 / 7.0) == L.MPA_OK
+    assert _validate(n=4096, block=0, halo=0, L=0.3) == L.MPA_EALIGN
+    assert _validate(n=4096, block=0, halo=0, L=1.0 / 7.0,
+                     dmmap=raman(raman_g0=0.2, raman_alpha=3.0)) == L.MPA_EUNSUPPORTED
     # a full-window plan needs no halo rule
     assert _validate(n=4096, block=0, halo=0, L=0.05) == L.MPA_OK
     assert _validate(n=4096, block=4096, halo=0, L=0.05) == L.MPA_OK
