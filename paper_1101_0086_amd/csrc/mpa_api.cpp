@@ -226,6 +226,16 @@ struct mpa_plan {
     int64_t table_bytes = 0;
     mpa::NodeBuffers nodes{};           // node-parallel schedule state (else all NULL)
     int64_t node_bytes = 0;
+    // full window larger than one workgroup's transform (four-step path)
+    bool window = false;
+    int n1 = 0, n2 = 0, split = 0;
+    std::vector<double> ns_host;        // node-scale rows (FP64, as built)
+    void* w_tw[8] = {};                 // tw1, tw1_64, tw2, tw2_64, twl, twh, twl_64, twh_64
+    void* w_psi0 = nullptr;
+    void* w_sums = nullptr;
+    void* w_cur = nullptr;
+    void* w_work = nullptr;
+    void* w_work64 = nullptr;
     // reverse-pass workspace, allocated by the first mpa_adjoint call
     void* adj_node = nullptr;           // n_blocks x n_iter x M x 3 x B complex
     void* adj_last = nullptr;           // n_blocks x B FP64 complex
@@ -246,7 +256,10 @@ static void plan_free(mpa_plan* p) {
     (void)hipDeviceSynchronize();
     for (void* q : {p->phase, p->phase_last, p->node_scale, p->twiddle, p->twiddle64, p->taper, p->work,
                     p->adj_node, p->adj_last, p->adj_gblk, p->adj_partial, p->adj_ga, p->adj_gb, p->adj_mask,
-                    p->adj_inputs, p->adj_subs, p->nodes.psi0, p->nodes.half_u0, p->nodes.u[0], p->nodes.u[1]})
+                    p->adj_inputs, p->adj_subs, p->nodes.psi0, p->nodes.half_u0, p->nodes.u[0], p->nodes.u[1],
+                    p->w_psi0, p->w_sums, p->w_cur, p->w_work, p->w_work64})
+        if (q) (void)hipFree(q);
+    for (void* q : p->w_tw)
         if (q) (void)hipFree(q);
     delete p;
 }
@@ -292,6 +305,14 @@ static int validate_params(const mpa_params* p, const mpa_map* map, Schedule* sc
         }
     }
     const int B = full ? (int)p->n : p->block;
+    if (full && p->n > 4096) {
+        // the four-step full-window path
+        if (p->n > (int64_t(1) << 20))
+            return fail(MPA_EUNSUPPORTED, "full windows above 2^20 modes are not supported (use time blocks)");
+        if (p->schedule != MPA_WAVEFRONT)
+            return fail(MPA_EUNSUPPORTED, "full windows above 4096 modes run in node order only");
+        return MPA_OK;
+    }
     if (!mpa::block_step_supported(p->precision, B, p->n_iter))
         return fail(MPA_EUNSUPPORTED, "block size %d with n_iter %d is not compiled (512..4096)", B,
                     p->n_iter);
@@ -457,6 +478,54 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
         plan_free(p);
         return fail(MPA_EDEVICE, "plan table construction failed");
     }
+    p->ns_host = ns;
+    p->window = full && params->n > 4096;
+    if (p->window) {
+        // four-step shape N = n1 n2 (n2 >= n1), spectral-order tables, twiddles and state
+        const int64_t N = params->n;
+        int lg = 0;
+        while ((int64_t(1) << lg) < N) ++lg;
+        p->n1 = 1 << (lg / 2);
+        p->n2 = (int)(N >> (lg / 2));
+        p->split = lg / 2;
+        auto phasors = [](int64_t count, double mult, double denom) {
+            std::vector<double> v(2 * (size_t)count);
+            for (int64_t j = 0; j < count; ++j) {
+                const double a = 2.0 * 3.14159265358979323846 * (double(j) * mult / denom);
+                v[2 * j] = std::cos(a);
+                v[2 * j + 1] = std::sin(a);
+            }
+            return v;
+        };
+        const std::vector<double> tabs[4] = {phasors(p->n1, 1.0, p->n1), phasors(p->n2, 1.0, p->n2),
+                                             phasors(int64_t(1) << p->split, 1.0, (double)N),
+                                             phasors(N >> p->split, (double)(int64_t(1) << p->split), (double)N)};
+        bool wok = true;
+        for (int t = 0; t < 4 && wok; ++t) {
+            const std::vector<double>& v = tabs[t];
+            // the node-precision copy at index 2t (or 2t for tw1/tw2 and 4/5 for twl/twh), FP64 beside it
+            const int ip = t < 2 ? 2 * t : 4 + (t - 2), i64 = t < 2 ? 2 * t + 1 : 6 + (t - 2);
+            wok = hipMalloc(&p->w_tw[i64], v.size() * 8) == hipSuccess &&
+                  hipMemcpy(p->w_tw[i64], v.data(), v.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMalloc(&p->w_tw[ip], v.size() * rsz) == hipSuccess && upload_real(p->w_tw[ip], v);
+        }
+        wok = wok && hipMalloc(&p->w_psi0, (size_t)N * 16) == hipSuccess &&
+              hipMalloc(&p->w_sums, (size_t)params->n_iter * N * 16) == hipSuccess &&
+              hipMalloc(&p->w_cur, (size_t)N * p->elem) == hipSuccess &&
+              hipMalloc(&p->w_work, (size_t)N * p->elem) == hipSuccess &&
+              hipMalloc(&p->w_work64, (size_t)N * 16) == hipSuccess;
+        // phase tables again, in the row-pass order of the four-step transform
+        wok = wok && mpa::launch_phase_table_t(p->phase, params->precision, p->n1, p->n2, rows,
+                                               (const double*)dcoef.p, 0) == hipSuccess &&
+              mpa::launch_phase_table_t(p->phase_last, MPA_C128, p->n1, p->n2, TT, (const double*)dlast.p, 0) ==
+                  hipSuccess &&
+              hipDeviceSynchronize() == hipSuccess;
+        if (!wok) {
+            plan_free(p);
+            return fail(MPA_ENOMEM, "full-window state or table construction failed");
+        }
+        p->node_bytes = (int64_t)((size_t)N * (16 * (2 + params->n_iter) + 2 * p->elem));
+    }
     if (params->schedule == MPA_NODE_PARALLEL) {
         const size_t nb = (size_t)p->n_blocks;
         const size_t u_bytes = nb * M * B * p->elem;
@@ -525,7 +594,41 @@ static int launch_long_step(mpa_plan* p, const void* in, void* out, int64_t m, h
     a.batch = batch;
     a.nodes = (batch == nullptr && p->nodes.psi0) ? &p->nodes : nullptr;
     a.stream = stream;
-    const hipError_t e = a.nodes ? mpa::launch_node_parallel_step(a) : mpa::launch_block_step(a);
+    hipError_t e;
+    if (p->window) {
+        mpa::WindowStepArgs w;
+        w.in = in;
+        w.out = out;
+        w.n = p->prm.n;
+        w.n1 = p->n1;
+        w.n2 = p->n2;
+        w.split = p->split;
+        w.phase = a.phase;
+        w.phase_last = a.phase_last;
+        w.node_scale_host = p->ns_host.data() + (size_t)gain_row(p, m, s) * 2 * (M + 1);
+        w.tw1 = p->w_tw[0];
+        w.tw1_64 = p->w_tw[1];
+        w.tw2 = p->w_tw[2];
+        w.tw2_64 = p->w_tw[3];
+        w.twl = p->w_tw[4];
+        w.twh = p->w_tw[5];
+        w.twl_64 = p->w_tw[6];
+        w.twh_64 = p->w_tw[7];
+        w.psi0 = p->w_psi0;
+        w.sums = p->w_sums;
+        w.cur = p->w_cur;
+        w.work = p->w_work;
+        w.work64 = p->w_work64;
+        w.M = M;
+        w.n_iter = p->prm.n_iter;
+        w.sigma = a.sigma;
+        w.out_scale = a.out_scale;
+        w.precision = p->prm.precision;
+        w.stream = stream;
+        e = mpa::launch_window_step(w);
+    } else {
+        e = a.nodes ? mpa::launch_node_parallel_step(a) : mpa::launch_block_step(a);
+    }
     if (e != hipSuccess) return fail(MPA_EDEVICE, "block step launch failed: %s", hipGetErrorString(e));
     return MPA_OK;
 }
@@ -762,6 +865,7 @@ int mpa_adjoint(mpa_plan* p, const void* checkpoints, void* grad, double z0, dou
     if (!p || !grad || !param_grad) return fail(MPA_EINVAL, "NULL plan, grad or param_grad");
     if (!p->sched.straddles.empty())
         return fail(MPA_EUNSUPPORTED, "the reverse pass needs long steps that stay within one span");
+    if (p->window) return fail(MPA_EUNSUPPORTED, "the reverse pass needs B <= 4096 (time blocks above that)");
     if (store_steps < 0) return fail(MPA_EINVAL, "store_steps must be >= 0");
     int64_t m0, m1;
     int st = grid_range(p, z0, z1, &m0, &m1);
