@@ -101,6 +101,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip accuracy and split-step comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-instance measurement")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient (reverse pass) measurement")
+    ap.add_argument("--grad-periods", type=int, default=20, help="map periods of the gradient measurement")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="for rocprofv3 --pmc: a 64 MiB copy (counter calibration), then 20 long steps")
     args = ap.parse_args()
@@ -187,7 +188,7 @@ def main():
         out["autotune"] = autotune_table(w, a0, torch, P)
         out["large"] = large(torch, P)
     if not args.no_grad:
-        out["gradient"] = gradient(torch, P)
+        out["gradient"] = gradient(torch, P, args.grad_periods)
     plan.close()
     if not args.no_cpu:
         log("CPU oracle baseline ...")
@@ -432,6 +433,26 @@ def compare(w, a0, plan, x, torch, P):
             log(f"SS {label} dz={dz:.3e}: in-band {e:.3e} full-band {e_full:.3e} time {el * 1e3:.1f} ms")
             if e <= e_mpa and (best is None or el < best["seconds"]):
                 best = rec
+    # blocking error at full size: FP64 blocked plan against the FP64 full-window
+    # plan (four-step transforms, no blocks) after one period
+    outs = {}
+    for block, halo in ((0, 0), (s.block, s.halo)):
+        pl = P.MPAPlan(n, dt, w.dmmap, s.L, s.M, s.n_iter, block, halo, P.MPA_C128, s.omega_band)
+        y = torch.from_numpy(a0).to(device="cuda:0", dtype=torch.complex128)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pl.propagate(y, 0.0, 1.0)
+        torch.cuda.synchronize()
+        outs[block] = (y.cpu().numpy(), time.perf_counter() - t0)
+        pl.close()
+    fw, bl = np.fft.ifft(outs[0][0]), np.fft.ifft(outs[s.block][0])
+    blocking = {"rel_l2_in_band": float(np.linalg.norm((bl - fw)[band]) / np.linalg.norm(fw[band])),
+                "rel_l2_full_band": float(np.linalg.norm(outs[s.block][0] - outs[0][0]) / np.linalg.norm(outs[0][0])),
+                "full_window_fp64_seconds": outs[0][1], "blocked_fp64_seconds": outs[s.block][1],
+                "full_window_rel_l2_in_band_vs_reference": err(outs[0][0])[1]}
+    log(f"blocking error after one period (FP64): in-band {blocking['rel_l2_in_band']:.2e}, "
+        f"full-band {blocking['rel_l2_full_band']:.2e}; full window {outs[0][1] * 1e3:.0f} ms, "
+        f"blocked {outs[s.block][1] * 1e3:.0f} ms")
     res = {"accuracy": {"mpa_rel_l2_in_band_after_one_period": e_mpa,
                         "mpa_rel_l2_full_band_after_one_period": e_mpa_full,
                         "in_band": f"|omega| <= {s.omega_band + 50.0:g}",
@@ -440,6 +461,7 @@ def compare(w, a0, plan, x, torch, P):
                         f"from it by {ref_err:.1e}",
                         "mpa_seconds_one_period": t_mpa},
            "picard_sweeps": picard,
+           "blocking_error": blocking,
            "split_step": {"sweep": sweep, "equal_accuracy": best,
                           "time_ratio_ss_over_mpa": (best["seconds"] / t_mpa) if best else None}}
     return res
