@@ -65,7 +65,7 @@ typedef enum {
     MPA_EDEVICE = -3,      /* no usable gfx950 device, or a HIP runtime error        */
     MPA_EALIGN = -4,       /* z0/z1 off the step grid, or a step not dividing a span */
     MPA_EHALO = -5,        /* halo too small for the long step (see above)           */
-    MPA_EUNSUPPORTED = -6  /* valid request outside the sizes this build compiles    */
+    MPA_EUNSUPPORTED = -6  /* valid request outside the sizes compiled in    */
 } mpa_status;
 
 typedef enum {

@@ -1137,7 +1137,7 @@ const char* mpa_status_string(int status) {
         case MPA_EDEVICE: return "MPA_EDEVICE: no usable gfx950 device or HIP error";
         case MPA_EALIGN: return "MPA_EALIGN: position or step off the grid";
         case MPA_EHALO: return "MPA_EHALO: halo too small for the long step";
-        case MPA_EUNSUPPORTED: return "MPA_EUNSUPPORTED: size not compiled in this build";
+        case MPA_EUNSUPPORTED: return "MPA_EUNSUPPORTED: size or combination not compiled into the library";
         default: return "unknown mpa_status";
     }
 }

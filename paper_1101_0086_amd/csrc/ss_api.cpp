@@ -102,7 +102,7 @@ int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz, int32_t 
     st = schedule_c(map, dz, steps.data(), &period, &amp);
     if (st) return st;
     if (!mpa::ss_small_supported(precision, n) && !mpa::ss_large_supported(precision, n))
-        return fail_status(MPA_EUNSUPPORTED, "split-step window size not compiled in this build (512..2^22)");
+        return fail_status(MPA_EUNSUPPORTED, "split-step window size not compiled into the library (512..2^22)");
     st = check_device_c(device);
     if (st) return st;
     if (hipSetDevice(device) != hipSuccess) return fail_status(MPA_EDEVICE, "hipSetDevice failed");
