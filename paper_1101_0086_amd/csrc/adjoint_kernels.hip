@@ -58,6 +58,14 @@ __device__ __forceinline__ long long wrap(long long g, long long n) {
     return g;
 }
 
+// node-precision transform: double-buffered when DB (see block_fft_db)
+template <typename T, int B, int SG, bool DB>
+__device__ __forceinline__ void node_fft(cx<T> (&v)[PTS], cx<T>*& db0, cx<T>*& db1, cx<T>* lds,
+                                         const cx<T>* __restrict__ tw, int tid) {
+    if constexpr (DB) block_fft_db<T, B, PTS, SG>(v, db0, db1, tw, tid);
+    else block_fft<T, B, PTS, SG>(v, lds, tw, tid);
+}
+
 }  // namespace
 
 template <typename T, int B, int NIT>
@@ -74,6 +82,11 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
     constexpr int NT = B / R;
     __shared__ cx<double> lds64[lds_elems<B>()];
     cx<T>* ldsT = reinterpret_cast<cx<T>*>(lds64);
+    // FP32 transforms double-buffered in the two halves of the FP64-sized LDS
+    // array; a barrier precedes every FP64 transform that follows them
+    constexpr bool DB = sizeof(T) == 4;
+    cx<T>* db0 = ldsT;
+    cx<T>* db1 = ldsT + (DB ? lds_elems<B>() : 0);
     const int tid = threadIdx.x;
     const long long c0 = (long long)blockIdx.x * core;
     const long long w0 = c0 - halo;
@@ -92,7 +105,7 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
             cur[m] = narrow<T>(scale(a, norm2(a)));
         }
         block_fft<double, B, R, +1, true>(psi0, lds64, tw64, tid);
-        block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
+        node_fft<T, B, +1, DB>(cur, db0, db1, ldsT, tw, tid);
         const T d0 = sigma * node_scale[1];
 #pragma unroll
         for (int m = 0; m < R; ++m) {
@@ -118,14 +131,14 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
                     cur[m] = cmul(cur[m], ph[m]);
                     slot[B + tid + NT * m] = cur[m];                       // y
                 }
-                block_fft<T, B, R, -1>(cur, ldsT, tw, tid);
+                node_fft<T, B, -1, DB>(cur, db0, db1, ldsT, tw, tid);
 #pragma unroll
                 for (int m = 0; m < R; ++m) {
                     const cx<T> a = scale(cur[m], cl);
                     slot[tid + NT * m] = a;                                // A
                     cur[m] = scale(a, norm2(a));
                 }
-                block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
+                node_fft<T, B, +1, DB>(cur, db0, db1, ldsT, tw, tid);
                 const bool need_next = (s < NIT - 1) || last_node;
                 const bool final_sum = last_node && (s == NIT - 1);
 #pragma unroll
@@ -169,6 +182,7 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
             const int t = tid + NT * m;
             big[m] = (t >= halo && t < halo + clen) ? g_out[c0 + (t - halo)] : cx<double>{0.0, 0.0};
         }
+        if constexpr (DB) __syncthreads();
         block_fft<double, B, R, +1, true>(big, lds64, tw64, tid);
 #pragma unroll
         for (int m = 0; m < R; ++m) {
@@ -219,14 +233,14 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
                 d_beta3 += r * (om * om * om * zl / 6.0);
                 cur[m] = rot<-1>(scale(cmul(narrow<T>(gu), ph[m]), dl));     // G(F[n])
             }
-            block_fft<T, B, R, -1>(cur, ldsT, tw, tid);                      // G(n)
+            node_fft<T, B, -1, DB>(cur, db0, db1, ldsT, tw, tid);                      // G(n)
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 const cx<T> a = slot[tid + NT * m];
                 const cx<T> g = cur[m];
                 cur[m] = scale(g, T(2) * norm2(a)) + sq_conj(a, g);           // G(A)
             }
-            block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
+            node_fft<T, B, +1, DB>(cur, db0, db1, ldsT, tw, tid);
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 int k = tid + NT * m;
@@ -260,13 +274,14 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
         const cx<double> a = scale(widen(in[wrap(w0 + t, n)]), taper[t]);
         cur[m] = narrow<T>(scale(a, norm2(a)));
     }
-    block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
+    node_fft<T, B, +1, DB>(cur, db0, db1, ldsT, tw, tid);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         d_sigma += re_dot(big[m], widen(rot<+1>(scale(cur[m], e0))));
         cur[m] = rot<-1>(scale(narrow<T>(big[m]), d0));
     }
-    block_fft<T, B, R, -1>(cur, ldsT, tw, tid);                              // G(n_0)
+    node_fft<T, B, -1, DB>(cur, db0, db1, ldsT, tw, tid);                              // G(n_0)
+    if constexpr (DB) __syncthreads();
     block_fft<double, B, R, -1, true>(g0, lds64, tw64, tid);                       // G(A_0) via psi_0
 #pragma unroll
     for (int m = 0; m < R; ++m) {

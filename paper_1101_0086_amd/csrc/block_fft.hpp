@@ -153,6 +153,86 @@ __device__ __forceinline__ void fft_from(cx<T> (&v)[R], cx<T>* lds,
     if constexpr (!last) fft_from<T, B, R, SIGN, P * r, COLD>(v, lds, tw, tid);
 }
 
+// ---- double-buffered variant ---------------------------------------------------
+// Passes alternate between two LDS buffers: pass s writes buf[s % 2] and pass
+// s + 1 reads it after one barrier.  The barrier after the reads is not
+// needed, since the next write goes to the other buffer, whose last readers
+// passed the barrier before this read.  A call ends having read
+// buf[(E - 1) % 2] (E exchanges); the caller's next call must start writing
+// the other buffer, so for odd E the two pointers are swapped on return.
+template <typename T, int B, int R, int r, int p, int SIGN, bool FROM_LDS, bool TO_LDS>
+__device__ __forceinline__ void fft_pass_db(cx<T> (&v)[R], const cx<T>* lds_in, cx<T>* lds_out,
+                                            const cx<T>* __restrict__ tw, int tid) {
+    constexpr int NT = B / R;
+    constexpr int NB = R / r;
+    if constexpr (FROM_LDS) {
+        __syncthreads();        // the previous pass's writes are visible
+#pragma unroll
+        for (int m = 0; m < R; ++m) v[m] = lds_in[lds_slot(tid + NT * m)];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int i = tid + u * NT;
+        const int k = i & (p - 1);
+        cx<T> x[r];
+#pragma unroll
+        for (int q = 0; q < r; ++q) x[q] = v[u + q * NB];
+        if constexpr (p > 1) {
+            constexpr int stride = B / (p * r);
+#pragma unroll
+            for (int q = 1; q < r; ++q) {
+                cx<T> w = tw[q * k * stride];
+                if constexpr (SIGN < 0) w.im = -w.im;
+                x[q] = cmul(x[q], w);
+            }
+        }
+        dft<SIGN, r>(x);
+        if constexpr (TO_LDS) {
+            const int base = (i - k) * r + k;
+#pragma unroll
+            for (int q = 0; q < r; ++q) lds_out[lds_slot(base + q * p)] = x[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < r; ++q) v[u + q * NB] = x[q];
+        }
+    }
+}
+
+template <typename T, int B, int R, int SIGN, int P, int S>
+__device__ __forceinline__ void fft_from_db(cx<T> (&v)[R], cx<T>* buf0, cx<T>* buf1,
+                                            const cx<T>* __restrict__ tw, int tid) {
+    constexpr int r = pass_radix<B, P>();
+    constexpr bool first = (P == 1);
+    constexpr bool last = (P * r == B);
+    // pass S reads buf[(S - 1) % 2] and writes buf[S % 2]
+    cx<T>* in = (S % 2) ? buf0 : buf1;
+    cx<T>* out = (S % 2) ? buf1 : buf0;
+    fft_pass_db<T, B, R, r, P, SIGN, !first, !last>(v, in, out, tw, tid);
+    if constexpr (!last) fft_from_db<T, B, R, SIGN, P * r, S + 1>(v, buf0, buf1, tw, tid);
+}
+
+template <int B, int P>
+constexpr int exchanges() {
+    constexpr int r = pass_radix<B, P>();
+    if constexpr (P * r == B) return 0;
+    else return 1 + exchanges<B, P * r>();
+}
+
+// B-point transform through two LDS buffers (each lds_elems<B>() elements);
+// see fft_pass_db.  Every LDS access made before the call must have passed
+// a barrier if it touched either buffer.
+template <typename T, int B, int R, int SIGN>
+__device__ __forceinline__ void block_fft_db(cx<T> (&v)[R], cx<T>*& buf0, cx<T>*& buf1,
+                                             const cx<T>* __restrict__ tw, int tid) {
+    static_assert((B & (B - 1)) == 0 && B >= 64, "power-of-two block");
+    fft_from_db<T, B, R, SIGN, 1, 0>(v, buf0, buf1, tw, tid);
+    if constexpr (exchanges<B, 1>() % 2 == 1) {
+        cx<T>* t = buf0;
+        buf0 = buf1;
+        buf1 = t;
+    }
+}
+
 // B-point transform of the workgroup's registers (see the file comment).
 // `tw` holds exp(+2 pi i j / B), j = 0..B-1.  Must be called by every
 // thread of the workgroup (it contains barriers).  COLD: the twiddle index
