@@ -132,23 +132,28 @@ def test_resume_step_and_determinism():
     assert np.array_equal(r1, r2) and np.array_equal(r1, r3)
 
 
-def test_full_size_8ch_sampled_blocks():
-    """2^18 modes, 8 channels, 4096-blocks with 512-halo (the benchmark's
-    launch configuration): one long step on the GPU, three blocks (first,
-    middle, ragged last) recomputed by the oracle one at a time."""
-    w = WORKLOADS["wdm8_n262144_f32"]
+@pytest.mark.parametrize("name", ["wdm8_n262144_f32", "wdm32_n4194304_f32"])
+def test_full_size_sampled_blocks(name):
+    """The benchmark's 2^18-mode 8-channel workload and the 2^22-mode
+    32-channel QPSK workload (the largest configuration) in their launch
+    configurations (4096-blocks, 512-halo): one long step on the GPU, three
+    blocks (first, middle, ragged last) recomputed by the oracle one at a
+    time, roll-off included."""
+    w = WORKLOADS[name]
     s = w.mpa
     a = w.field()
-    say("full size 8ch", w.grid.n)
+    say("full size sampled blocks", name, w.grid.n)
     got = _run_mpa(a, w.grid, w.dmmap, s.L, s.M, s.n_iter, s.block, s.halo, 0, 0.0, s.L,
                    s.omega_band)
     parts = O.block_partition(w.grid.n, s.block, s.halo)
     omega_b = O.omega_grid(s.block, w.grid.dt)
     taper = O.block_taper(s.block, s.halo)
+    b2, b3 = w.dmmap.beta2[0], w.dmmap.beta3[0]
+    mask = O.block_mask(omega_b, b2, b3, s.L, s.halo, w.grid.dt)
     for b in (0, len(parts) // 2, len(parts) - 1):
         w0, c0, clen = parts[b]
         idx = (w0 + np.arange(s.block)) % w.grid.n
-        res = O.mpa_long_step(a[idx] * taper, omega_b, w.dmmap.beta2[0], w.dmmap.beta3[0],
-                              w.dmmap.sigma[0], w.dmmap.gamma, s.L, s.M, s.n_iter)
+        res = O.mpa_long_step(a[idx] * taper, omega_b, b2, b3, w.dmmap.sigma[0], w.dmmap.gamma,
+                              s.L, s.M, s.n_iter, out_mask=mask)
         ref = res[s.halo:s.halo + clen]
         assert rel_l2(got[c0:c0 + clen], ref) < TOL_F32, b
