@@ -78,236 +78,50 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restr
                          const cx<T>* __restrict__ tw, const cx<double>* __restrict__ tw64,
                          const double* __restrict__ taper, const cx<double>* __restrict__ mask_grad, int M,
                          T sigma, double out_scale, double w1, double dz) {
-    constexpr int R = PTS;
-    constexpr int NT = B / R;
     __shared__ cx<double> lds64[lds_elems<B>()];
-    cx<T>* ldsT = reinterpret_cast<cx<T>*>(lds64);
-    // FP32 transforms double-buffered in the two halves of the FP64-sized LDS
-    // array; a barrier precedes every FP64 transform that follows them
-    constexpr bool DB = sizeof(T) == 4;
-    cx<T>* db0 = ldsT;
-    cx<T>* db1 = ldsT + (DB ? lds_elems<B>() : 0);
-    const int tid = threadIdx.x;
     const long long c0 = (long long)blockIdx.x * core;
-    const long long w0 = c0 - halo;
     cx<T>* __restrict__ store = node_store + (size_t)blockIdx.x * NIT * M * 3 * B;
     cx<double>* __restrict__ last = last_store + (size_t)blockIdx.x * B;
+    cx<double>* __restrict__ g_item = g_blk + (size_t)blockIdx.x * B;
+    double* __restrict__ part = partial + (size_t)blockIdx.x * 3;
+    const int thread = threadIdx.x;
+#include "adjoint_body.inc"
+}
 
-    // ---- forward recompute of the block's long step, keeping node values ----
-    {
-        cx<double> psi0[R], S[NIT][R];
-        cx<T> cur[R], ph[R];
-#pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const int t = tid + NT * m;
-            const cx<double> a = scale(widen(in[wrap(w0 + t, n)]), taper[t]);
-            psi0[m] = a;
-            cur[m] = narrow<T>(scale(a, norm2(a)));
-        }
-        block_fft<double, B, R, +1, true>(psi0, lds64, tw64, tid);
-        node_fft<T, B, +1, DB>(cur, db0, db1, ldsT, tw, tid);
-        const T d0 = sigma * node_scale[1];
-#pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const cx<double> u0 = widen(rot<+1>(scale(cur[m], d0 * T(0.5))));
-#pragma unroll
-            for (int s = 0; s < NIT; ++s) S[s][m] = u0;
-        }
-        for (int l = 1; l <= M; ++l) {
-            const T cl = node_scale[2 * l];
-            const T el = node_scale[2 * l + 1];
-            const T dl = sigma * el;
-#pragma unroll
-            for (int m = 0; m < R; ++m) {
-                ph[m] = phase[(size_t)l * B + tid + NT * m];
-                cur[m] = narrow<T>(psi0[m]);
-            }
-            const bool last_node = (l == M);
-#pragma unroll
-            for (int s = 0; s < NIT; ++s) {
-                cx<T>* __restrict__ slot = store + (size_t)((s * M + l - 1) * 3) * B;
-#pragma unroll
-                for (int m = 0; m < R; ++m) {
-                    cur[m] = cmul(cur[m], ph[m]);
-                    slot[B + tid + NT * m] = cur[m];                       // y
-                }
-                node_fft<T, B, -1, DB>(cur, db0, db1, ldsT, tw, tid);
-#pragma unroll
-                for (int m = 0; m < R; ++m) {
-                    const cx<T> a = scale(cur[m], cl);
-                    slot[tid + NT * m] = a;                                // A
-                    cur[m] = scale(a, norm2(a));
-                }
-                node_fft<T, B, +1, DB>(cur, db0, db1, ldsT, tw, tid);
-                const bool need_next = (s < NIT - 1) || last_node;
-                const bool final_sum = last_node && (s == NIT - 1);
-#pragma unroll
-                for (int m = 0; m < R; ++m) {
-#pragma clang fp contract(off)
-                    const cx<T> v = cmulc(cur[m], ph[m]);
-                    slot[2 * B + tid + NT * m] = rot<+1>(scale(v, el));    // U / sigma
-                    const cx<double> u = widen(rot<+1>(scale(v, dl)));
-                    if (need_next) {
-                        const cx<double> nxt = psi0[m] + (S[s][m] + scale(u, 0.5));
-                        if (final_sum) psi0[m] = nxt;
-                        else cur[m] = narrow<T>(nxt);
-                    }
-                    if (!last_node) S[s][m] = S[s][m] + u;
-                }
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < R; ++m) last[tid + NT * m] = psi0[m];         // psi^(n_iter)_M
+// Many fields of different lengths, concatenated (as the forward batch
+// kernel): a fixed grid of workgroups walks the (instance, block) work list;
+// each workgroup reuses its own node store for every item it takes.  The
+// sigma derivative is taken with respect to the instance's effective sigma
+// (the span's sigma times the instance's scale).
+template <typename T, int B, int NIT>
+__global__ void __launch_bounds__(B / PTS)
+mpa_adjoint_batch_kernel(const cx<T>* __restrict__ fin, const cx<double>* __restrict__ gin,
+                         cx<double>* __restrict__ g_blk, double* __restrict__ partial,
+                         cx<T>* __restrict__ node_store, cx<double>* __restrict__ last_store,
+                         const int2* __restrict__ items, int n_items, const long long* __restrict__ offset,
+                         const long long* __restrict__ len, const double* __restrict__ sigma_scale, int core,
+                         int halo, const cx<T>* __restrict__ phase, const cx<double>* __restrict__ phase_last,
+                         const T* __restrict__ node_scale, const cx<T>* __restrict__ tw,
+                         const cx<double>* __restrict__ tw64, const double* __restrict__ taper,
+                         const cx<double>* __restrict__ mask_grad, int M, double sigma_span, double out_scale,
+                         double w1, double dz) {
+    __shared__ cx<double> lds64[lds_elems<B>()];
+    cx<T>* __restrict__ store = node_store + (size_t)blockIdx.x * NIT * M * 3 * B;
+    cx<double>* __restrict__ last = last_store + (size_t)blockIdx.x * B;
+    for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+        const int2 it = items[w];
+        const cx<T>* __restrict__ in = fin + offset[it.x];
+        const cx<double>* __restrict__ g_out = gin + offset[it.x];
+        const long long n = len[it.x];
+        const long long c0 = (long long)it.y * core;
+        const T sigma = T(sigma_span * sigma_scale[it.x]);
+        cx<double>* __restrict__ g_item = g_blk + (size_t)w * B;
+        double* __restrict__ part = partial + (size_t)w * 3;
+        int thread = threadIdx.x;
+        asm volatile("" : "+v"(thread));
+        __syncthreads();     // the previous item's last LDS reads are done
+#include "adjoint_body.inc"
     }
-
-    // ---- reverse pass ----
-    // Only the gradient of psi^(n_iter)_M (from the output) is of the size of
-    // the field's gradient; it reaches psi_0 with weight 1 and every U of the
-    // last sweep with weight 1/2 or 1, and is kept in FP64 (`big`).  Every
-    // other gradient in the block passes through a node evaluation (a factor
-    // sigma dz) and is kept in the node precision T: the running reverse
-    // trapezoid sums Rs of the earlier sweeps, the carried G(psi^(s+1)_l) and
-    // the sweep-0 part of G(psi_0).
-    double d_sigma = 0.0, d_beta2 = 0.0, d_beta3 = 0.0;
-    cx<double> big[R];
-    cx<T> gp0[R], gn[R], cur[R], ph[R];
-    cx<T> Rs[NIT > 1 ? NIT - 1 : 1][R];
-    const double zM = M * dz;
-    {
-        // step 7: out = out_scale F^-1[psi_M e^{i beta_M} mask]; only the core is output
-        const long long rest = n - c0;
-        const int clen = rest < core ? (int)rest : core;
-#pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const int t = tid + NT * m;
-            big[m] = (t >= halo && t < halo + clen) ? g_out[c0 + (t - halo)] : cx<double>{0.0, 0.0};
-        }
-        if constexpr (DB) __syncthreads();
-        block_fft<double, B, R, +1, true>(big, lds64, tw64, tid);
-#pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const int k = tid + NT * m;
-            const double om = w1 * double(k < B / 2 ? k : k - B);
-            const cx<double> gx = scale(big[m], out_scale);
-            const cx<double> psiM = last[k];
-            const cx<double> pl = phase_last[k];
-            const double r = re_dot_i(gx, cmul(psiM, pl));
-            d_beta2 += r * (0.5 * om * om * zM);
-            d_beta3 += r * (om * om * om * zM / 6.0);
-            if (mask_grad) {
-                d_beta2 += re_dot(gx, cmul(psiM, mask_grad[k]));
-                d_beta3 += re_dot(gx, cmul(psiM, mask_grad[B + k]));
-            }
-            big[m] = cmulc(gx, pl);                                         // G(psi^(n_iter)_M)
-            gp0[m] = {T(0), T(0)};
-#pragma unroll
-            for (int s = 0; s + 1 < NIT; ++s) Rs[s][m] = {T(0), T(0)};
-        }
-    }
-    for (int l = M; l >= 1; --l) {
-        const T cl = node_scale[2 * l];
-        const T dl = sigma * node_scale[2 * l + 1];
-        const double zl = l * dz;
-#pragma unroll
-        for (int m = 0; m < R; ++m) ph[m] = phase[(size_t)l * B + tid + NT * m];
-#pragma unroll
-        for (int s = NIT - 1; s >= 0; --s) {
-            const cx<T>* __restrict__ slot = store + (size_t)((s * M + l - 1) * 3) * B;
-            // trapezoid adjoint: G(U^(s)_l) = G(psi^(s+1)_l) / 2 + sum_{l' > l} G(psi^(s+1)_l')
-#pragma unroll
-            for (int m = 0; m < R; ++m) {
-                int k = tid + NT * m;
-                asm volatile("" : "+v"(k));      // recomputed per node: keeps omega out of registers
-                const double om = w1 * double(k < B / 2 ? k : k - B);
-                cx<double> gu;
-                if (s == NIT - 1) {
-                    gu = (l == M) ? scale(big[m], 0.5) : big[m];
-                } else {
-                    gu = widen(scale(gn[m], T(0.5)) + Rs[s][m]);
-                    Rs[s][m] = Rs[s][m] + gn[m];
-                }
-                const cx<double> up = widen(slot[2 * B + k]);
-                d_sigma += re_dot(gu, up);
-                const double r = -re_dot_i(gu, up) * double(sigma);
-                d_beta2 += r * (0.5 * om * om * zl);
-                d_beta3 += r * (om * om * om * zl / 6.0);
-                cur[m] = rot<-1>(scale(cmul(narrow<T>(gu), ph[m]), dl));     // G(F[n])
-            }
-            node_fft<T, B, -1, DB>(cur, db0, db1, ldsT, tw, tid);                      // G(n)
-#pragma unroll
-            for (int m = 0; m < R; ++m) {
-                const cx<T> a = slot[tid + NT * m];
-                const cx<T> g = cur[m];
-                cur[m] = scale(g, T(2) * norm2(a)) + sq_conj(a, g);           // G(A)
-            }
-            node_fft<T, B, +1, DB>(cur, db0, db1, ldsT, tw, tid);
-#pragma unroll
-            for (int m = 0; m < R; ++m) {
-                int k = tid + NT * m;
-                asm volatile("" : "+v"(k));
-                const double om = w1 * double(k < B / 2 ? k : k - B);
-                const cx<T> gy = scale(cur[m], cl);                           // G(y)
-                const double r = re_dot_i(widen(gy), widen(slot[B + k]));
-                d_beta2 += r * (0.5 * om * om * zl);
-                d_beta3 += r * (om * om * om * zl / 6.0);
-                const cx<T> gps = cmulc(gy, ph[m]);                           // G(psi^(s)_l)
-                if (s > 0) gn[m] = gps;
-                else gp0[m] = gp0[m] + gps;
-            }
-        }
-    }
-
-    // node 0 (U_0 = i sigma dz F[|A_0|^2 A_0], shared by every sweep) and psi_0 = F[A_0]
-    const T e0 = node_scale[1];
-    const T d0 = sigma * e0;
-    cx<double> g0[R];
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-        // sum over l >= 1 of G(psi^(s+1)_l) for every sweep: the last sweep's is big
-        cx<T> small = {T(0), T(0)};
-#pragma unroll
-        for (int s = 0; s + 1 < NIT; ++s) small = small + Rs[s][m];
-        const cx<double> tot = big[m] + widen(small);
-        g0[m] = tot + widen(gp0[m]);                                          // G(psi_0)
-        big[m] = scale(tot, 0.5);                                             // G(U_0)
-        const int t = tid + NT * m;
-        const cx<double> a = scale(widen(in[wrap(w0 + t, n)]), taper[t]);
-        cur[m] = narrow<T>(scale(a, norm2(a)));
-    }
-    node_fft<T, B, +1, DB>(cur, db0, db1, ldsT, tw, tid);
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-        d_sigma += re_dot(big[m], widen(rot<+1>(scale(cur[m], e0))));
-        cur[m] = rot<-1>(scale(narrow<T>(big[m]), d0));
-    }
-    node_fft<T, B, -1, DB>(cur, db0, db1, ldsT, tw, tid);                              // G(n_0)
-    if constexpr (DB) __syncthreads();
-    block_fft<double, B, R, -1, true>(g0, lds64, tw64, tid);                       // G(A_0) via psi_0
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-        const int t = tid + NT * m;
-        const cx<double> a = scale(widen(in[wrap(w0 + t, n)]), taper[t]);
-        const cx<double> g = widen(cur[m]);
-        const cx<double> ga = g0[m] + scale(g, 2.0 * norm2(a)) + sq_conj(a, g);
-        g_blk[(size_t)blockIdx.x * B + t] = scale(ga, taper[t]);
-    }
-
-    // workgroup sums of the parameter derivatives (fixed order)
-    double* red = reinterpret_cast<double*>(lds64);
-    __syncthreads();
-    red[tid] = d_sigma;
-    red[NT + tid] = d_beta2;
-    red[2 * NT + tid] = d_beta3;
-    for (int h = NT / 2; h > 0; h >>= 1) {
-        __syncthreads();
-        if (tid < h) {
-            red[tid] += red[tid + h];
-            red[NT + tid] += red[NT + tid + h];
-            red[2 * NT + tid] += red[2 * NT + tid + h];
-        }
-    }
-    __syncthreads();
-    if (tid < 3) partial[(size_t)blockIdx.x * 3 + tid] = red[tid * NT];
 }
 
 // g_in[i] = sum over the windows b containing sample i of g_blk[b][i - (b C - H) mod N];
