@@ -189,6 +189,7 @@ def main():
         out["large"] = large(torch, P)
     if not args.no_grad:
         out["gradient"] = gradient(torch, P, args.grad_periods)
+        out["batched_gradient"] = batched_gradient(torch, P)
     plan.close()
     if not args.no_cpu:
         log("CPU oracle baseline ...")
@@ -344,6 +345,57 @@ def gradient(torch, P, periods=20):
          "dl_dsigma": pgc[0].tolist(), "dl_dbeta2": pgc[1].tolist(), "dl_dbeta3": pgc[2].tolist()}
     log(f"gradient ({periods} periods): forward {t_fwd:.2f} s, checkpointed {t_ck:.2f} s, reverse {t_adj:.2f} s "
         f"({r['gradient_over_forward']:.2f}x forward), reverse step {r['adjoint_step_us']:.1f} us")
+    return r
+
+
+def batched_gradient(torch, P, count=32, periods=1):
+    """Gradients of 32 instances of the 2^16-mode 4-channel workload (seeds
+    differ, sigma scales uniform in [0.8, 1.2]) through one map period (4000
+    long steps) with one batched launch per long step: checkpointed forward
+    and reverse pass, timed after a warm-up, against the plain batched
+    forward."""
+    import numpy as np
+    from workloads import WORKLOADS
+    w = WORKLOADS["wdm4_n65536_f32"]
+    s = w.mpa
+    rng = np.random.default_rng(7)
+    sig = rng.uniform(0.8, 1.2, count).tolist()
+    ns = [w.grid.n] * count
+    bp = P.MPABatchPlan(ns, w.grid.dt, w.dmmap, s.L, s.M, s.n_iter, s.block, s.halo, P.MPA_C64, s.omega_band,
+                        sigma_scale=sig)
+    info = bp.info()
+    x0 = torch.from_numpy(np.concatenate([w.field(seed=w.seed + i) for i in range(count)])).to(
+        device="cuda:0", dtype=torch.complex64)
+    z1 = float(periods)
+    steps = int(round(z1 / s.L))
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    x = x0.clone()
+    ck = bp.propagate_checkpointed(x, 0.0, 20 * s.L)              # warm-up, workspace
+    bp.adjoint(ck, (2 * x).contiguous(), 0.0, 20 * s.L)
+    x = x0.clone()
+    t_fwd, _ = timed(lambda: bp.propagate(x, 0.0, z1))
+    x = x0.clone()
+    t_ck, ck = timed(lambda: bp.propagate_checkpointed(x, 0.0, z1))
+    g = (2 * x).contiguous()
+    t_adj, _ = timed(lambda: bp.adjoint(ck, g, 0.0, z1))
+    bp.close()
+    ms = info["total_samples"] * s.M * steps
+    r = {"workload": f"{count} x {w.name}", "total_modes": info["total_samples"],
+         "work_items_per_launch": info["work_items"], "long_steps": steps,
+         "forward_s": t_fwd, "checkpointed_forward_s": t_ck, "reverse_s": t_adj,
+         "gradient_over_forward": (t_ck + t_adj) / t_fwd,
+         "forward_mode_steps_per_s": ms / t_fwd,
+         "gradient_mode_steps_per_s": ms / (t_ck + t_adj),
+         "adjoint_step_us": (t_adj - t_fwd) / steps * 1e6}
+    log(f"batched gradient ({count} instances, {steps} long steps): forward {t_fwd:.2f} s, checkpointed "
+        f"{t_ck:.2f} s, reverse {t_adj:.2f} s, gradient {r['gradient_mode_steps_per_s']:.3e} mode-steps/s")
     return r
 
 

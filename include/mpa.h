@@ -248,6 +248,25 @@ int mpa_batch_get_info(const mpa_batch_plan* plan, int64_t* total_samples,
 int mpa_batch_propagate(mpa_batch_plan* plan, void* fields, double z0, double z1,
                         void* stream);
 
+/* Gradients through mpa_batch_propagate, as mpa_checkpoint_count /
+ * mpa_propagate_checkpointed / mpa_adjoint for one field, on the
+ * concatenated fields: a checkpoint is total_samples complex samples (all
+ * instances), and `grads` holds G of every instance, concatenated.  The
+ * parameters are shared by the instances, so param_grad (3 x n_seg doubles)
+ * receives the derivative of the one loss over all of them; an instance's
+ * sigma is the span's sigma times its sigma_scale, and its share of
+ * dl/dsigma is weighted by that scale.  Each instance's G(A(z0)) is that of
+ * mpa_adjoint on a plan of its own (sigma scaled, same parameters): the
+ * kernels run the same per-block operations, with the work items walked by a
+ * fixed grid of workgroups.  The workspace (held by the batch plan) is
+ * grid x (3 n_iter M + 1) x block + work_items x block complex samples plus
+ * the kept step inputs.                                                     */
+int mpa_batch_checkpoint_count(const mpa_batch_plan* plan, double z0, double z1, int64_t* count);
+int mpa_batch_propagate_checkpointed(mpa_batch_plan* plan, void* fields, double z0, double z1,
+                                     void* checkpoints, void* stream);
+int mpa_batch_adjoint(mpa_batch_plan* plan, const void* checkpoints, void* grads, double z0,
+                      double z1, double* param_grad, int64_t store_steps, void* stream);
+
 /* ---- captured launch sequences (HIP graphs) ------------------------------
  *
  * Record the launches of mpa_propagate / mpa_batch_propagate from z0 to z1

@@ -147,6 +147,7 @@ class MPABatchPlan:
         self.ns = [int(v) for v in ns]
         self.n = sum(self.ns)
         self.precision, self.device = int(precision), int(device)
+        self.n_seg = len(dmmap.seg_len)
         p = _lib.make_params(max(self.ns), dt, L, M, n_iter, block, halo, precision, omega_band)
         m = _lib.MapStruct(dmmap)
         d = _lib.BatchDesc(self.ns, sigma_scale)
@@ -172,6 +173,37 @@ class MPABatchPlan:
         _lib.check(_lib.lib().mpa_batch_propagate(self._h, C.c_void_p(fields.data_ptr()), float(z0),
                                                   float(z1), _stream_handle(torch, fields.device)))
         return fields
+
+    def checkpoint_count(self, z0, z1):
+        c = C.c_int64()
+        _lib.check(_lib.lib().mpa_batch_checkpoint_count(self._h, float(z0), float(z1), C.byref(c)))
+        return c.value
+
+    def propagate_checkpointed(self, fields, z0, z1):
+        """mpa_batch_propagate_checkpointed: marches the concatenated `fields`
+        in place and returns the checkpoints (k, total samples)."""
+        torch = _check_field(fields, self.precision, self.n)
+        k = self.checkpoint_count(z0, z1)
+        ckpt = torch.empty((k, self.n), dtype=fields.dtype, device=fields.device)
+        _lib.check(_lib.lib().mpa_batch_propagate_checkpointed(
+            self._h, C.c_void_p(fields.data_ptr()), float(z0), float(z1),
+            C.c_void_p(ckpt.data_ptr() if k else 0), _stream_handle(torch, fields.device)))
+        return ckpt
+
+    def adjoint(self, checkpoints, grads, z0, z1, store_steps=0):
+        """mpa_batch_adjoint: turns G(A(z1)) of every instance (concatenated in
+        `grads`) into G(A(z0)) in place and returns the derivatives of the loss
+        with respect to the shared (sigma, beta2, beta3) per span, (3, n_seg) FP64."""
+        torch = _check_field(grads, self.precision, self.n)
+        k = self.checkpoint_count(z0, z1)
+        if checkpoints.shape != (k, self.n) or checkpoints.dtype != grads.dtype or not checkpoints.is_contiguous():
+            raise ValueError(f"checkpoints must be a contiguous ({k}, {self.n}) {grads.dtype} tensor")
+        pg = torch.empty((3, self.n_seg), dtype=torch.float64, device=grads.device)
+        _lib.check(_lib.lib().mpa_batch_adjoint(
+            self._h, C.c_void_p(checkpoints.data_ptr() if k else 0), C.c_void_p(grads.data_ptr()),
+            float(z0), float(z1), C.c_void_p(pg.data_ptr()), int(store_steps),
+            _stream_handle(torch, grads.device)))
+        return pg
 
     def capture(self, fields, z0, z1):
         _check_field(fields, self.precision, self.n)

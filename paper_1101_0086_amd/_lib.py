@@ -31,7 +31,8 @@ EXPORTED = ("mpa_plan_create", "mpa_plan_destroy", "mpa_plan_get_info", "mpa_pla
             "mpa_batch_plan_destroy", "mpa_batch_get_info", "mpa_batch_propagate",
             "mpa_graph_capture", "mpa_batch_graph_capture", "mpa_graph_launch", "mpa_graph_destroy",
             "ss_plan_create", "ss_plan_destroy", "ss_propagate", "mpa_status_string", "mpa_last_error",
-            "mpa_checkpoint_count", "mpa_propagate_checkpointed", "mpa_adjoint")
+            "mpa_checkpoint_count", "mpa_propagate_checkpointed", "mpa_adjoint",
+            "mpa_batch_checkpoint_count", "mpa_batch_propagate_checkpointed", "mpa_batch_adjoint")
 
 
 class mpa_map(C.Structure):
@@ -102,6 +103,9 @@ def lib() -> C.CDLL:
     h.mpa_checkpoint_count.argtypes = [vp, dp, dp, C.POINTER(C.c_int64)]
     h.mpa_propagate_checkpointed.argtypes = [vp, vp, dp, dp, vp, vp]
     h.mpa_adjoint.argtypes = [vp, vp, vp, dp, dp, vp, C.c_int64, vp]
+    h.mpa_batch_checkpoint_count.argtypes = [vp, dp, dp, C.POINTER(C.c_int64)]
+    h.mpa_batch_propagate_checkpointed.argtypes = [vp, vp, dp, dp, vp, vp]
+    h.mpa_batch_adjoint.argtypes = [vp, vp, vp, dp, dp, vp, C.c_int64, vp]
     h.mpa_status_string.argtypes = [C.c_int]
     h.mpa_status_string.restype = C.c_char_p
     h.mpa_last_error.argtypes = [C.c_char_p, C.c_int]

@@ -68,53 +68,43 @@ __device__ __forceinline__ void node_fft(cx<T> (&v)[PTS], cx<T>*& db0, cx<T>*& d
 
 }  // namespace
 
+// One workgroup per work item.  A single field (items == nullptr): item w is
+// block w of the field.  Many fields of different lengths concatenated (as in
+// the forward batch kernel): item w is block items[w].y of instance
+// items[w].x, a fixed grid of workgroups walks the list, and each workgroup
+// reuses its own node store for every item it takes.  The sigma derivative
+// is taken with respect to the sigma the item runs with (the span's sigma
+// times the instance's scale).
 template <typename T, int B, int NIT>
 __global__ void __launch_bounds__(B / PTS)
-mpa_adjoint_block_kernel(const cx<T>* __restrict__ in, const cx<double>* __restrict__ g_out,
-                         cx<double>* __restrict__ g_blk, double* __restrict__ partial,
-                         cx<T>* __restrict__ node_store, cx<double>* __restrict__ last_store, long long n,
-                         int core, int halo, const cx<T>* __restrict__ phase,
-                         const cx<double>* __restrict__ phase_last, const T* __restrict__ node_scale,
-                         const cx<T>* __restrict__ tw, const cx<double>* __restrict__ tw64,
-                         const double* __restrict__ taper, const cx<double>* __restrict__ mask_grad, int M,
-                         T sigma, double out_scale, double w1, double dz) {
-    __shared__ cx<double> lds64[lds_elems<B>()];
-    const long long c0 = (long long)blockIdx.x * core;
-    cx<T>* __restrict__ store = node_store + (size_t)blockIdx.x * NIT * M * 3 * B;
-    cx<double>* __restrict__ last = last_store + (size_t)blockIdx.x * B;
-    cx<double>* __restrict__ g_item = g_blk + (size_t)blockIdx.x * B;
-    double* __restrict__ part = partial + (size_t)blockIdx.x * 3;
-    const int thread = threadIdx.x;
-#include "adjoint_body.inc"
-}
-
-// Many fields of different lengths, concatenated (as the forward batch
-// kernel): a fixed grid of workgroups walks the (instance, block) work list;
-// each workgroup reuses its own node store for every item it takes.  The
-// sigma derivative is taken with respect to the instance's effective sigma
-// (the span's sigma times the instance's scale).
-template <typename T, int B, int NIT>
-__global__ void __launch_bounds__(B / PTS)
-mpa_adjoint_batch_kernel(const cx<T>* __restrict__ fin, const cx<double>* __restrict__ gin,
+mpa_adjoint_block_kernel(const cx<T>* __restrict__ fin, const cx<double>* __restrict__ gin,
                          cx<double>* __restrict__ g_blk, double* __restrict__ partial,
                          cx<T>* __restrict__ node_store, cx<double>* __restrict__ last_store,
                          const int2* __restrict__ items, int n_items, const long long* __restrict__ offset,
-                         const long long* __restrict__ len, const double* __restrict__ sigma_scale, int core,
-                         int halo, const cx<T>* __restrict__ phase, const cx<double>* __restrict__ phase_last,
-                         const T* __restrict__ node_scale, const cx<T>* __restrict__ tw,
-                         const cx<double>* __restrict__ tw64, const double* __restrict__ taper,
-                         const cx<double>* __restrict__ mask_grad, int M, double sigma_span, double out_scale,
-                         double w1, double dz) {
+                         const long long* __restrict__ len, const double* __restrict__ sigma_scale,
+                         long long n_field, int core, int halo, const cx<T>* __restrict__ phase,
+                         const cx<double>* __restrict__ phase_last, const T* __restrict__ node_scale,
+                         const cx<T>* __restrict__ tw, const cx<double>* __restrict__ tw64,
+                         const double* __restrict__ taper, const cx<double>* __restrict__ mask_grad, int M,
+                         double sigma_span, double out_scale, double w1, double dz) {
     __shared__ cx<double> lds64[lds_elems<B>()];
     cx<T>* __restrict__ store = node_store + (size_t)blockIdx.x * NIT * M * 3 * B;
     cx<double>* __restrict__ last = last_store + (size_t)blockIdx.x * B;
     for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
-        const int2 it = items[w];
-        const cx<T>* __restrict__ in = fin + offset[it.x];
-        const cx<double>* __restrict__ g_out = gin + offset[it.x];
-        const long long n = len[it.x];
-        const long long c0 = (long long)it.y * core;
-        const T sigma = T(sigma_span * sigma_scale[it.x]);
+        long long base = 0, n = n_field;
+        int blk = w;
+        double sc = 1.0;
+        if (items) {
+            const int2 it = items[w];
+            base = offset[it.x];
+            n = len[it.x];
+            blk = it.y;
+            sc = sigma_scale[it.x];
+        }
+        const cx<T>* __restrict__ in = fin + base;
+        const cx<double>* __restrict__ g_out = gin + base;
+        const long long c0 = (long long)blk * core;
+        const T sigma = T(sigma_span * sc);
         cx<double>* __restrict__ g_item = g_blk + (size_t)w * B;
         double* __restrict__ part = partial + (size_t)w * 3;
         int thread = threadIdx.x;
@@ -124,18 +114,38 @@ mpa_adjoint_batch_kernel(const cx<T>* __restrict__ fin, const cx<double>* __rest
     }
 }
 
-// g_in[i] = sum over the windows b containing sample i of g_blk[b][i - (b C - H) mod N];
-// workgroup 0 also adds the per-block parameter derivatives (in block order)
-// to param_grad[q * n_seg + span], q = 0 (sigma), 1 (beta2), 2 (beta3).
+// g_in[i] = sum over the windows b containing sample i of g_blk[b][i - (b C - H) mod N],
+// per field of a batch (offset != nullptr: instance by binary search over the
+// offsets, its items from item_base); workgroup 0 also adds the work items'
+// parameter derivatives (in item order; sigma weighted by the instance's
+// scale) to param_grad[q * n_seg + span], q = 0 (sigma), 1 (beta2), 2 (beta3).
 __global__ void adjoint_gather_kernel(const cx<double>* __restrict__ g_blk, cx<double>* __restrict__ g_in,
-                                      long long n, int B, int core, int halo, int n_blocks,
-                                      const double* __restrict__ partial, double* __restrict__ param_grad,
-                                      int n_seg, int span) {
+                                      long long count, int B, int core, int halo, int n_blocks_field,
+                                      const long long* __restrict__ offset, const long long* __restrict__ len,
+                                      const int* __restrict__ item_base, int n_inst,
+                                      const int2* __restrict__ items, const double* __restrict__ sigma_scale,
+                                      int n_items, const double* __restrict__ partial,
+                                      double* __restrict__ param_grad, int n_seg, int span) {
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        long long li = i, n = count;
+        long long first = 0;
+        int n_blocks = n_blocks_field;
+        if (offset) {
+            int lo = 0, hi = n_inst - 1;               // the last instance starting at or before i
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (offset[mid] <= i) lo = mid;
+                else hi = mid - 1;
+            }
+            li = i - offset[lo];
+            n = len[lo];
+            n_blocks = (int)((n + core - 1) / core);
+            first = item_base[lo];
+        }
         cx<double> acc = {0.0, 0.0};
         for (int k = -1; k <= 1; ++k) {
-            const long long ip = i + k * n;           // the sample's position relative to the windows
+            const long long ip = li + k * n;          // the sample's position relative to the windows
             // windows b with b C - H <= ip < b C - H + B
             long long hi = ip + halo;
             long long lo = ip + halo - B;
@@ -145,7 +155,7 @@ __global__ void adjoint_gather_kernel(const cx<double>* __restrict__ g_blk, cx<d
             if (hi > n_blocks - 1) hi = n_blocks - 1;
             for (long long b = lo; b <= hi; ++b) {
                 const long long t = ip - (b * core - halo);
-                acc = acc + g_blk[b * B + t];
+                acc = acc + g_blk[(first + b) * B + t];
             }
         }
         g_in[i] = acc;
@@ -154,8 +164,12 @@ __global__ void adjoint_gather_kernel(const cx<double>* __restrict__ g_blk, cx<d
         __shared__ double red[3][256];
         const int tid = threadIdx.x;
         double s[3] = {0.0, 0.0, 0.0};
-        for (int b = tid; b < n_blocks; b += blockDim.x)
-            for (int q = 0; q < 3; ++q) s[q] += partial[(size_t)b * 3 + q];
+        for (int w = tid; w < n_items; w += blockDim.x) {
+            const double f = items ? sigma_scale[items[w].x] : 1.0;
+            s[0] += partial[(size_t)w * 3] * f;
+            s[1] += partial[(size_t)w * 3 + 1];
+            s[2] += partial[(size_t)w * 3 + 2];
+        }
         for (int q = 0; q < 3; ++q) red[q][tid] = s[q];
         for (int h = blockDim.x / 2; h > 0; h >>= 1) {
             __syncthreads();
@@ -181,14 +195,20 @@ __global__ void zero_kernel(double* __restrict__ p, long long count) {
 
 template <typename T, int B, int NIT>
 static hipError_t adjoint_typed(const AdjointStepArgs& a) {
-    hipLaunchKernelGGL((mpa_adjoint_block_kernel<T, B, NIT>), dim3(a.n_blocks), dim3(B / PTS), 0, a.stream,
+    const BatchItems* bt = a.batch;
+    const int n_items = bt ? bt->n_items : a.n_blocks;
+    const int grid = bt ? bt->grid : a.n_blocks;
+    hipLaunchKernelGGL((mpa_adjoint_block_kernel<T, B, NIT>), dim3(grid), dim3(B / PTS), 0, a.stream,
                        static_cast<const cx<T>*>(a.in), static_cast<const cx<double>*>(a.g_out),
                        static_cast<cx<double>*>(a.g_blk), a.partial, static_cast<cx<T>*>(a.node_store),
-                       static_cast<cx<double>*>(a.last_store), (long long)a.n, a.core, a.halo,
+                       static_cast<cx<double>*>(a.last_store), bt ? static_cast<const int2*>(bt->items) : nullptr,
+                       n_items, bt ? static_cast<const long long*>(bt->offset) : nullptr,
+                       bt ? static_cast<const long long*>(bt->len) : nullptr,
+                       bt ? static_cast<const double*>(bt->sigma_scale) : nullptr, (long long)a.n, a.core, a.halo,
                        static_cast<const cx<T>*>(a.phase), static_cast<const cx<double>*>(a.phase_last),
                        static_cast<const T*>(a.node_scale), static_cast<const cx<T>*>(a.twiddle),
                        static_cast<const cx<double>*>(a.twiddle64), static_cast<const double*>(a.taper),
-                       static_cast<const cx<double>*>(a.mask_grad), a.M, T(a.sigma), a.out_scale, a.w1, a.dz);
+                       static_cast<const cx<double>*>(a.mask_grad), a.M, a.sigma, a.out_scale, a.w1, a.dz);
     return hipGetLastError();
 }
 
@@ -220,15 +240,20 @@ hipError_t launch_adjoint_step(const AdjointStepArgs& a) {
     return a.precision == 0 ? adjoint_b<float>(a) : adjoint_b<double>(a);
 }
 
-hipError_t launch_adjoint_gather(const void* g_blk, void* g_in, int64_t n, int block, int core, int halo,
-                                 int n_blocks, const double* partial, double* param_grad, int n_seg, int span,
-                                 hipStream_t stream) {
+hipError_t launch_adjoint_gather(const AdjointGatherArgs& a) {
     const int tpb = 256;
-    const long long want = (n + tpb - 1) / tpb;
+    const long long want = (a.count + tpb - 1) / tpb;
     const unsigned grid = (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
-    hipLaunchKernelGGL(adjoint_gather_kernel, dim3(grid), dim3(tpb), 0, stream,
-                       static_cast<const cx<double>*>(g_blk), static_cast<cx<double>*>(g_in), (long long)n, block,
-                       core, halo, n_blocks, partial, param_grad, n_seg, span);
+    const BatchItems* bt = a.batch;
+    hipLaunchKernelGGL(adjoint_gather_kernel, dim3(grid), dim3(tpb), 0, a.stream,
+                       static_cast<const cx<double>*>(a.g_blk), static_cast<cx<double>*>(a.g_in),
+                       (long long)a.count, a.block, a.core, a.halo, a.n_blocks,
+                       bt ? static_cast<const long long*>(bt->offset) : nullptr,
+                       bt ? static_cast<const long long*>(bt->len) : nullptr,
+                       static_cast<const int*>(a.item_base), a.n_inst,
+                       bt ? static_cast<const int2*>(bt->items) : nullptr,
+                       bt ? static_cast<const double*>(bt->sigma_scale) : nullptr, bt ? bt->n_items : a.n_blocks,
+                       a.partial, a.param_grad, a.n_seg, a.span);
     return hipGetLastError();
 }
 

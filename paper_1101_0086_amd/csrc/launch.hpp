@@ -56,13 +56,13 @@ hipError_t launch_copy_field(const void* src, void* dst, int64_t count, int prec
 
 // Reverse pass of one long step over every block of one field.
 struct AdjointStepArgs {
-    const void* in;          // field at z0 of the long step (plan precision)
-    const void* g_out;       // FP64 complex N: gradient with respect to the field at z0 + L
-    void* g_blk;             // FP64 complex n_blocks x B: each window's input gradient (tapered)
-    double* partial;         // n_blocks x 3: d/dsigma, d/dbeta2, d/dbeta3 of each block
-    void* node_store;        // n_blocks x n_iter x M x 3 x B complex (plan precision)
-    void* last_store;        // n_blocks x B FP64 complex
-    int64_t n;
+    const void* in;          // fields at z0 of the long step (plan precision)
+    const void* g_out;       // FP64 complex: gradient with respect to the fields at z0 + L
+    void* g_blk;             // FP64 complex, work items x B: each window's input gradient (tapered)
+    double* partial;         // work items x 3: d/dsigma, d/dbeta2, d/dbeta3 of each item
+    void* node_store;        // workgroups x n_iter x M x 3 x B complex (plan precision)
+    void* last_store;        // workgroups x B FP64 complex
+    int64_t n;               // samples of the field (single field)
     int32_t block, halo, core, n_blocks;
     const void* phase;
     const void* phase_last;
@@ -76,15 +76,29 @@ struct AdjointStepArgs {
     double w1;               // 2 pi / (B dt): block frequency spacing
     double dz;               // L / M
     int32_t precision;
+    const BatchItems* batch; // concatenated fields (work list, grid), or nullptr: one field of n blocks
     hipStream_t stream;
 };
 
 hipError_t launch_adjoint_step(const AdjointStepArgs& a);
-// g_in[i] = sum of g_blk over the windows containing sample i; adds the
-// blocks' parameter derivatives to param_grad[q * n_seg + span].
-hipError_t launch_adjoint_gather(const void* g_blk, void* g_in, int64_t n, int block, int core, int halo,
-                                 int n_blocks, const double* partial, double* param_grad, int n_seg, int span,
-                                 hipStream_t stream);
+
+// g_in[i] = sum of g_blk over the windows containing sample i (per field of a
+// batch); adds the work items' parameter derivatives to
+// param_grad[q * n_seg + span] (sigma weighted by each instance's scale).
+struct AdjointGatherArgs {
+    const void* g_blk;
+    void* g_in;
+    int64_t count;           // samples (all fields of a batch)
+    int32_t block, core, halo, n_blocks;   // n_blocks: single field
+    const double* partial;
+    double* param_grad;
+    int32_t n_seg, span;
+    const BatchItems* batch; // or nullptr
+    const void* item_base;   // batch: int32 first work item of each instance
+    int32_t n_inst;
+    hipStream_t stream;
+};
+hipError_t launch_adjoint_gather(const AdjointGatherArgs& a);
 // complex conversion between precisions (0: FP32, 1: FP64); FP32 -> FP32 is not offered
 hipError_t launch_convert(const void* src, int src_precision, void* dst, int dst_precision, int64_t count,
                           hipStream_t stream);

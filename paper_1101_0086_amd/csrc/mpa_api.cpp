@@ -201,6 +201,28 @@ struct DevBuf {
     }
 };
 
+// Reverse-pass workspace, allocated by the first reverse pass and grown as needed.
+struct AdjWork {
+    void* node = nullptr;       // workgroups x n_iter x M x 3 x B complex (plan precision)
+    void* last = nullptr;       // workgroups x B FP64 complex
+    void* gblk = nullptr;       // work items x B FP64 complex
+    void* partial = nullptr;    // work items x 3 doubles
+    void* ga = nullptr;         // FP64 complex fields: the gradient carried between long steps
+    void* gb = nullptr;
+    void* inputs = nullptr;     // inputs_cap fields: inputs of the long steps being reversed
+    int64_t inputs_cap = 0;
+    void* subs = nullptr;       // subs_cap fields: inner checkpoints of a long map period
+    int64_t subs_cap = 0;
+    void release() {
+        for (void** q : {&node, &last, &gblk, &partial, &ga, &gb, &inputs, &subs})
+            if (*q) {
+                (void)hipFree(*q);
+                *q = nullptr;
+            }
+        inputs_cap = subs_cap = 0;
+    }
+};
+
 }  // namespace
 
 struct mpa_plan {
@@ -236,18 +258,9 @@ struct mpa_plan {
     void* w_cur = nullptr;
     void* w_work = nullptr;
     void* w_work64 = nullptr;
-    // reverse-pass workspace, allocated by the first mpa_adjoint call
-    void* adj_node = nullptr;           // n_blocks x n_iter x M x 3 x B complex
-    void* adj_last = nullptr;           // n_blocks x B FP64 complex
-    void* adj_gblk = nullptr;           // n_blocks x B FP64 complex
-    void* adj_partial = nullptr;        // n_blocks x 3 doubles
-    void* adj_ga = nullptr;             // N FP64 complex (gradient carried between long steps)
-    void* adj_gb = nullptr;             // N FP64 complex
+    // reverse pass: workspace of the plan's own field, roll-off derivative tables
+    AdjWork adj;
     void* adj_mask = nullptr;           // n_seg x 2 x B FP64 complex (blocked plans)
-    void* adj_inputs = nullptr;         // adj_inputs_cap fields: inputs of the long steps being reversed
-    int64_t adj_inputs_cap = 0;
-    void* adj_subs = nullptr;           // adj_subs_cap fields: inner checkpoints of a long map period
-    int64_t adj_subs_cap = 0;
 };
 
 static void plan_free(mpa_plan* p) {
@@ -255,12 +268,12 @@ static void plan_free(mpa_plan* p) {
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
     for (void* q : {p->phase, p->phase_last, p->node_scale, p->twiddle, p->twiddle64, p->taper, p->work,
-                    p->adj_node, p->adj_last, p->adj_gblk, p->adj_partial, p->adj_ga, p->adj_gb, p->adj_mask,
-                    p->adj_inputs, p->adj_subs, p->nodes.psi0, p->nodes.half_u0, p->nodes.u[0], p->nodes.u[1],
+                    p->adj_mask, p->nodes.psi0, p->nodes.half_u0, p->nodes.u[0], p->nodes.u[1],
                     p->w_psi0, p->w_sums, p->w_cur, p->w_work, p->w_work64})
         if (q) (void)hipFree(q);
     for (void* q : p->w_tw)
         if (q) (void)hipFree(q);
+    p->adj.release();
     delete p;
 }
 
@@ -695,8 +708,25 @@ static int grid_range(const mpa_plan* p, double z0, double z1, int64_t* m0, int6
     return MPA_OK;
 }
 
+// What a reverse pass runs over: the plan's own field, or the concatenated
+// fields of a batch with the work list its kernels walk.
+struct AdjTarget {
+    mpa_plan* p;                        // tables and schedule
+    const mpa::BatchItems* batch;       // nullptr: the plan's own field
+    const void* item_base;              // batch: int32 first work item of each instance
+    int32_t n_inst;
+    int64_t count;                      // complex samples (all fields)
+    int32_t n_items, grid;              // work items per long step, reverse-kernel workgroups
+    void* work;                         // count samples (forward march)
+    AdjWork* w;
+};
+
+static AdjTarget single_target(mpa_plan* p) {
+    return {p, nullptr, nullptr, 0, p->prm.n, p->n_blocks, p->n_blocks, p->work, &p->adj};
+}
+
 // Grow-only device buffer of `count` fields.
-static int reserve_fields(mpa_plan* p, void** buf, int64_t* cap, int64_t count) {
+static int reserve_fields(const AdjTarget& t, void** buf, int64_t* cap, int64_t count) {
     if (count <= *cap) return MPA_OK;
     if (*buf) {
         (void)hipDeviceSynchronize();
@@ -704,7 +734,7 @@ static int reserve_fields(mpa_plan* p, void** buf, int64_t* cap, int64_t count) 
         *buf = nullptr;
         *cap = 0;
     }
-    if (hipMalloc(buf, (size_t)count * p->prm.n * p->elem) != hipSuccess) {
+    if (hipMalloc(buf, (size_t)count * t.count * t.p->elem) != hipSuccess) {
         *buf = nullptr;
         return fail(MPA_ENOMEM, "adjoint: allocation of %lld fields failed", (long long)count);
     }
@@ -713,25 +743,24 @@ static int reserve_fields(mpa_plan* p, void** buf, int64_t* cap, int64_t count) 
 }
 
 // Fixed part of the reverse-pass workspace and the roll-off derivative tables.
-static int adjoint_setup(mpa_plan* p) {
-    if (p->adj_node) return MPA_OK;
+static int adjoint_setup(const AdjTarget& t) {
+    mpa_plan* p = t.p;
+    AdjWork* w = t.w;
     const int B = p->block, M = p->prm.M, nit = p->prm.n_iter, S = (int)p->beta2.size();
-    const size_t nb = (size_t)p->n_blocks;
-    const bool ok = hipMalloc(&p->adj_node, nb * nit * M * 3 * B * p->elem) == hipSuccess &&
-                    hipMalloc(&p->adj_last, nb * B * 16) == hipSuccess &&
-                    hipMalloc(&p->adj_gblk, nb * B * 16) == hipSuccess &&
-                    hipMalloc(&p->adj_partial, nb * 3 * sizeof(double)) == hipSuccess &&
-                    hipMalloc(&p->adj_ga, (size_t)p->prm.n * 16) == hipSuccess &&
-                    hipMalloc(&p->adj_gb, (size_t)p->prm.n * 16) == hipSuccess;
-    if (!ok) {
-        for (void** q : {&p->adj_node, &p->adj_last, &p->adj_gblk, &p->adj_partial, &p->adj_ga, &p->adj_gb})
-            if (*q) {
-                (void)hipFree(*q);
-                *q = nullptr;
-            }
-        return fail(MPA_ENOMEM, "adjoint: workspace allocation failed");
+    if (!w->node) {
+        const size_t wg = (size_t)t.grid, ni = (size_t)t.n_items;
+        const bool ok = hipMalloc(&w->node, wg * nit * M * 3 * B * p->elem) == hipSuccess &&
+                        hipMalloc(&w->last, wg * B * 16) == hipSuccess &&
+                        hipMalloc(&w->gblk, ni * B * 16) == hipSuccess &&
+                        hipMalloc(&w->partial, ni * 3 * sizeof(double)) == hipSuccess &&
+                        hipMalloc(&w->ga, (size_t)t.count * 16) == hipSuccess &&
+                        hipMalloc(&w->gb, (size_t)t.count * 16) == hipSuccess;
+        if (!ok) {
+            w->release();
+            return fail(MPA_ENOMEM, "adjoint: workspace allocation failed");
+        }
     }
-    if (p->halo > 0) {
+    if (p->halo > 0 && !p->adj_mask) {
         // e^{i beta_M(omega)} times the derivatives of the block roll-off with respect to
         // beta2 and beta3: the roll-off is d((g - 0.35) / 0.15) d((q - 0.8) / 0.1) with
         // g = |u| L / (halo dt), u = beta2 omega + beta3 omega^2 / 2, q = |omega| dt / pi,
@@ -740,7 +769,7 @@ static int adjoint_setup(mpa_plan* p) {
         const double bdt = B * p->prm.dt;
         const double w1 = 2.0 * pi / bdt;
         const double hd = p->prm.L / (p->halo * p->prm.dt);
-        std::vector<double> t((size_t)S * 4 * B);
+        std::vector<double> tab((size_t)S * 4 * B);
         auto drop = [&](double x) { return x <= 0 ? 1.0 : (x >= 1 ? 0.0 : 0.5 * (1.0 + std::cos(pi * x))); };
         auto slope = [&](double x) { return (x > 0 && x < 1) ? -0.5 * pi * std::sin(pi * x) : 0.0; };
         for (int s = 0; s < S; ++s) {
@@ -757,34 +786,39 @@ static int adjoint_setup(mpa_plan* p) {
                 const double turns = c2 * kp * kp + c3 * kp * kp * kp;
                 const double f = turns - std::nearbyint(turns);
                 const double c = std::cos(2.0 * pi * f), sn = std::sin(2.0 * pi * f);
-                double* row = t.data() + (size_t)s * 4 * B;
+                double* row = tab.data() + (size_t)s * 4 * B;
                 row[2 * k] = dm2 * c;
                 row[2 * k + 1] = dm2 * sn;
                 row[2 * B + 2 * k] = dm3 * c;
                 row[2 * B + 2 * k + 1] = dm3 * sn;
             }
         }
-        if (hipMalloc(&p->adj_mask, t.size() * 8) != hipSuccess ||
-            hipMemcpy(p->adj_mask, t.data(), t.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+        void* d = nullptr;
+        if (hipMalloc(&d, tab.size() * 8) != hipSuccess) return fail(MPA_ENOMEM, "adjoint: table allocation failed");
+        if (hipMemcpy(d, tab.data(), tab.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(d);
             return fail(MPA_EDEVICE, "adjoint: roll-off derivative table upload failed");
+        }
+        p->adj_mask = d;
     }
     return MPA_OK;
 }
 
 // Reverse pass of long step m: g_in (FP64) from g_out (FP64), adding the
 // step's parameter derivatives to param_grad.
-static int adjoint_long_step(mpa_plan* p, const void* in, const void* g_out, void* g_in, int64_t m,
+static int adjoint_long_step(const AdjTarget& t, const void* in, const void* g_out, void* g_in, int64_t m,
                              double* param_grad, hipStream_t stream) {
+    mpa_plan* p = t.p;
     const int s = p->sched.span_of(m);
     const int M = p->prm.M;
     const double gain = p->sched.amp_after(m) ? p->lumped : 1.0;
     mpa::AdjointStepArgs a;
     a.in = in;
     a.g_out = g_out;
-    a.g_blk = p->adj_gblk;
-    a.partial = (double*)p->adj_partial;
-    a.node_store = p->adj_node;
-    a.last_store = p->adj_last;
+    a.g_blk = t.w->gblk;
+    a.partial = (double*)t.w->partial;
+    a.node_store = t.w->node;
+    a.last_store = t.w->last;
     a.n = p->prm.n;
     a.block = p->block;
     a.halo = p->halo;
@@ -804,29 +838,139 @@ static int adjoint_long_step(mpa_plan* p, const void* in, const void* g_out, voi
     a.w1 = 2.0 * 3.14159265358979323846 / (p->block * p->prm.dt);
     a.dz = p->prm.L / M;
     a.precision = p->prm.precision;
+    a.batch = t.batch;
     a.stream = stream;
     hipError_t e = mpa::launch_adjoint_step(a);
     if (e != hipSuccess) return fail(MPA_EDEVICE, "adjoint step launch failed: %s", hipGetErrorString(e));
-    e = mpa::launch_adjoint_gather(p->adj_gblk, g_in, p->prm.n, p->block, p->core, p->halo, p->n_blocks,
-                                   (const double*)p->adj_partial, param_grad, (int)p->beta2.size(), s, stream);
+    mpa::AdjointGatherArgs g;
+    g.g_blk = t.w->gblk;
+    g.g_in = g_in;
+    g.count = t.count;
+    g.block = p->block;
+    g.core = p->core;
+    g.halo = p->halo;
+    g.n_blocks = p->n_blocks;
+    g.partial = (const double*)t.w->partial;
+    g.param_grad = param_grad;
+    g.n_seg = (int)p->beta2.size();
+    g.span = s;
+    g.batch = t.batch;
+    g.item_base = t.item_base;
+    g.n_inst = t.n_inst;
+    g.stream = stream;
+    e = mpa::launch_adjoint_gather(g);
     if (e != hipSuccess) return fail(MPA_EDEVICE, "adjoint gather launch failed: %s", hipGetErrorString(e));
     return MPA_OK;
 }
 
-static void* field_at(const mpa_plan* p, const void* base, int64_t i) {
-    return (char*)base + (size_t)i * p->prm.n * p->elem;
+static void* field_at(const AdjTarget& t, const void* base, int64_t i) {
+    return (char*)base + (size_t)i * t.count * t.p->elem;
 }
 
 // Run `count` long steps from m, reading `src` and leaving the result in `dst`,
 // using inputs slots 0.. as intermediates (src may be slot 0).
-static int advance(mpa_plan* p, const void* src, void* dst, int64_t m, int64_t count, hipStream_t stream) {
+static int advance(const AdjTarget& t, const void* src, void* dst, int64_t m, int64_t count, hipStream_t stream) {
     const void* cur = src;
     for (int64_t i = 0; i < count; ++i) {
-        void* out = (i == count - 1) ? dst : field_at(p, p->adj_inputs, (i + 1) % 2);
-        int st = launch_long_step(p, cur, out, m + i, stream);
+        void* out = (i == count - 1) ? dst : field_at(t, t.w->inputs, (i + 1) % 2);
+        int st = launch_long_step(t.p, cur, out, m + i, stream, t.batch);
         if (st) return st;
         cur = out;
     }
+    return MPA_OK;
+}
+
+// March over [z0, z1], copying the field(s) at the start of every segment into checkpoints.
+static int forward_checkpointed(const AdjTarget& t, void* field, double z0, double z1, void* checkpoints,
+                                hipStream_t s) {
+    mpa_plan* p = t.p;
+    int64_t m0, m1;
+    int st = grid_range(p, z0, z1, &m0, &m1);
+    if (st) return st;
+    const std::vector<int64_t> seg = segment_starts(p, m0, m1);
+    if (!seg.empty() && !checkpoints) return fail(MPA_EINVAL, "NULL checkpoints");
+    if (hipSetDevice(p->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
+    for (size_t k = 0; k < seg.size(); ++k) {
+        const int64_t a = seg[k], b = (k + 1 < seg.size()) ? seg[k + 1] : m1;
+        if (mpa::launch_copy_field(field, field_at(t, checkpoints, (int64_t)k), t.count, p->prm.precision, s) !=
+            hipSuccess)
+            return fail(MPA_EDEVICE, "checkpoint copy failed");
+        st = march(p, field, t.work, t.count, a * p->prm.L, b * p->prm.L, s, t.batch);
+        if (st) return st;
+    }
+    return MPA_OK;
+}
+
+// Reverse pass over [z0, z1] from the forward checkpoints (see mpa_adjoint).
+static int reverse(const AdjTarget& t, const void* checkpoints, void* grad, double z0, double z1,
+                   double* param_grad, int64_t store_steps, hipStream_t s) {
+    mpa_plan* p = t.p;
+    if (!p->sched.straddles.empty())
+        return fail(MPA_EUNSUPPORTED, "the reverse pass needs long steps that stay within one span");
+    if (p->window) return fail(MPA_EUNSUPPORTED, "the reverse pass needs B <= 4096 (time blocks above that)");
+    if (store_steps < 0) return fail(MPA_EINVAL, "store_steps must be >= 0");
+    int64_t m0, m1;
+    int st = grid_range(p, z0, z1, &m0, &m1);
+    if (st) return st;
+    const std::vector<int64_t> seg = segment_starts(p, m0, m1);
+    if (!seg.empty() && !checkpoints) return fail(MPA_EINVAL, "NULL checkpoints");
+    if (hipSetDevice(p->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
+    const int n_seg = (int)p->beta2.size();
+    if (mpa::launch_zero(param_grad, 3 * (int64_t)n_seg, s) != hipSuccess)
+        return fail(MPA_EDEVICE, "param_grad clear failed");
+    if (seg.empty()) return MPA_OK;
+    st = adjoint_setup(t);
+    if (st) return st;
+
+    // the longest segment decides how many step inputs are kept at once
+    int64_t longest = 0;
+    for (size_t k = 0; k < seg.size(); ++k)
+        longest = std::max(longest, ((k + 1 < seg.size()) ? seg[k + 1] : m1) - seg[k]);
+    const int64_t field_bytes = t.count * (int64_t)p->elem;
+    int64_t Q = store_steps;
+    if (Q == 0) Q = longest * field_bytes <= MPA_ADJOINT_STORE_BYTES ? longest : (int64_t)std::ceil(std::sqrt((double)longest));
+    Q = std::max<int64_t>(1, std::min(Q, longest));
+    AdjWork* w = t.w;
+    st = reserve_fields(t, &w->inputs, &w->inputs_cap, std::max<int64_t>(Q, 2));
+    if (st) return st;
+    const int64_t n_sub = (longest + Q - 1) / Q;
+    if (n_sub > 1) {
+        st = reserve_fields(t, &w->subs, &w->subs_cap, n_sub);
+        if (st) return st;
+    }
+
+    void* ga = w->ga;
+    void* gb = w->gb;
+    if (mpa::launch_convert(grad, p->prm.precision, ga, MPA_C128, t.count, s) != hipSuccess)
+        return fail(MPA_EDEVICE, "gradient conversion failed");
+    for (int64_t k = (int64_t)seg.size() - 1; k >= 0; --k) {
+        const int64_t a = seg[k], b = (k + 1 < (int64_t)seg.size()) ? seg[k + 1] : m1;
+        const void* ck = field_at(t, checkpoints, k);
+        const int64_t P = b - a, subs = (P + Q - 1) / Q;
+        // inner checkpoints at a + j Q (j >= 1) when the segment is longer than Q
+        for (int64_t j = 1; j < subs; ++j) {
+            st = advance(t, j == 1 ? ck : field_at(t, w->subs, j - 1), field_at(t, w->subs, j), a + (j - 1) * Q, Q, s);
+            if (st) return st;
+        }
+        for (int64_t j = subs - 1; j >= 0; --j) {
+            const int64_t s0 = a + j * Q, q = std::min(Q, b - s0);
+            const void* start = j == 0 ? ck : field_at(t, w->subs, j);
+            // inputs of steps s0 .. s0 + q - 1 in slots 0 .. q - 1
+            if (mpa::launch_copy_field(start, w->inputs, t.count, p->prm.precision, s) != hipSuccess)
+                return fail(MPA_EDEVICE, "copy failed");
+            for (int64_t i = 0; i + 1 < q; ++i) {
+                st = launch_long_step(p, field_at(t, w->inputs, i), field_at(t, w->inputs, i + 1), s0 + i, s, t.batch);
+                if (st) return st;
+            }
+            for (int64_t i = q - 1; i >= 0; --i) {
+                st = adjoint_long_step(t, field_at(t, w->inputs, i), ga, gb, s0 + i, param_grad, s);
+                if (st) return st;
+                std::swap(ga, gb);
+            }
+        }
+    }
+    if (mpa::launch_convert(ga, MPA_C128, grad, p->prm.precision, t.count, s) != hipSuccess)
+        return fail(MPA_EDEVICE, "gradient conversion failed");
     return MPA_OK;
 }
 
@@ -842,95 +986,13 @@ int mpa_checkpoint_count(const mpa_plan* p, double z0, double z1, int64_t* count
 int mpa_propagate_checkpointed(mpa_plan* p, void* field, double z0, double z1, void* checkpoints,
                                void* stream) {
     if (!p || !field) return fail(MPA_EINVAL, "NULL plan or field");
-    int64_t m0, m1;
-    int st = grid_range(p, z0, z1, &m0, &m1);
-    if (st) return st;
-    const std::vector<int64_t> seg = segment_starts(p, m0, m1);
-    if (!seg.empty() && !checkpoints) return fail(MPA_EINVAL, "NULL checkpoints");
-    if (hipSetDevice(p->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
-    hipStream_t s = (hipStream_t)stream;
-    for (size_t k = 0; k < seg.size(); ++k) {
-        const int64_t a = seg[k], b = (k + 1 < seg.size()) ? seg[k + 1] : m1;
-        if (mpa::launch_copy_field(field, field_at(p, checkpoints, (int64_t)k), p->prm.n, p->prm.precision, s) !=
-            hipSuccess)
-            return fail(MPA_EDEVICE, "checkpoint copy failed");
-        st = march(p, field, p->work, p->prm.n, a * p->prm.L, b * p->prm.L, s, nullptr);
-        if (st) return st;
-    }
-    return MPA_OK;
+    return forward_checkpointed(single_target(p), field, z0, z1, checkpoints, (hipStream_t)stream);
 }
 
 int mpa_adjoint(mpa_plan* p, const void* checkpoints, void* grad, double z0, double z1, double* param_grad,
                 int64_t store_steps, void* stream) {
     if (!p || !grad || !param_grad) return fail(MPA_EINVAL, "NULL plan, grad or param_grad");
-    if (!p->sched.straddles.empty())
-        return fail(MPA_EUNSUPPORTED, "the reverse pass needs long steps that stay within one span");
-    if (p->window) return fail(MPA_EUNSUPPORTED, "the reverse pass needs B <= 4096 (time blocks above that)");
-    if (store_steps < 0) return fail(MPA_EINVAL, "store_steps must be >= 0");
-    int64_t m0, m1;
-    int st = grid_range(p, z0, z1, &m0, &m1);
-    if (st) return st;
-    const std::vector<int64_t> seg = segment_starts(p, m0, m1);
-    if (!seg.empty() && !checkpoints) return fail(MPA_EINVAL, "NULL checkpoints");
-    if (hipSetDevice(p->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
-    hipStream_t s = (hipStream_t)stream;
-    const int n_seg = (int)p->beta2.size();
-    if (mpa::launch_zero(param_grad, 3 * (int64_t)n_seg, s) != hipSuccess)
-        return fail(MPA_EDEVICE, "param_grad clear failed");
-    if (seg.empty()) return MPA_OK;
-    st = adjoint_setup(p);
-    if (st) return st;
-
-    // the longest segment decides how many step inputs are kept at once
-    int64_t longest = 0;
-    for (size_t k = 0; k < seg.size(); ++k)
-        longest = std::max(longest, ((k + 1 < seg.size()) ? seg[k + 1] : m1) - seg[k]);
-    const int64_t field_bytes = p->prm.n * (int64_t)p->elem;
-    int64_t Q = store_steps;
-    if (Q == 0) Q = longest * field_bytes <= MPA_ADJOINT_STORE_BYTES ? longest : (int64_t)std::ceil(std::sqrt((double)longest));
-    Q = std::max<int64_t>(1, std::min(Q, longest));
-    st = reserve_fields(p, &p->adj_inputs, &p->adj_inputs_cap, std::max<int64_t>(Q, 2));
-    if (st) return st;
-    const int64_t n_sub = (longest + Q - 1) / Q;
-    if (n_sub > 1) {
-        st = reserve_fields(p, &p->adj_subs, &p->adj_subs_cap, n_sub);
-        if (st) return st;
-    }
-
-    void* ga = p->adj_ga;
-    void* gb = p->adj_gb;
-    if (mpa::launch_convert(grad, p->prm.precision, ga, MPA_C128, p->prm.n, s) != hipSuccess)
-        return fail(MPA_EDEVICE, "gradient conversion failed");
-    for (int64_t k = (int64_t)seg.size() - 1; k >= 0; --k) {
-        const int64_t a = seg[k], b = (k + 1 < (int64_t)seg.size()) ? seg[k + 1] : m1;
-        const void* ck = field_at(p, checkpoints, k);
-        const int64_t P = b - a, subs = (P + Q - 1) / Q;
-        // inner checkpoints at a + j Q (j >= 1) when the segment is longer than Q
-        for (int64_t j = 1; j < subs; ++j) {
-            st = advance(p, j == 1 ? ck : field_at(p, p->adj_subs, j - 1), field_at(p, p->adj_subs, j),
-                         a + (j - 1) * Q, Q, s);
-            if (st) return st;
-        }
-        for (int64_t j = subs - 1; j >= 0; --j) {
-            const int64_t s0 = a + j * Q, q = std::min(Q, b - s0);
-            const void* start = j == 0 ? ck : field_at(p, p->adj_subs, j);
-            // inputs of steps s0 .. s0 + q - 1 in slots 0 .. q - 1
-            if (mpa::launch_copy_field(start, p->adj_inputs, p->prm.n, p->prm.precision, s) != hipSuccess)
-                return fail(MPA_EDEVICE, "copy failed");
-            for (int64_t i = 0; i + 1 < q; ++i) {
-                st = launch_long_step(p, field_at(p, p->adj_inputs, i), field_at(p, p->adj_inputs, i + 1), s0 + i, s);
-                if (st) return st;
-            }
-            for (int64_t i = q - 1; i >= 0; --i) {
-                st = adjoint_long_step(p, field_at(p, p->adj_inputs, i), ga, gb, s0 + i, param_grad, s);
-                if (st) return st;
-                std::swap(ga, gb);
-            }
-        }
-    }
-    if (mpa::launch_convert(ga, MPA_C128, grad, p->prm.precision, p->prm.n, s) != hipSuccess)
-        return fail(MPA_EDEVICE, "gradient conversion failed");
-    return MPA_OK;
+    return reverse(single_target(p), checkpoints, grad, z0, z1, param_grad, store_steps, (hipStream_t)stream);
 }
 
 // ---- batches of independent fields -------------------------------------------------
@@ -945,7 +1007,9 @@ struct mpa_batch_plan {
     void* d_offset = nullptr;
     void* d_len = nullptr;
     void* d_sigma = nullptr;
+    void* d_item_base = nullptr;        // int32 first work item of each instance
     void* work = nullptr;
+    AdjWork adj;                        // reverse-pass workspace
 };
 
 static void batch_free(mpa_batch_plan* b) {
@@ -954,8 +1018,9 @@ static void batch_free(mpa_batch_plan* b) {
         (void)hipSetDevice(b->base->device);
         (void)hipDeviceSynchronize();
     }
-    for (void* q : {b->d_items, b->d_offset, b->d_len, b->d_sigma, b->work})
+    for (void* q : {b->d_items, b->d_offset, b->d_len, b->d_sigma, b->d_item_base, b->work})
         if (q) (void)hipFree(q);
+    b->adj.release();
     plan_free(b->base);
     delete b;
 }
@@ -1000,8 +1065,9 @@ int mpa_batch_plan_create(const mpa_params* params, const mpa_map* map, const mp
         return st;
     }
     const int C = b->base->core;
-    std::vector<int> items;
+    std::vector<int> items, item_base;
     for (int i = 0; i < desc->count; ++i) {
+        item_base.push_back((int)(items.size() / 2));
         b->len.push_back(desc->n[i]);
         b->offset.push_back(b->total);
         b->sigma_scale.push_back(desc->sigma_scale ? desc->sigma_scale[i] : 1.0);
@@ -1019,6 +1085,7 @@ int mpa_batch_plan_create(const mpa_params* params, const mpa_map* map, const mp
               hipMalloc(&b->d_offset, b->offset.size() * 8) == hipSuccess &&
               hipMalloc(&b->d_len, b->len.size() * 8) == hipSuccess &&
               hipMalloc(&b->d_sigma, b->sigma_scale.size() * 8) == hipSuccess &&
+              hipMalloc(&b->d_item_base, item_base.size() * sizeof(int)) == hipSuccess &&
               hipMalloc(&b->work, (size_t)b->total * b->base->elem) == hipSuccess;
     if (!ok) {
         batch_free(b);
@@ -1027,7 +1094,9 @@ int mpa_batch_plan_create(const mpa_params* params, const mpa_map* map, const mp
     ok = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(b->d_offset, b->offset.data(), b->offset.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(b->d_len, b->len.data(), b->len.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(b->d_sigma, b->sigma_scale.data(), b->sigma_scale.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+         hipMemcpy(b->d_sigma, b->sigma_scale.data(), b->sigma_scale.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->d_item_base, item_base.data(), item_base.size() * sizeof(int), hipMemcpyHostToDevice) ==
+             hipSuccess;
     if (!ok) {
         batch_free(b);
         return fail(MPA_EDEVICE, "batch upload failed");
@@ -1058,6 +1127,28 @@ int mpa_batch_propagate(mpa_batch_plan* b, void* fields, double z0, double z1, v
     if (!b || !fields) return fail(MPA_EINVAL, "NULL batch plan or fields");
     if (hipSetDevice(b->base->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
     return march(b->base, fields, b->work, b->total, z0, z1, (hipStream_t)stream, &b->items);
+}
+
+static AdjTarget batch_target(mpa_batch_plan* b) {
+    return {b->base,           &b->items, b->d_item_base, (int32_t)b->len.size(), b->total, b->items.n_items,
+            b->items.grid,     b->work,   &b->adj};
+}
+
+int mpa_batch_checkpoint_count(const mpa_batch_plan* b, double z0, double z1, int64_t* count) {
+    if (!b) return fail(MPA_EINVAL, "NULL batch plan");
+    return mpa_checkpoint_count(b->base, z0, z1, count);
+}
+
+int mpa_batch_propagate_checkpointed(mpa_batch_plan* b, void* fields, double z0, double z1, void* checkpoints,
+                                     void* stream) {
+    if (!b || !fields) return fail(MPA_EINVAL, "NULL batch plan or fields");
+    return forward_checkpointed(batch_target(b), fields, z0, z1, checkpoints, (hipStream_t)stream);
+}
+
+int mpa_batch_adjoint(mpa_batch_plan* b, const void* checkpoints, void* grads, double z0, double z1,
+                      double* param_grad, int64_t store_steps, void* stream) {
+    if (!b || !grads || !param_grad) return fail(MPA_EINVAL, "NULL batch plan, grads or param_grad");
+    return reverse(batch_target(b), checkpoints, grads, z0, z1, param_grad, store_steps, (hipStream_t)stream);
 }
 
 // ---- captured launch sequences ----------------------------------------------------

@@ -104,6 +104,12 @@ def test_null_arguments_rejected():
     assert h.mpa_step(None, None, C.c_double(0.0), None) == L.MPA_EINVAL
     assert h.mpa_propagate(None, None, C.c_double(0.0), C.c_double(1.0), None) == L.MPA_EINVAL
     assert h.ss_propagate(None, None, C.c_double(0.0), C.c_double(1.0), None) == L.MPA_EINVAL
+    cnt = C.c_int64()
+    assert h.mpa_checkpoint_count(None, 0.0, 1.0, C.byref(cnt)) == L.MPA_EINVAL
+    assert h.mpa_batch_checkpoint_count(None, 0.0, 1.0, C.byref(cnt)) == L.MPA_EINVAL
+    assert h.mpa_adjoint(None, None, None, 0.0, 1.0, None, 0, None) == L.MPA_EINVAL
+    assert h.mpa_batch_adjoint(None, None, None, 0.0, 1.0, None, 0, None) == L.MPA_EINVAL
+    assert h.mpa_batch_propagate_checkpointed(None, None, 0.0, 1.0, None, None) == L.MPA_EINVAL
     out = C.c_void_p(123)
     assert h.mpa_plan_create(None, None, 0, C.byref(out)) == L.MPA_EINVAL and out.value is None
     assert h.mpa_plan_destroy(None) == L.MPA_OK

@@ -1,0 +1,118 @@
+"""Batched reverse pass (mpa_batch_propagate_checkpointed / mpa_batch_adjoint
+through the C ABI).
+
+* every instance's field gradient equals that of mpa_adjoint on a plan of its
+  own with the instance's sigma (bitwise: the reverse kernel runs the same
+  per-block arithmetic, only the work list and the grid differ), in both
+  precisions, over a range that crosses an amplifier and a map-period
+  boundary (two checkpoints), with and without inner checkpoints;
+* the shared parameter derivatives are the sum of the per-instance ones,
+  the sigma derivative weighted by each instance's sigma scale (the sums are
+  taken in another order, so to 1e-12 of their norm);
+* an FP64 batch matches the FP64 oracle's gradients instance by instance.
+
+Loss l = sum over instances of sum |A_i(z1) - target_i|^2, so
+G(A_i(z1)) = 2 (A_i(z1) - target_i).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.gpu_util import rel_l2, say, to_dev, to_host
+from workloads import Grid, dm_map
+from workloads.wdm import _fast_wdm_field
+
+pytestmark = pytest.mark.gpu
+
+DT = 10.0 / 1024
+BAND = 145.0
+
+
+def _case(ns, seed, block):
+    halo = block // 8
+    rate = O.halo_rate(BAND, 20.0, 0.1)
+    k = math.ceil(0.5 / (0.25 * halo * DT / rate))
+    L = 0.5 / k
+    rng = np.random.default_rng(seed)
+    fields = [_fast_wdm_field(Grid(n, DT), n // 1024, 8, "ook", np.random.default_rng(seed + i))
+              for i, n in enumerate(ns)]
+    g_out = [0.1 * (rng.normal(size=n) + 1j * rng.normal(size=n)) for n in ns]
+    return fields, g_out, halo, L
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("store_steps", [0, 2])
+def test_batch_adjoint_equals_single_plans(prec, store_steps):
+    import paper_1101_0086_amd as P
+    ns = [8192, 4096, 16384, 2048]
+    scales = [1.0, 0.5, 2.0, 0.8]
+    block = 2048
+    fields, g_out, halo, L = _case(ns, 5, block)
+    dmm = dm_map(beta3=0.1)
+    z0, z1 = 1.0 - 3 * L, 1.0 + 2 * L       # amplifier and period start at 1.0
+    say("batch adjoint vs single plans", prec, store_steps, ns)
+    bp = P.MPABatchPlan(ns, DT, dmm, L, 2, 2, block, halo, prec, BAND, sigma_scale=scales)
+    assert bp.checkpoint_count(z0, z1) == 2
+    x = to_dev(np.concatenate(fields), prec)
+    ck = bp.propagate_checkpointed(x, z0, z1)
+    g = to_dev(np.concatenate(g_out), prec)
+    pg = bp.adjoint(ck, g, z0, z1, store_steps).cpu().numpy()
+    got_x = [to_host(v) for v in bp.split(x)]
+    got_g = [to_host(v) for v in bp.split(g)]
+    bp.close()
+    ref_p = np.zeros((3, 2))
+    for a, go, n, sc, gx, gg in zip(fields, g_out, ns, scales, got_x, got_g):
+        p = P.MPAPlan(n, DT, dmm.with_sigma(sc), L, 2, 2, block, halo, prec, BAND)
+        y = to_dev(a, prec)
+        c1 = p.propagate_checkpointed(y, z0, z1)
+        h = to_dev(go, prec)
+        q = p.adjoint(c1, h, z0, z1, store_steps).cpu().numpy()
+        p.close()
+        assert np.array_equal(to_host(y), gx)
+        assert np.array_equal(to_host(h), gg), n
+        ref_p[0] += sc * q[0]
+        ref_p[1:] += q[1:]
+    err = np.linalg.norm(pg - ref_p) / np.linalg.norm(ref_p)
+    assert err < 1e-12, (err, pg, ref_p)
+
+
+def test_batch_adjoint_fp64_matches_oracle():
+    import paper_1101_0086_amd as P
+    ns = [4096, 2048, 8192]
+    scales = [1.0, 1.6, 0.7]
+    block = 1024
+    fields, g_out, halo, L = _case(ns, 17, block)
+    dmm = dm_map(beta3=0.1)
+    z0, z1 = 0.5 - 2 * L, 0.5 + L           # span change at 0.5
+    say("batch adjoint fp64 vs oracle", ns)
+    bp = P.MPABatchPlan(ns, DT, dmm, L, 2, 2, block, halo, P.MPA_C128, BAND, sigma_scale=scales)
+    x = to_dev(np.concatenate(fields), 1)
+    ck = bp.propagate_checkpointed(x, z0, z1)
+    g = to_dev(np.concatenate(g_out), 1)
+    pg = bp.adjoint(ck, g, z0, z1).cpu().numpy()
+    got_g = [to_host(v) for v in bp.split(g)]
+    bp.close()
+    ref_p = np.zeros((3, 2))
+    for a, go, sc, gg in zip(fields, g_out, scales, got_g):
+        ga, gs, g2, g3 = O.mpa_propagate_vjp(a, DT, dmm.with_sigma(sc), L, 2, 2, z0, z1, go, block, halo)
+        assert rel_l2(gg, ga) < 1e-10
+        ref_p += np.stack([sc * gs, g2, g3])
+    err = np.linalg.norm(pg - ref_p) / np.linalg.norm(ref_p)
+    assert err < 1e-9, (err, pg, ref_p)
+
+
+def test_batch_adjoint_empty_range():
+    import paper_1101_0086_amd as P
+    ns = [2048, 4096]
+    fields, g_out, halo, L = _case(ns, 3, 1024)
+    bp = P.MPABatchPlan(ns, DT, dm_map(), L, 2, 2, 1024, halo, P.MPA_C64, BAND)
+    assert bp.checkpoint_count(0.25, 0.25) == 0
+    g = to_dev(np.concatenate(g_out), 0)
+    before = to_host(g)
+    import torch
+    pg = bp.adjoint(torch.empty((0, bp.n), dtype=g.dtype, device=g.device), g, 0.25, 0.25)
+    bp.close()
+    assert np.array_equal(to_host(g), before)
+    assert not pg.cpu().numpy().any()
