@@ -197,7 +197,8 @@ template <typename T, int B, int NIT>
 static hipError_t adjoint_typed(const AdjointStepArgs& a) {
     const BatchItems* bt = a.batch;
     const int n_items = bt ? bt->n_items : a.n_blocks;
-    const int grid = bt ? bt->grid : a.n_blocks;
+    const int grid = bt ? a.grid : a.n_blocks;
+    if (grid < 1 || grid > n_items) return hipErrorInvalidValue;
     hipLaunchKernelGGL((mpa_adjoint_block_kernel<T, B, NIT>), dim3(grid), dim3(B / PTS), 0, a.stream,
                        static_cast<const cx<T>*>(a.in), static_cast<const cx<double>*>(a.g_out),
                        static_cast<cx<double>*>(a.g_blk), a.partial, static_cast<cx<T>*>(a.node_store),
@@ -233,6 +234,26 @@ static hipError_t adjoint_b(const AdjointStepArgs& a) {
         case 4096: return adjoint_nit<T, 4096>(a);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <typename T>
+static int per_cu_b(int block, int n_iter) {
+    int n = 0;
+    auto q = [&](const void* f) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block / PTS, 0) != hipSuccess) n = 0;
+    };
+#define MPA_ADJ_OCC(BB, NN) \
+    if (block == BB && n_iter == NN) q(reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, BB, NN>));
+#define MPA_ADJ_OCC_B(BB) MPA_ADJ_OCC(BB, 1) MPA_ADJ_OCC(BB, 2) MPA_ADJ_OCC(BB, 3) MPA_ADJ_OCC(BB, 4) MPA_ADJ_OCC(BB, 5)
+    MPA_ADJ_OCC_B(512) MPA_ADJ_OCC_B(1024) MPA_ADJ_OCC_B(2048) MPA_ADJ_OCC_B(4096)
+#undef MPA_ADJ_OCC_B
+#undef MPA_ADJ_OCC
+    return n;
+}
+
+int adjoint_workgroups_per_cu(int precision, int block, int n_iter) {
+    if (!block_step_supported(precision, block, n_iter)) return 0;
+    return precision == 0 ? per_cu_b<float>(block, n_iter) : per_cu_b<double>(block, n_iter);
 }
 
 hipError_t launch_adjoint_step(const AdjointStepArgs& a) {

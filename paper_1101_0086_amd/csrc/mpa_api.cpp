@@ -839,6 +839,7 @@ static int adjoint_long_step(const AdjTarget& t, const void* in, const void* g_o
     a.dz = p->prm.L / M;
     a.precision = p->prm.precision;
     a.batch = t.batch;
+    a.grid = t.grid;
     a.stream = stream;
     hipError_t e = mpa::launch_adjoint_step(a);
     if (e != hipSuccess) return fail(MPA_EDEVICE, "adjoint step launch failed: %s", hipGetErrorString(e));
@@ -1010,6 +1011,7 @@ struct mpa_batch_plan {
     void* d_item_base = nullptr;        // int32 first work item of each instance
     void* work = nullptr;
     AdjWork adj;                        // reverse-pass workspace
+    int adj_grid = 0;                   // reverse-kernel workgroups (set on first use)
 };
 
 static void batch_free(mpa_batch_plan* b) {
@@ -1129,9 +1131,28 @@ int mpa_batch_propagate(mpa_batch_plan* b, void* fields, double z0, double z1, v
     return march(b->base, fields, b->work, b->total, z0, z1, (hipStream_t)stream, &b->items);
 }
 
+// The reverse kernel holds one workgroup per CU or few (its registers), so
+// the work list is dealt out in equal shares to as many workgroups as fit at
+// once: every resident workgroup takes the same number of items (a static
+// list dealt to more workgroups than fit leaves the last round part empty).
+static int adjoint_grid(mpa_batch_plan* b) {
+    if (b->adj_grid) return b->adj_grid;
+    const mpa_plan* p = b->base;
+    const int n = b->items.n_items;
+    int cus = 0;
+    (void)hipSetDevice(p->device);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus <= 0)
+        cus = 256;
+    const int per_cu = mpa::adjoint_workgroups_per_cu(p->prm.precision, p->block, p->prm.n_iter);
+    const int slots = cus * (per_cu > 0 ? per_cu : 1);
+    const int rounds = (n + slots - 1) / slots;
+    b->adj_grid = (n + rounds - 1) / rounds;
+    return b->adj_grid;
+}
+
 static AdjTarget batch_target(mpa_batch_plan* b) {
-    return {b->base,           &b->items, b->d_item_base, (int32_t)b->len.size(), b->total, b->items.n_items,
-            b->items.grid,     b->work,   &b->adj};
+    return {b->base,         &b->items, b->d_item_base, (int32_t)b->len.size(), b->total, b->items.n_items,
+            adjoint_grid(b), b->work,   &b->adj};
 }
 
 int mpa_batch_checkpoint_count(const mpa_batch_plan* b, double z0, double z1, int64_t* count) {
