@@ -4,8 +4,8 @@ Cases span several blocks with a ragged last core, every compiled block
 size, 1..5 Picard sweeps, both precisions, marching across a span boundary
 and an amplifier, the small full-window workload (4096 modes, FP64, ten DM
 periods) and, at the full 2^18-mode 8-channel size in the launch
-configuration the benchmark times, sampled blocks that the oracle computes
-one at a time.
+configuration the benchmark times, and at the largest size a plan accepts
+(2^30 modes), sampled blocks that the oracle computes one at a time.
 """
 import math
 
@@ -157,3 +157,41 @@ def test_full_size_sampled_blocks(name):
                               s.L, s.M, s.n_iter, out_mask=mask)
         ref = res[s.halo:s.halo + clen]
         assert rel_l2(got[c0:c0 + clen], ref) < TOL_F32, b
+
+
+def test_maximum_size_sampled_blocks():
+    """The largest field a plan accepts, 2^30 modes in FP32 (8 GiB, 349526
+    blocks of 4096 with a ragged 1024-sample last core), in the benchmark's
+    launch configuration: the 2^18-mode 8-channel field repeated 4096 times
+    (a WDM pulse train of the same structure), one long step, three blocks
+    (first, middle, last) recomputed by the oracle one at a time."""
+    import torch
+
+    import paper_1101_0086_amd as P
+    w = WORKLOADS["wdm8_n262144_f32"]
+    s = w.mpa
+    n = 1 << 30
+    a = w.field()
+    say("maximum size sampled blocks", n)
+    plan = P.MPAPlan(n, w.grid.dt, w.dmmap, s.L, s.M, s.n_iter, s.block, s.halo, 0, s.omega_band)
+    assert plan.info()["n_blocks"] == -(-n // (s.block - 2 * s.halo))
+    x = torch.from_numpy(a.astype(np.complex64)).to("cuda:0").repeat(n // a.size)
+    plan.propagate(x, 0.0, s.L)
+    parts = O.block_partition(n, s.block, s.halo)
+    omega_b = O.omega_grid(s.block, w.grid.dt)
+    taper = O.block_taper(s.block, s.halo)
+    b2, b3 = w.dmmap.beta2[0], w.dmmap.beta3[0]
+    mask = O.block_mask(omega_b, b2, b3, s.L, s.halo, w.grid.dt)
+    checks = []
+    for b in (0, len(parts) // 2, len(parts) - 1):
+        w0, c0, clen = parts[b]
+        idx = (w0 + np.arange(s.block)) % n
+        res = O.mpa_long_step(a[idx % a.size] * taper, omega_b, b2, b3, w.dmmap.sigma[0], w.dmmap.gamma,
+                              s.L, s.M, s.n_iter, out_mask=mask)
+        got = x[c0:c0 + clen].cpu().numpy().astype(np.complex128)
+        checks.append((b, clen, rel_l2(got, res[s.halo:s.halo + clen])))
+    plan.close()
+    del x
+    assert checks[-1][1] == 1024
+    for b, _, e in checks:
+        assert e < TOL_F32, (b, e)
