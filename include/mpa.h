@@ -34,6 +34,10 @@
  *     the calling thread's most recent failure.
  *   - A plan is not thread safe: calls on one plan must not overlap in time
  *     on different host threads.  Different plans are independent.
+ *   - A plan's device scratch (the march's work field, the reverse-pass
+ *     workspace) is shared by all its calls: work of one plan enqueued on
+ *     two streams must be ordered between them by the caller (events), else
+ *     the launches race on that scratch.
  *
  * Time blocking (not part of the paper): with block = B < N the window is
  * cut into blocks of B samples that overlap by `halo` samples per side; each
