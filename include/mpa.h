@@ -216,7 +216,11 @@ int mpa_propagate_checkpointed(mpa_plan* plan, void* field, double z0, double z1
  * dl/dsigma, dl/dbeta2 and dl/dbeta3 of every span of the map (in that order,
  * n_seg entries each; the derivative of the block roll-off with respect to
  * beta2 and beta3 is included).  `store_steps`: the most long-step inputs
- * kept at once (0: the automatic rule above).  The first call allocates a
+ * kept at once (0: the automatic rule above; under it, when there are
+ * several segments and two segments' inputs fit in MPA_ADJOINT_STORE_BYTES,
+ * the inputs of the next segment are recomputed on a second stream of the
+ * plan's while the current segment is reversed on `stream`, ordered by
+ * events; the results are bitwise those of one stream).  The first call allocates a
  * workspace of n_blocks x (3 n_iter M + 2) x B complex samples plus the
  * kept step inputs, held by the plan until it is destroyed.  Deterministic:
  * per-block partial sums are added in a fixed order.                        */

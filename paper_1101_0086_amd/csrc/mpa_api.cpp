@@ -213,6 +213,9 @@ struct AdjWork {
     int64_t inputs_cap = 0;
     void* subs = nullptr;       // subs_cap fields: inner checkpoints of a long map period
     int64_t subs_cap = 0;
+    hipStream_t aux = nullptr;  // recompute of the next segment's inputs (default priority)
+    hipEvent_t fork = nullptr;  // caller's stream -> aux
+    hipEvent_t join = nullptr;  // aux -> caller's stream
     void release() {
         for (void** q : {&node, &last, &gblk, &partial, &ga, &gb, &inputs, &subs})
             if (*q) {
@@ -220,6 +223,11 @@ struct AdjWork {
                 *q = nullptr;
             }
         inputs_cap = subs_cap = 0;
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (aux) (void)hipStreamDestroy(aux);
+        fork = join = nullptr;
+        aux = nullptr;
     }
 };
 
@@ -881,6 +889,17 @@ static int advance(const AdjTarget& t, const void* src, void* dst, int64_t m, in
     return MPA_OK;
 }
 
+// Inputs of long steps s0 .. s0 + q - 1 into slots 0 .. q - 1 of `slots`, from the field at s0.
+static int recompute(const AdjTarget& t, const void* start, void* slots, int64_t s0, int64_t q, hipStream_t stream) {
+    if (mpa::launch_copy_field(start, slots, t.count, t.p->prm.precision, stream) != hipSuccess)
+        return fail(MPA_EDEVICE, "copy failed");
+    for (int64_t i = 0; i + 1 < q; ++i) {
+        int st = launch_long_step(t.p, field_at(t, slots, i), field_at(t, slots, i + 1), s0 + i, stream, t.batch);
+        if (st) return st;
+    }
+    return MPA_OK;
+}
+
 // March over [z0, z1], copying the field(s) at the start of every segment into checkpoints.
 static int forward_checkpointed(const AdjTarget& t, void* field, double z0, double z1, void* checkpoints,
                                 hipStream_t s) {
@@ -928,45 +947,82 @@ static int reverse(const AdjTarget& t, const void* checkpoints, void* grad, doub
     for (size_t k = 0; k < seg.size(); ++k)
         longest = std::max(longest, ((k + 1 < seg.size()) ? seg[k + 1] : m1) - seg[k]);
     const int64_t field_bytes = t.count * (int64_t)p->elem;
+    // automatic rule with several segments and room for two of them: the next
+    // segment's inputs are recomputed on a second stream while the current
+    // segment is reversed
+    const bool overlap = store_steps == 0 && seg.size() > 1 && 2 * longest * field_bytes <= MPA_ADJOINT_STORE_BYTES;
     int64_t Q = store_steps;
     if (Q == 0) Q = longest * field_bytes <= MPA_ADJOINT_STORE_BYTES ? longest : (int64_t)std::ceil(std::sqrt((double)longest));
     Q = std::max<int64_t>(1, std::min(Q, longest));
     AdjWork* w = t.w;
-    st = reserve_fields(t, &w->inputs, &w->inputs_cap, std::max<int64_t>(Q, 2));
+    st = reserve_fields(t, &w->inputs, &w->inputs_cap, overlap ? 2 * Q : std::max<int64_t>(Q, 2));
     if (st) return st;
     const int64_t n_sub = (longest + Q - 1) / Q;
     if (n_sub > 1) {
         st = reserve_fields(t, &w->subs, &w->subs_cap, n_sub);
         if (st) return st;
     }
+    if (overlap && !w->aux) {
+        if (hipStreamCreateWithFlags(&w->aux, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&w->fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&w->join, hipEventDisableTiming) != hipSuccess)
+            return fail(MPA_EDEVICE, "adjoint: stream or event creation failed");
+    }
 
     void* ga = w->ga;
     void* gb = w->gb;
     if (mpa::launch_convert(grad, p->prm.precision, ga, MPA_C128, t.count, s) != hipSuccess)
         return fail(MPA_EDEVICE, "gradient conversion failed");
-    for (int64_t k = (int64_t)seg.size() - 1; k >= 0; --k) {
-        const int64_t a = seg[k], b = (k + 1 < (int64_t)seg.size()) ? seg[k + 1] : m1;
-        const void* ck = field_at(t, checkpoints, k);
-        const int64_t P = b - a, subs = (P + Q - 1) / Q;
-        // inner checkpoints at a + j Q (j >= 1) when the segment is longer than Q
-        for (int64_t j = 1; j < subs; ++j) {
-            st = advance(t, j == 1 ? ck : field_at(t, w->subs, j - 1), field_at(t, w->subs, j), a + (j - 1) * Q, Q, s);
-            if (st) return st;
+    const int64_t K = (int64_t)seg.size();
+    auto seg_end = [&](int64_t k) { return k + 1 < K ? seg[k + 1] : m1; };
+    auto reverse_steps = [&](const void* slots, int64_t s0, int64_t q) {
+        for (int64_t i = q - 1; i >= 0; --i) {
+            int rs = adjoint_long_step(t, field_at(t, slots, i), ga, gb, s0 + i, param_grad, s);
+            if (rs) return rs;
+            std::swap(ga, gb);
         }
-        for (int64_t j = subs - 1; j >= 0; --j) {
-            const int64_t s0 = a + j * Q, q = std::min(Q, b - s0);
-            const void* start = j == 0 ? ck : field_at(t, w->subs, j);
-            // inputs of steps s0 .. s0 + q - 1 in slots 0 .. q - 1
-            if (mpa::launch_copy_field(start, w->inputs, t.count, p->prm.precision, s) != hipSuccess)
-                return fail(MPA_EDEVICE, "copy failed");
-            for (int64_t i = 0; i + 1 < q; ++i) {
-                st = launch_long_step(p, field_at(t, w->inputs, i), field_at(t, w->inputs, i + 1), s0 + i, s, t.batch);
+        return (int)MPA_OK;
+    };
+    if (overlap) {
+        // Segment k's inputs live in half (K - 1 - k) % 2 of the slots.  The
+        // aux stream recomputes segment k - 1 into the other half once the
+        // reverse of segment k + 1, which read that half, is done, while the
+        // caller's stream reverses segment k; the caller's stream waits for
+        // each recompute before reversing it.
+        auto half = [&](int64_t k) { return field_at(t, w->inputs, ((K - 1 - k) & 1) * Q); };
+        auto ev = [&](hipEvent_t e, hipStream_t from, hipStream_t to) {
+            return hipEventRecord(e, from) == hipSuccess && hipStreamWaitEvent(to, e, 0) == hipSuccess;
+        };
+        if (!ev(w->fork, s, w->aux)) return fail(MPA_EDEVICE, "adjoint: stream ordering failed");
+        st = recompute(t, field_at(t, checkpoints, K - 1), half(K - 1), seg[K - 1], seg_end(K - 1) - seg[K - 1], w->aux);
+        if (st) return st;
+        for (int64_t k = K - 1; k >= 0; --k) {
+            if (!ev(w->join, w->aux, s)) return fail(MPA_EDEVICE, "adjoint: stream ordering failed");
+            if (k > 0) {
+                if (!ev(w->fork, s, w->aux)) return fail(MPA_EDEVICE, "adjoint: stream ordering failed");
+                st = recompute(t, field_at(t, checkpoints, k - 1), half(k - 1), seg[k - 1], seg_end(k - 1) - seg[k - 1],
+                               w->aux);
                 if (st) return st;
             }
-            for (int64_t i = q - 1; i >= 0; --i) {
-                st = adjoint_long_step(t, field_at(t, w->inputs, i), ga, gb, s0 + i, param_grad, s);
+            st = reverse_steps(half(k), seg[k], seg_end(k) - seg[k]);
+            if (st) return st;
+        }
+    } else {
+        for (int64_t k = K - 1; k >= 0; --k) {
+            const int64_t a = seg[k], b = seg_end(k);
+            const void* ck = field_at(t, checkpoints, k);
+            const int64_t P = b - a, subs = (P + Q - 1) / Q;
+            // inner checkpoints at a + j Q (j >= 1) when the segment is longer than Q
+            for (int64_t j = 1; j < subs; ++j) {
+                st = advance(t, j == 1 ? ck : field_at(t, w->subs, j - 1), field_at(t, w->subs, j), a + (j - 1) * Q, Q, s);
                 if (st) return st;
-                std::swap(ga, gb);
+            }
+            for (int64_t j = subs - 1; j >= 0; --j) {
+                const int64_t s0 = a + j * Q, q = std::min(Q, b - s0);
+                st = recompute(t, j == 0 ? ck : field_at(t, w->subs, j), w->inputs, s0, q, s);
+                if (st) return st;
+                st = reverse_steps(w->inputs, s0, q);
+                if (st) return st;
             }
         }
     }

@@ -203,6 +203,26 @@ def test_inner_checkpoints_are_bitwise_identical():
         assert np.array_equal(g_q, g_all) and np.array_equal(p_q, p_all), q
 
 
+def test_overlapped_recompute_is_bitwise_identical():
+    """Four checkpoint segments (two whole map periods of 4836 long steps):
+    the automatic rule recomputes each segment's step inputs on a second
+    stream while the previous segment is reversed; the gradients equal, bit
+    for bit, those of the one-stream schedule (all inputs of a segment kept,
+    store_steps = 4836) and of inner checkpoints every 1000 long steps."""
+    grid, a, band, halo, L = _blocked(1024)
+    dmmap = dm_map(beta3=0.1)
+    g_out = np.random.default_rng(19).normal(size=a.size) + 1j * np.random.default_rng(20).normal(size=a.size)
+    z0, z1 = 1.0 - 5 * L, 3.0 + 4 * L
+    plan = _plan(grid, dmmap, L, 2, 2, 1024, halo, 0, band)
+    assert plan.checkpoint_count(z0, z1) == 4
+    say("adjoint overlapped recompute")
+    _, g_ov, p_ov = _gpu_grad(plan, a, g_out, z0, z1, 0, store_steps=0)
+    for q in (int(round(1.0 / L)), 1000):
+        _, g_q, p_q = _gpu_grad(plan, a, g_out, z0, z1, 0, store_steps=q)
+        assert np.array_equal(g_q, g_ov) and np.array_equal(p_q, p_ov), q
+    plan.close()
+
+
 def test_checkpointed_forward_matches_propagate():
     w = WORKLOADS["dm1ch_n4096_f64"]
     s = w.mpa
