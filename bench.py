@@ -239,16 +239,16 @@ def batched(torch, P, count=256, steps=200):
 
 
 def autotune_table(w, a0, torch, P):
-    """Autotuner over (block, L, M) at the workload's dz (fixed accuracy)."""
+    """Autotuner over (block, halo, L, M) at the workload's dz (fixed accuracy)."""
     from paper_1101_0086_amd.autotune import autotune
     s = w.mpa
     x = torch.from_numpy(a0).to(device="cuda:0", dtype=torch.complex64)
     best, cands = autotune(x, w.grid.dt, w.dmmap, s.L / s.M, s.n_iter, s.omega_band)
     rows = [{"block": c.block, "halo": c.halo, "L": c.L, "M": c.M,
              "mode_steps_per_s": w.grid.n / (c.seconds_per_unit_z * (s.L / s.M))} for c in cands]
-    log("autotune: " + ", ".join(f"B={r['block']} L={r['L']:.2e} M={r['M']}: {r['mode_steps_per_s']:.3e}"
+    log("autotune: " + ", ".join(f"B={r['block']} H={r['halo']} L={r['L']:.2e} M={r['M']}: {r['mode_steps_per_s']:.3e}"
                                  for r in rows))
-    return {"dz": s.L / s.M, "candidates": rows, "best_block": best.block}
+    return {"dz": s.L / s.M, "candidates": rows, "best_block": best.block, "best_halo": best.halo}
 
 
 def large(torch, P, steps=200):
@@ -474,6 +474,27 @@ def compare(w, a0, plan, x, torch, P):
         picard.append({"n_iter": nit, "rel_l2_in_band": e, "rel_l2_full_band": e_full, "seconds": el,
                        "mode_steps_per_s": n * s.M / s.L / el})
         log(f"MPA n_iter={nit}: in-band {e:.3e} full-band {e_full:.3e} time {el * 1e3:.1f} ms")
+    # the autotuner's pick (block, halo, L, M) at the same quadrature interval
+    from paper_1101_0086_amd.autotune import autotune
+    dz_q = s.L / s.M
+    pick, _ = autotune(torch.from_numpy(a0).to(device="cuda:0", dtype=x.dtype), dt, w.dmmap, dz_q, s.n_iter,
+                       s.omega_band)
+    pl = P.MPAPlan(n, dt, w.dmmap, pick.L, pick.M, s.n_iter, pick.block, pick.halo, P.MPA_C64, s.omega_band)
+    y = torch.from_numpy(a0).to(device="cuda:0", dtype=x.dtype)
+    pl.propagate(y, 0.0, 20 * pick.L)
+    y = torch.from_numpy(a0).to(device="cuda:0", dtype=x.dtype)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pl.propagate(y, 0.0, 1.0)
+    torch.cuda.synchronize()
+    t_pick = time.perf_counter() - t0
+    pl.close()
+    e_full, e = err(y.cpu().numpy().astype(np.complex128))
+    tuned = {"block": pick.block, "halo": pick.halo, "L": pick.L, "M": pick.M, "dz": dz_q,
+             "rel_l2_in_band": e, "rel_l2_full_band": e_full, "seconds_one_period": t_pick,
+             "mode_steps_per_s": n / dz_q / t_pick}
+    log(f"autotuned pick B={pick.block} H={pick.halo} L={pick.L:.3e} M={pick.M}: in-band {e:.3e} "
+        f"full-band {e_full:.3e}, {t_pick * 1e3:.1f} ms, {tuned['mode_steps_per_s']:.3e} mode-steps/s")
     sweep = []
     best = None
     for k in (1000, 1414, 2000, 2828, 4000, 5657, 8000, 11314, 16000):
@@ -515,6 +536,7 @@ def compare(w, a0, plan, x, torch, P):
                         f"from it by {ref_err:.1e}",
                         "mpa_seconds_one_period": t_mpa},
            "picard_sweeps": picard,
+           "autotuned_pick": tuned,
            "blocking_error": blocking,
            "split_step": {"sweep": sweep, "equal_accuracy": best,
                           "time_ratio_ss_over_mpa": (best["seconds"] / t_mpa) if best else None}}

@@ -1,15 +1,18 @@
-"""Choice of block size, long step and nodes per long step at fixed accuracy.
+"""Choice of block size, overlap, long step and nodes per long step at fixed
+accuracy.
 
 The leading error terms of both the MPA and split-step (Eqs. 5 and 7) are
 L^3/M^2 per long step, i.e. (L/M)^2 = dz^2 per unit distance, so at a fixed
 quadrature interval dz the accuracy is fixed and only the cost changes with
-(B, L, M): larger blocks allow longer long steps (fewer of the three extra
+(B, H, L, M): larger blocks allow longer long steps (fewer of the three extra
 transforms per long step) but cost more per point and give fewer blocks to
-spread over the GPU.  For every compiled block size B (halo B/8) the
-candidate takes the longest long step L = k dz that divides every span and
-the amplifier spacing and keeps the group delay of the signal band within
-the halo rule; the tuner times a few launches of each on the GPU and keeps
-the cheapest per unit distance.
+spread over the GPU; a wider halo H (overlap 2H/B of 25 % or 50 %) also
+allows a longer long step and gives more blocks (core B - 2H), at the price
+of computing more samples twice.  For every compiled block size B and halo
+B/8 or B/4 the candidate takes the longest long step L = k dz that divides
+every span and the amplifier spacing and keeps the group delay of the
+signal band within the halo rule; the tuner times a few launches of each on
+the GPU and keeps the cheapest per unit distance.
 """
 from __future__ import annotations
 
@@ -19,6 +22,7 @@ import time
 from typing import List, Optional
 
 BLOCKS = (512, 1024, 2048, 4096)
+HALO_DIVISORS = (8, 4)    # halo B/8 (25 % overlap) and B/4 (50 %)
 HALO_RULE = 0.25          # the library's check: rate * L <= 0.25 * halo * dt
 
 
@@ -39,35 +43,36 @@ def _steps(length: float, h: float) -> int:
 
 
 def candidates(n: int, dt: float, dmmap, dz: float, omega_band: float,
-               blocks=BLOCKS) -> List[Candidate]:
-    """One candidate per block size B <= n: halo B/8 and the longest long step
-    that is a multiple of dz, divides every span (and the amplifier spacing)
-    and satisfies the halo rule for every span."""
+               blocks=BLOCKS, halo_divisors=HALO_DIVISORS) -> List[Candidate]:
+    """One candidate per block size B <= n and halo B/d (d in halo_divisors):
+    the longest long step that is a multiple of dz, divides every span (and
+    the amplifier spacing) and satisfies the halo rule for every span."""
     counts = [_steps(s, dz) for s in dmmap.seg_len]
     if dmmap.z_amp > 0:
         counts.append(_steps(dmmap.z_amp, dz))
     g = 0
     for c in counts:
         g = math.gcd(g, c)
+    rate = max(abs(b2) * omega_band + 0.5 * abs(b3) * omega_band ** 2
+               for b2, b3 in zip(dmmap.beta2, dmmap.beta3))
     out = []
     for B in blocks:
         if B > n:
             continue
-        H = B // 8
-        rate = max(abs(b2) * omega_band + 0.5 * abs(b3) * omega_band ** 2
-                   for b2, b3 in zip(dmmap.beta2, dmmap.beta3))
-        lmax = HALO_RULE * H * dt / rate if rate > 0 else float("inf")
-        best = 0
-        for k in range(1, g + 1):
-            if g % k == 0 and k * dz <= lmax * (1 - 1e-12):
-                best = k
-        if best:
-            out.append(Candidate(B, H, best * dz, best))
+        for d in halo_divisors:
+            H = B // d
+            lmax = HALO_RULE * H * dt / rate if rate > 0 else float("inf")
+            best = 0
+            for k in range(1, g + 1):
+                if g % k == 0 and k * dz <= lmax * (1 - 1e-12):
+                    best = k
+            if best:
+                out.append(Candidate(B, H, best * dz, best))
     return out
 
 
 def autotune(field, dt: float, dmmap, dz: float, n_iter: int, omega_band: float,
-             precision: int = 0, launches: int = 40, blocks=BLOCKS):
+             precision: int = 0, launches: int = 40, blocks=BLOCKS, halo_divisors=HALO_DIVISORS):
     """Time every candidate on `field` (a complex CUDA tensor, left
     unchanged) and return (best Candidate, list of all timed candidates)."""
     import torch
@@ -75,7 +80,7 @@ def autotune(field, dt: float, dmmap, dz: float, n_iter: int, omega_band: float,
     from . import MPAPlan
 
     n = field.numel()
-    cands = candidates(n, dt, dmmap, dz, omega_band, blocks)
+    cands = candidates(n, dt, dmmap, dz, omega_band, blocks, halo_divisors)
     if not cands:
         raise ValueError("no block size satisfies the halo rule at this dz")
     for c in cands:

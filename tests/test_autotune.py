@@ -1,6 +1,6 @@
 """Candidate enumeration of the autotuner (host logic): every candidate
 satisfies the library's own validation, is a multiple of dz dividing the
-spans, and is the longest such long step for its block size."""
+spans, and is the longest such long step for its block size and halo."""
 import ctypes as C
 
 from workloads import WORKLOADS, dm_map
@@ -12,21 +12,25 @@ def test_candidates_are_valid_and_maximal():
     w = WORKLOADS["wdm8_n262144_f32"]
     dz = 1.25e-4
     cands = candidates(w.grid.n, w.grid.dt, w.dmmap, dz, w.mpa.omega_band)
-    # 512- and 1024-blocks cannot take even one dz inside the halo rule
-    assert [c.block for c in cands] == [2048, 4096]
+    # halos of 64 and 128 samples cannot take even one dz inside the halo rule
+    assert [(c.block, c.halo) for c in cands] == [(1024, 256), (2048, 256), (2048, 512), (4096, 512),
+                                                  (4096, 1024)]
     rate = max(abs(b2) * w.mpa.omega_band + 0.5 * abs(b3) * w.mpa.omega_band ** 2
                for b2, b3 in zip(w.dmmap.beta2, w.dmmap.beta3))
     m = L.MapStruct(w.dmmap)
     for c in cands:
-        assert abs(c.L - c.M * dz) < 1e-15 and c.halo == c.block // 8
+        assert abs(c.L - c.M * dz) < 1e-15 and c.halo in (c.block // 8, c.block // 4)
         p = L.make_params(w.grid.n, w.grid.dt, c.L, c.M, 2, c.block, c.halo, 0, w.mpa.omega_band)
         assert L.lib().mpa_plan_validate(C.byref(p), C.byref(m.s)) == L.MPA_OK
         # the next admissible multiple of dz breaks the halo rule
         nxt = [k for k in range(c.M + 1, 4001) if 4000 % k == 0][0]
         assert rate * nxt * dz > HALO_RULE * c.halo * w.grid.dt
-    # the 4096-block candidate has the benchmark's long step (the benchmark
-    # takes M = 4 nodes per long step, dz = L / 4, instead of dz = L / 2)
-    assert cands[-1].L == w.mpa.L
+    # the 4096-block, 512-halo candidate has the benchmark's long step (the
+    # benchmark takes M = 4 nodes per long step, dz = L / 4, instead of
+    # dz = L / 2); the wider halo admits a longer one
+    by = {(c.block, c.halo): c for c in cands}
+    assert by[(4096, 512)].L == w.mpa.L
+    assert by[(4096, 1024)].L > w.mpa.L
 
 
 def test_no_candidate_when_halo_rule_cannot_hold():
