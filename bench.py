@@ -255,7 +255,8 @@ def large(torch, P, steps=200):
     """The 32-channel QPSK workload (2^22 modes, 1366 blocks of 4096): MPA
     (L = dz = 7.8125e-6, 2 sweeps) and split-step at the same dz, throughput
     over `steps` long steps from the seeded field (no accuracy run: the
-    channel band reaches half the grid's Nyquist frequency)."""
+    channel band reaches half the grid's Nyquist frequency), and the
+    autotuner's table of block sizes and overlaps at that dz."""
     from workloads import WORKLOADS
     w = WORKLOADS["wdm32_n4194304_f32"]
     s = w.mpa
@@ -281,11 +282,19 @@ def large(torch, P, steps=200):
     t_ss = time.perf_counter() - t0
     ss.close()
     n = w.grid.n
+    # block size and overlap autotuned at the same dz
+    from paper_1101_0086_amd.autotune import autotune
+    x = torch.from_numpy(a).to(device="cuda:0", dtype=torch.complex64)
+    pick, cands = autotune(x, w.grid.dt, w.dmmap, dz, s.n_iter, s.omega_band, launches=20)
+    tuned = [{"block": c.block, "halo": c.halo, "L": c.L, "M": c.M,
+              "mode_steps_per_s": n / (c.seconds_per_unit_z * dz)} for c in cands]
     r = {"workload": w.name, "n_modes": n, "n_blocks": nb, "dz": dz,
          "mpa_mode_steps_per_s": n * s.M * steps / t_mpa, "mpa_us_per_launch": t_mpa / steps * 1e6,
-         "ss_f32_mode_steps_per_s": n * steps / t_ss}
+         "ss_f32_mode_steps_per_s": n * steps / t_ss, "autotune": tuned,
+         "autotune_pick": {"block": pick.block, "halo": pick.halo, "L": pick.L, "M": pick.M}}
     log(f"large: MPA {r['mpa_mode_steps_per_s']:.3e} ({r['mpa_us_per_launch']:.0f} us/launch), "
-        f"split-step {r['ss_f32_mode_steps_per_s']:.3e} mode-steps/s")
+        f"split-step {r['ss_f32_mode_steps_per_s']:.3e} mode-steps/s; autotune: "
+        + ", ".join(f"B={t['block']} H={t['halo']} M={t['M']}: {t['mode_steps_per_s']:.3e}" for t in tuned))
     return r
 
 
