@@ -232,10 +232,30 @@ def batched(torch, P, count=256, steps=200):
     bp.close()
     ms = info["total_samples"] * M * steps
     log(f"batched: {info['work_items']} work items, eager {ms / t_eager:.3e}, graph {ms / t_graph:.3e} mode-steps/s")
+    # block size and overlap at the same dz (candidates of the autotuner for the
+    # shortest instance), each timed eagerly over the same distance
+    from paper_1101_0086_amd.autotune import candidates
+    dz = L / M
+    tuned = []
+    for c in candidates(min(ns), dt, dm_map(beta3=0.1), dz, band):
+        cp = P.MPABatchPlan(ns, dt, dm_map(beta3=0.1), c.L, c.M, nit, c.block, c.halo, P.MPA_C64, band,
+                            sigma_scale=sig)
+        y = x.clone()
+        cp.propagate(y, 0.0, 4 * c.L)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cp.propagate(y, 0.0, z1)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        cp.close()
+        tuned.append({"block": c.block, "halo": c.halo, "L": c.L, "M": c.M,
+                      "mode_steps_per_s": info["total_samples"] * (z1 / dz) / el})
+    log("batched, block size and overlap at dz = %.1e: " % dz
+        + ", ".join(f"B={t['block']} H={t['halo']} M={t['M']}: {t['mode_steps_per_s']:.3e}" for t in tuned))
     return {"instances": count, "total_modes": info["total_samples"], "work_items_per_launch": info["work_items"],
             "L": L, "M": M, "n_iter": nit, "block": 4096, "halo": 512, "long_steps": steps,
             "mode_steps_per_s_eager": ms / t_eager, "mode_steps_per_s_graph": ms / t_graph,
-            "us_per_long_step_graph": t_graph / steps * 1e6}
+            "us_per_long_step_graph": t_graph / steps * 1e6, "block_overlap_at_same_dz": tuned}
 
 
 def autotune_table(w, a0, torch, P):
