@@ -376,6 +376,27 @@ def gradient(torch, P, periods=20):
          "dl_dsigma": pgc[0].tolist(), "dl_dbeta2": pgc[1].tolist(), "dl_dbeta3": pgc[2].tolist()}
     log(f"gradient ({periods} periods): forward {t_fwd:.2f} s, checkpointed {t_ck:.2f} s, reverse {t_adj:.2f} s "
         f"({r['gradient_over_forward']:.2f}x forward), reverse {r['reverse_us_per_long_step']:.1f} us per long step")
+    # block size and overlap at the same dz: gradient over one period each
+    from paper_1101_0086_amd.autotune import candidates
+    dz = s.L / s.M
+    table = []
+    for c in candidates(w.grid.n, w.grid.dt, w.dmmap, dz, s.omega_band):
+        pl = P.MPAPlan(w.grid.n, w.grid.dt, w.dmmap, c.L, c.M, s.n_iter, c.block, c.halo, P.MPA_C64, s.omega_band)
+        x = x0.clone()
+        ck = pl.propagate_checkpointed(x, 0.0, 20 * c.L)
+        pl.adjoint(ck, (2 * x).contiguous(), 0.0, 20 * c.L)
+        x = x0.clone()
+        tc, ck = timed(lambda: pl.propagate_checkpointed(x, 0.0, 1.0))
+        g = (2 * (x - target)).contiguous()
+        ta, _ = timed(lambda: pl.adjoint(ck, g, 0.0, 1.0))
+        pl.close()
+        del ck
+        table.append({"block": c.block, "halo": c.halo, "L": c.L, "M": c.M, "gradient_s_per_period": tc + ta,
+                      "gradient_mode_steps_per_s": w.grid.n / dz / (tc + ta)})
+    r["block_overlap_at_same_dz"] = table
+    log("gradient, block size and overlap at dz = %.2e, one period: " % dz
+        + ", ".join(f"B={t['block']} H={t['halo']} M={t['M']}: {t['gradient_s_per_period'] * 1e3:.0f} ms"
+                    for t in table))
     return r
 
 
