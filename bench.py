@@ -102,6 +102,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-instance measurement")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient (reverse pass) measurement")
     ap.add_argument("--grad-periods", type=int, default=20, help="map periods of the gradient measurement")
+    ap.add_argument("--block", type=int, help="override the workload's block size")
+    ap.add_argument("--halo", type=int, help="override the workload's halo")
+    ap.add_argument("--long-step", type=float, help="override the workload's long step L")
+    ap.add_argument("--nodes", type=int, help="override the workload's nodes per long step M")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="for rocprofv3 --pmc: a 64 MiB copy (counter calibration), then 20 long steps")
     args = ap.parse_args()
@@ -117,6 +121,11 @@ def main():
     from workloads import WORKLOADS
 
     w = WORKLOADS[args.workload]
+    over = {k: v for k, v in (("block", args.block), ("halo", args.halo), ("L", args.long_step),
+                              ("M", args.nodes)) if v is not None}
+    if over:                # another launch configuration of the same workload
+        import dataclasses
+        w = dataclasses.replace(w, mpa=dataclasses.replace(w.mpa, **over))
     s = w.mpa
     n = w.grid.n
     launches_per_step = int(round(1.0 / s.L))
