@@ -6,10 +6,10 @@ L^3/M^2 per long step, i.e. (L/M)^2 = dz^2 per unit distance, so at a fixed
 quadrature interval dz the accuracy is fixed and only the cost changes with
 (B, H, L, M): larger blocks allow longer long steps (fewer of the three extra
 transforms per long step) but cost more per point and give fewer blocks to
-spread over the GPU; a wider halo H (overlap 2H/B of 25 % or 50 %) also
-allows a longer long step and gives more blocks (core B - 2H), at the price
-of computing more samples twice.  For every compiled block size B and halo
-B/8 or B/4 the candidate takes the longest long step L = k dz that divides
+spread over the GPU; a wider halo H (overlap 2H/B of 25 %, 50 % or 75 %)
+also allows a longer long step and gives more blocks (core B - 2H), at the
+price of computing more samples twice.  For every compiled block size B and
+halo B/8, B/4 or 3B/8 the candidate takes the longest long step L = k dz that divides
 every span and the amplifier spacing and keeps the group delay of the
 signal band within the halo rule; the tuner times a few launches of each on
 the GPU and keeps the cheapest per unit distance.
@@ -22,7 +22,7 @@ import time
 from typing import List, Optional
 
 BLOCKS = (512, 1024, 2048, 4096)
-HALO_DIVISORS = (8, 4)    # halo B/8 (25 % overlap) and B/4 (50 %)
+HALO_FRACTIONS = ((1, 8), (1, 4), (3, 8))   # halo B/8, B/4, 3B/8: overlap 2H/B of 25, 50, 75 %
 HALO_RULE = 0.25          # the library's check: rate * L <= 0.25 * halo * dt
 
 
@@ -43,8 +43,8 @@ def _steps(length: float, h: float) -> int:
 
 
 def candidates(n: int, dt: float, dmmap, dz: float, omega_band: float,
-               blocks=BLOCKS, halo_divisors=HALO_DIVISORS) -> List[Candidate]:
-    """One candidate per block size B <= n and halo B/d (d in halo_divisors):
+               blocks=BLOCKS, halo_fractions=HALO_FRACTIONS) -> List[Candidate]:
+    """One candidate per block size B <= n and halo B p/q ((p, q) in halo_fractions):
     the longest long step that is a multiple of dz, divides every span (and
     the amplifier spacing) and satisfies the halo rule for every span."""
     counts = [_steps(s, dz) for s in dmmap.seg_len]
@@ -59,8 +59,8 @@ def candidates(n: int, dt: float, dmmap, dz: float, omega_band: float,
     for B in blocks:
         if B > n:
             continue
-        for d in halo_divisors:
-            H = B // d
+        for num, den in halo_fractions:
+            H = B * num // den
             lmax = HALO_RULE * H * dt / rate if rate > 0 else float("inf")
             best = 0
             for k in range(1, g + 1):
@@ -72,7 +72,7 @@ def candidates(n: int, dt: float, dmmap, dz: float, omega_band: float,
 
 
 def autotune(field, dt: float, dmmap, dz: float, n_iter: int, omega_band: float,
-             precision: int = 0, launches: int = 40, blocks=BLOCKS, halo_divisors=HALO_DIVISORS):
+             precision: int = 0, launches: int = 40, blocks=BLOCKS, halo_fractions=HALO_FRACTIONS):
     """Time every candidate on `field` (a complex CUDA tensor, left
     unchanged) and return (best Candidate, list of all timed candidates)."""
     import torch
@@ -80,7 +80,7 @@ def autotune(field, dt: float, dmmap, dz: float, n_iter: int, omega_band: float,
     from . import MPAPlan
 
     n = field.numel()
-    cands = candidates(n, dt, dmmap, dz, omega_band, blocks, halo_divisors)
+    cands = candidates(n, dt, dmmap, dz, omega_band, blocks, halo_fractions)
     if not cands:
         raise ValueError("no block size satisfies the halo rule at this dz")
     for c in cands:

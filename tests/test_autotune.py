@@ -13,13 +13,13 @@ def test_candidates_are_valid_and_maximal():
     dz = 1.25e-4
     cands = candidates(w.grid.n, w.grid.dt, w.dmmap, dz, w.mpa.omega_band)
     # halos of 64 and 128 samples cannot take even one dz inside the halo rule
-    assert [(c.block, c.halo) for c in cands] == [(1024, 256), (2048, 256), (2048, 512), (4096, 512),
-                                                  (4096, 1024)]
+    assert [(c.block, c.halo) for c in cands] == [(1024, 256), (1024, 384), (2048, 256), (2048, 512), (2048, 768),
+                                                  (4096, 512), (4096, 1024), (4096, 1536)]
     rate = max(abs(b2) * w.mpa.omega_band + 0.5 * abs(b3) * w.mpa.omega_band ** 2
                for b2, b3 in zip(w.dmmap.beta2, w.dmmap.beta3))
     m = L.MapStruct(w.dmmap)
     for c in cands:
-        assert abs(c.L - c.M * dz) < 1e-15 and c.halo in (c.block // 8, c.block // 4)
+        assert abs(c.L - c.M * dz) < 1e-15 and c.halo in (c.block // 8, c.block // 4, 3 * c.block // 8)
         p = L.make_params(w.grid.n, w.grid.dt, c.L, c.M, 2, c.block, c.halo, 0, w.mpa.omega_band)
         assert L.lib().mpa_plan_validate(C.byref(p), C.byref(m.s)) == L.MPA_OK
         # the next admissible multiple of dz breaks the halo rule
