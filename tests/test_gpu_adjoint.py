@@ -109,6 +109,27 @@ def test_blocked_across_span_and_amplifier(block, prec):
         plan.close()
 
 
+@pytest.mark.parametrize("block,halo", [(512, 192), (1024, 256)])
+def test_wide_overlaps(block, halo):
+    """75 % and 50 % overlaps (halo 3B/8 and B/4, the autotuner's gradient
+    picks): FP32 plans against the oracle across a span change."""
+    grid, a, band, _, _ = _blocked(block)
+    rate = O.halo_rate(band, 20.0, 0.1)
+    k = math.ceil(0.5 / (0.25 * halo * grid.dt / rate))
+    while (0.5 / k) * rate > 0.25 * halo * grid.dt:
+        k += 1
+    L = 0.5 / k
+    dmmap = dm_map(beta3=0.1)
+    target = 0.8 * a
+    z0, z1 = 0.5 - 2 * L, 0.5 + 2 * L
+    _, g_out, ref_g, ref_p = _oracle(a, grid.dt, dmmap, L, 2, 2, z0, z1, target, block, halo)
+    say("adjoint wide overlap", block, halo)
+    plan = _plan(grid, dmmap, L, 2, 2, block, halo, 0, band)
+    _, got_g, got_p = _gpu_grad(plan, a, g_out, z0, z1, 0)
+    plan.close()
+    _compare(0, got_g, got_p, ref_g, ref_p)
+
+
 @pytest.mark.parametrize("nit", [1, 3])
 def test_sweeps_and_nodes(nit):
     grid, a, band, halo, L = _blocked(1024)

@@ -132,14 +132,25 @@ def test_resume_step_and_determinism():
     assert np.array_equal(r1, r2) and np.array_equal(r1, r3)
 
 
-@pytest.mark.parametrize("name", ["wdm8_n262144_f32", "wdm32_n4194304_f32"])
-def test_full_size_sampled_blocks(name):
+@pytest.mark.parametrize("name,over", [
+    ("wdm8_n262144_f32", None),
+    ("wdm32_n4194304_f32", None),
+    # the autotuner's picks at the same dz: 50 % and 75 % overlaps
+    ("wdm8_n262144_f32", dict(block=2048, halo=512, L=3.125e-4, M=5)),
+    ("wdm8_n262144_f32", dict(block=4096, halo=1536, L=6.25e-4, M=10)),
+    ("wdm32_n4194304_f32", dict(block=4096, halo=1024, L=1.5625e-5, M=2)),
+])
+def test_full_size_sampled_blocks(name, over):
     """The benchmark's 2^18-mode 8-channel workload and the 2^22-mode
     32-channel QPSK workload (the largest configuration) in their launch
-    configurations (4096-blocks, 512-halo): one long step on the GPU, three
-    blocks (first, middle, ragged last) recomputed by the oracle one at a
-    time, roll-off included."""
+    configurations (4096-blocks, 512-halo) and in the wider-overlap
+    configurations the autotuner picks at the same dz: one long step on the
+    GPU, three blocks (first, middle, ragged last) recomputed by the oracle
+    one at a time, roll-off included."""
+    import dataclasses
     w = WORKLOADS[name]
+    if over:
+        w = dataclasses.replace(w, mpa=dataclasses.replace(w.mpa, **over))
     s = w.mpa
     a = w.field()
     say("full size sampled blocks", name, w.grid.n)
