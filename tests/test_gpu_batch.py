@@ -6,7 +6,9 @@ graphs, through the C ABI.
   differs), with a per-instance sigma;
 * an FP64 batch matches the oracle instance by instance;
 * a captured graph replayed several times, with eager work and
-  synchronisations between replays, matches the eager result every time.
+  synchronisations between replays, matches the eager result every time;
+* the benchmark's 256-instance batch at full size, in its launch
+  configuration, on sampled blocks of sampled instances against the oracle.
 """
 import math
 
@@ -139,3 +141,46 @@ def test_picard_sweeps_chosen_from_the_residual():
         dists.append(dist)
     assert picks[1] >= picks[0]
     assert dists[1][1] > 10 * dists[0][1]
+
+
+def test_batched_workload_full_size_sampled_blocks():
+    """The benchmark's batch at full size (256 instances, N = 2^14..2^18,
+    sum N = 2.7e7, 8915 work items) in its launch configuration (4096-blocks,
+    512-halo, L = 5e-5, M = 1, two sweeps, FP32, per-instance sigma): one
+    batched long step, then the first, middle and last block of four
+    instances (the first, the last, the shortest and the longest)
+    recomputed by the oracle one at a time, roll-off included."""
+    import torch
+
+    import paper_1101_0086_amd as P
+    from tests.gpu_util import TOL_F32
+    from workloads.wdm import batched_instances
+    inst = batched_instances(256, 4)
+    ns = [g.n for g, _, _, _ in inst]
+    sig = [s for _, _, s, _ in inst]
+    dt = inst[0][0].dt
+    band = 0.5 * 15 * 40.0 + 5.0
+    L, M, nit, B, H = 5e-5, 1, 2, 4096, 512
+    dmm = dm_map(beta3=0.1)
+    say("batched workload full size", len(ns), sum(ns))
+    bp = P.MPABatchPlan(ns, dt, dmm, L, M, nit, B, H, P.MPA_C64, band, sigma_scale=sig)
+    assert bp.info()["work_items"] == sum(-(-n // (B - 2 * H)) for n in ns)
+    x = torch.from_numpy(np.concatenate([f for _, _, _, f in inst])).to(device="cuda:0", dtype=torch.complex64)
+    bp.propagate(x, 0.0, L)
+    views = bp.split(x)
+    omega_b = O.omega_grid(B, dt)
+    taper = O.block_taper(B, H)
+    mask = O.block_mask(omega_b, dmm.beta2[0], dmm.beta3[0], L, H, dt)
+    picks = sorted({0, len(ns) - 1, int(np.argmin(ns)), int(np.argmax(ns))})
+    for i in picks:
+        a = inst[i][3]
+        n = ns[i]
+        got = views[i].cpu().numpy().astype(np.complex128)
+        parts = O.block_partition(n, B, H)
+        for b in (0, len(parts) // 2, len(parts) - 1):
+            w0, c0, clen = parts[b]
+            idx = (w0 + np.arange(B)) % n
+            res = O.mpa_long_step(a[idx] * taper, omega_b, dmm.beta2[0], dmm.beta3[0], sig[i], dmm.gamma, L, M,
+                                  nit, out_mask=mask)
+            assert rel_l2(got[c0:c0 + clen], res[H:H + clen]) < TOL_F32, (i, n, b)
+    bp.close()
