@@ -554,6 +554,27 @@ def compare(w, a0, plan, x, torch, P):
              "mode_steps_per_s": n / dz_q / t_pick}
     log(f"autotuned pick B={pick.block} H={pick.halo} L={pick.L:.3e} M={pick.M}: in-band {e:.3e} "
         f"full-band {e_full:.3e}, {t_pick * 1e3:.1f} ms, {tuned['mode_steps_per_s']:.3e} mode-steps/s")
+    # and the sweep count from the Picard residual for that pick (1e-5 of the
+    # five-sweep result after 200 long steps, far below the quadrature error)
+    from paper_1101_0086_amd.autotune import choose_n_iter
+    nit_pick, dist = choose_n_iter(torch.from_numpy(a0).to(device="cuda:0", dtype=x.dtype), dt, w.dmmap,
+                                   pick.L, pick.M, pick.block, pick.halo, s.omega_band)
+    pl = P.MPAPlan(n, dt, w.dmmap, pick.L, pick.M, nit_pick, pick.block, pick.halo, P.MPA_C64, s.omega_band)
+    y = torch.from_numpy(a0).to(device="cuda:0", dtype=x.dtype)
+    pl.propagate(y, 0.0, 20 * pick.L)
+    y = torch.from_numpy(a0).to(device="cuda:0", dtype=x.dtype)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pl.propagate(y, 0.0, 1.0)
+    torch.cuda.synchronize()
+    t_nit = time.perf_counter() - t0
+    pl.close()
+    e_full, e = err(y.cpu().numpy().astype(np.complex128))
+    tuned["picard"] = {"n_iter": nit_pick, "residual_vs_five_sweeps": {str(k): v for k, v in dist.items()},
+                       "rel_l2_in_band": e, "rel_l2_full_band": e_full, "seconds_one_period": t_nit,
+                       "mode_steps_per_s": n / dz_q / t_nit}
+    log(f"autotuned pick with n_iter={nit_pick} (Picard residual): in-band {e:.3e} full-band {e_full:.3e}, "
+        f"{t_nit * 1e3:.1f} ms, {n / dz_q / t_nit:.3e} mode-steps/s")
     sweep = []
     best = None
     for k in (1000, 1414, 2000, 2828, 4000, 5657, 8000, 11314, 16000):
