@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--halo", type=int, help="override the workload's halo")
     ap.add_argument("--long-step", type=float, help="override the workload's long step L")
     ap.add_argument("--nodes", type=int, help="override the workload's nodes per long step M")
+    ap.add_argument("--pmc-grad", action="store_true",
+                    help="for rocprofv3 --pmc: 20 reverse long steps of the 2^16-mode gradient workload")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="for rocprofv3 --pmc: a 64 MiB copy (counter calibration), then 20 long steps")
     args = ap.parse_args()
@@ -119,6 +121,19 @@ def main():
 
     import paper_1101_0086_amd as P
     from workloads import WORKLOADS
+
+    if args.pmc_grad:
+        g = WORKLOADS["wdm4_n65536_f32"]
+        gs = g.mpa
+        pl = P.MPAPlan(g.grid.n, g.grid.dt, g.dmmap, gs.L, gs.M, gs.n_iter, gs.block, gs.halo, P.MPA_C64,
+                       gs.omega_band)
+        xg = torch.from_numpy(g.field()).to(device="cuda:0", dtype=torch.complex64)
+        ck = pl.propagate_checkpointed(xg, 0.0, 20 * gs.L)
+        pl.adjoint(ck, (2 * xg).contiguous(), 0.0, 20 * gs.L)
+        torch.cuda.synchronize()
+        pl.close()
+        print(json.dumps({"pmc_grad": True, "reverse_launches": 20}), flush=True)
+        return
 
     w = WORKLOADS[args.workload]
     over = {k: v for k, v in (("block", args.block), ("halo", args.halo), ("L", args.long_step),
