@@ -962,11 +962,11 @@ static int reverse(const AdjTarget& t, const void* checkpoints, void* grad, doub
         st = reserve_fields(t, &w->subs, &w->subs_cap, n_sub);
         if (st) return st;
     }
-    if (overlap && !w->aux) {
-        if (hipStreamCreateWithFlags(&w->aux, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&w->fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&w->join, hipEventDisableTiming) != hipSuccess)
-            return fail(MPA_EDEVICE, "adjoint: stream or event creation failed");
+    if (overlap) {
+        const bool ok = (w->aux || hipStreamCreateWithFlags(&w->aux, hipStreamNonBlocking) == hipSuccess) &&
+                        (w->fork || hipEventCreateWithFlags(&w->fork, hipEventDisableTiming) == hipSuccess) &&
+                        (w->join || hipEventCreateWithFlags(&w->join, hipEventDisableTiming) == hipSuccess);
+        if (!ok) return fail(MPA_EDEVICE, "adjoint: stream or event creation failed");
     }
 
     void* ga = w->ga;
