@@ -148,6 +148,7 @@ class MPABatchPlan:
         self.n = sum(self.ns)
         self.precision, self.device = int(precision), int(device)
         self.n_seg = len(dmmap.seg_len)
+        self.coefficients = tuple(tuple(float(v) for v in getattr(dmmap, f)) for f in ("sigma", "beta2", "beta3"))
         p = _lib.make_params(max(self.ns), dt, L, M, n_iter, block, halo, precision, omega_band)
         m = _lib.MapStruct(dmmap)
         d = _lib.BatchDesc(self.ns, sigma_scale)

@@ -8,6 +8,10 @@ checkpoint per map period (mpa_propagate_checkpointed); the backward runs
 mpa_adjoint, which recomputes each period from its checkpoint.  The map
 coefficients are baked into the plan's tables, so the tensors passed must
 hold the plan's values; their gradients are returned as FP64.
+
+`plan` may also be an MPABatchPlan: `field` is then the instances'
+concatenated fields, and the coefficient gradients are those of the map the
+instances share (each instance's sigma is the map's times its scale).
 """
 from __future__ import annotations
 

@@ -9,7 +9,9 @@ through the C ABI).
 * the shared parameter derivatives are the sum of the per-instance ones,
   the sigma derivative weighted by each instance's sigma scale (the sums are
   taken in another order, so to 1e-12 of their norm);
-* an FP64 batch matches the FP64 oracle's gradients instance by instance.
+* an FP64 batch matches the FP64 oracle's gradients instance by instance;
+* the torch.autograd binding over a batch plan returns exactly the C ABI's
+  gradients.
 
 Loss l = sum over instances of sum |A_i(z1) - target_i|^2, so
 G(A_i(z1)) = 2 (A_i(z1) - target_i).
@@ -116,3 +118,34 @@ def test_batch_adjoint_empty_range():
     bp.close()
     assert np.array_equal(to_host(g), before)
     assert not pg.cpu().numpy().any()
+
+
+def test_batch_autograd_binding():
+    """The torch.autograd binding over a batch plan returns exactly the
+    gradients of mpa_batch_adjoint through the C ABI."""
+    import torch
+
+    import paper_1101_0086_amd as P
+    from paper_1101_0086_amd.autograd import propagate
+    ns = [4096, 2048, 8192]
+    scales = [1.0, 1.4, 0.6]
+    fields, _, halo, L = _case(ns, 23, 1024)
+    dmm = dm_map(beta3=0.1)
+    z0, z1 = 1.0 - 2 * L, 1.0 + 3 * L
+    say("batch autograd")
+    bp = P.MPABatchPlan(ns, DT, dmm, L, 2, 2, 1024, halo, P.MPA_C64, BAND, sigma_scale=scales)
+    a = np.concatenate(fields)
+    x = to_dev(a, 0).requires_grad_(True)
+    sig = torch.tensor(dmm.sigma, dtype=torch.float64, requires_grad=True)
+    b3 = torch.tensor(dmm.beta3, dtype=torch.float64, requires_grad=True)
+    out = propagate(bp, x, z0, z1, sigma=sig, beta3=b3)
+    loss = (out.real ** 2 + out.imag ** 2).sum()
+    loss.backward()
+    y = to_dev(a, 0)
+    ck = bp.propagate_checkpointed(y, z0, z1)
+    assert torch.equal(y, out.detach())
+    g = 2 * y
+    pg = bp.adjoint(ck, g, z0, z1)
+    bp.close()
+    assert torch.equal(x.grad, g)
+    assert torch.equal(sig.grad, pg[0].cpu()) and torch.equal(b3.grad, pg[2].cpu())
