@@ -2,7 +2,7 @@
 lumped amplifiers) through the C ABI against the FP64 oracle: full window
 and blocked plans, both precisions, across a span change, an amplifier and a
 period start; the reverse pass against the oracle gradient; split-step plans
-refuse the profile."""
+refuse the profile; a batch with the profile."""
 import math
 
 import numpy as np
@@ -88,3 +88,31 @@ def test_split_step_refuses_distributed_gain():
     with pytest.raises(P.MPAError) as e:
         P.SSPlan(4096, 10 / 256, _raman(dm_map()), 0.01)
     assert e.value.status == -6
+
+
+def test_batch_with_distributed_gain():
+    """A batch (two instances, sigma scales 1 and 0.7) with distributed gain,
+    across an amplifier: each instance against the oracle with its own
+    sigma, FP64."""
+    import paper_1101_0086_amd as P
+    dt, B = 10.0 / 1024, 1024
+    ns, scales = [4096, 8192], [1.0, 0.7]
+    fields = [wdm_field(Grid(n, dt), n // 128, 4, "ook", np.random.default_rng(50 + i)) for i, n in enumerate(ns)]
+    band = 65.0
+    halo = B // 8
+    rate = O.halo_rate(band, 20.0, 0.1)
+    k = math.ceil(0.5 / (0.25 * halo * dt / rate))
+    while (0.5 / k) * rate > 0.25 * halo * dt:
+        k += 1
+    L = 0.5 / k
+    dmm = _raman(dm_map(beta3=0.1))
+    z0, z1 = 1.0 - 3 * L, 1.0 + 2 * L
+    say("distributed gain batch")
+    bp = P.MPABatchPlan(ns, dt, dmm, L, 2, 2, B, halo, P.MPA_C128, band, sigma_scale=scales)
+    x = to_dev(np.concatenate(fields), 1)
+    bp.propagate(x, z0, z1)
+    got = [to_host(v) for v in bp.split(x)]
+    bp.close()
+    for a, sc, g in zip(fields, scales, got):
+        ref = O.mpa_propagate(a, dt, dmm.with_sigma(sc), L, 2, 2, z0, z1, B, halo)
+        assert rel_l2(g, ref) < TOL_F64, sc
