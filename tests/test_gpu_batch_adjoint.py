@@ -5,7 +5,8 @@ through the C ABI).
   own with the instance's sigma (bitwise: the reverse kernel runs the same
   per-block arithmetic, only the work list and the grid differ), in both
   precisions, over a range that crosses an amplifier and a map-period
-  boundary (two checkpoints), with and without inner checkpoints;
+  boundary (two checkpoints), with and without inner checkpoints, and with
+  distributed gain;
 * the shared parameter derivatives are the sum of the per-instance ones,
   the sigma derivative weighted by each instance's sigma scale (the sums are
   taken in another order, so to 1e-12 of their norm);
@@ -44,15 +45,18 @@ def _case(ns, seed, block):
     return fields, g_out, halo, L
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("store_steps", [0, 2])
-def test_batch_adjoint_equals_single_plans(prec, store_steps):
+@pytest.mark.parametrize("prec,store_steps,gain", [(0, 0, False), (0, 2, False), (1, 0, False), (1, 2, False),
+                                                   (0, 0, True)])
+def test_batch_adjoint_equals_single_plans(prec, store_steps, gain):
     import paper_1101_0086_amd as P
+    from workloads.wdm import DMMap
     ns = [8192, 4096, 16384, 2048]
     scales = [1.0, 0.5, 2.0, 0.8]
     block = 2048
     fields, g_out, halo, L = _case(ns, 5, block)
     dmm = dm_map(beta3=0.1)
+    if gain:                                  # distributed gain across the amplifier at 1.0
+        dmm = DMMap(**{**dmm.__dict__, "raman_g0": 0.2, "raman_alpha": 3.0})
     z0, z1 = 1.0 - 3 * L, 1.0 + 2 * L       # amplifier and period start at 1.0
     say("batch adjoint vs single plans", prec, store_steps, ns)
     bp = P.MPABatchPlan(ns, DT, dmm, L, 2, 2, block, halo, prec, BAND, sigma_scale=scales)
