@@ -24,6 +24,9 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
   shift equivariance; sigma = 0 blocked error below the halo bound.
 * ``ss_long_step`` / ``ss_propagate``: linear closed forms; exact SPM
   kick; second order; unitarity; time reversibility.
+* ``ss_long_step_gain`` (split-step with distributed gain): the exact linear
+  solution at sigma = 0, the energy balance exp(2 int G) to rounding, and
+  the uniform-loss split-step when the distributed gain is zero.
 * ``mpa_propagate``: marching and resume identity; lumped gain restores the
   span loss exactly.
 * ``mpa_long_step_vjp`` / ``mpa_blocked_long_step_vjp`` /
@@ -38,6 +41,7 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
 from .nlse import (DMMapSpec, paper_fft, paper_ifft, omega_grid, beta_phase,
                    linear_step, mpa_long_step, mpa_blocked_long_step,
                    block_partition, block_taper, block_mask, halo_rate, mpa_step, mpa_propagate, ss_long_step,
+                   ss_long_step_gain,
                    ss_propagate, reference_propagate, if_trapezoid_long_step,
                    span_of_long_step, rel_l2)
 from .adjoint import (mpa_long_step_vjp, mpa_blocked_long_step_vjp, mpa_propagate_vjp,
@@ -46,6 +50,7 @@ from .adjoint import (mpa_long_step_vjp, mpa_blocked_long_step_vjp, mpa_propagat
 __all__ = ["DMMapSpec", "paper_fft", "paper_ifft", "omega_grid", "beta_phase",
            "linear_step", "mpa_long_step", "mpa_blocked_long_step",
            "block_partition", "block_taper", "block_mask", "halo_rate", "mpa_step", "mpa_propagate", "ss_long_step",
+           "ss_long_step_gain",
            "ss_propagate", "reference_propagate", "if_trapezoid_long_step",
            "span_of_long_step", "rel_l2", "mpa_long_step_vjp", "mpa_blocked_long_step_vjp",
            "mpa_propagate_vjp", "block_mask_grad"]

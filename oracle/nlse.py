@@ -442,11 +442,31 @@ def ss_long_step(a0: np.ndarray, omega: np.ndarray, beta2: float, beta3: float,
     return linear_step(a, omega, beta2, beta3, gamma, dz / 2)
 
 
+def ss_long_step_gain(a0: np.ndarray, omega: np.ndarray, beta2: float, beta3: float,
+                      sigma: float, dmmap, zeta0: float, dz: float, steps: int) -> np.ndarray:
+    """Split-step of Eq. 4 over `steps` steps of dz when G depends on z
+    (distributed gain): every step is the symmetric product of Eq. 4,
+    e^{i L dz/2} e^{i N dz} e^{i L dz/2}, and each linear half step propagates
+    exactly over its own interval, multiplying by exp(int G) over it (zeta0 is
+    the start's position in its amplifier period; the run stays inside it)."""
+    a = a0
+    for j in range(steps):
+        z = zeta0 + j * dz
+        for half, zs in ((0, z), (1, z + dz / 2)):
+            g = float(gain_integral(dmmap, zs, dz / 2))
+            a = paper_ifft(paper_fft(a) * np.exp(1j * beta_phase(omega, beta2, beta3, dz / 2) + g))
+            if half == 0:
+                a = a * np.exp(1j * sigma * np.abs(a) ** 2 * dz)
+    return a
+
+
 def ss_propagate(a: np.ndarray, dt: float, dmmap, dz: float, z0: float,
                  z1: float) -> np.ndarray:
     """Split-step from z0 to z1 with step dz: Eq. 4 applied to every run of
     steps that stays inside one span and ends at the next span boundary,
-    amplifier or z1; lumped gain after a run ending on an amplifier."""
+    amplifier or z1; lumped gain after a run ending on an amplifier.  With
+    distributed gain the runs take ss_long_step_gain and the lumped gain is
+    that of lumped_gain."""
     n = a.shape[0]
     omega = omega_grid(n, dt)
     j0, j1 = _grid_index(z0, dz), _grid_index(z1, dz)
@@ -464,11 +484,17 @@ def ss_propagate(a: np.ndarray, dt: float, dmmap, dz: float, z0: float,
         run = min(acc - r, j1 - j)
         if every:
             run = min(run, every - (j % every))
-        a = ss_long_step(a, omega, dmmap.beta2[s], dmmap.beta3[s], dmmap.sigma[s],
-                         dmmap.gamma, run * dz, run)
+        if _raman(dmmap)[0] > 0:
+            if not every:
+                raise ValueError("distributed gain needs amplifiers (z_amp > 0)")
+            a = ss_long_step_gain(a, omega, dmmap.beta2[s], dmmap.beta3[s], dmmap.sigma[s], dmmap,
+                                  (j % every) * dz, dz, run)
+        else:
+            a = ss_long_step(a, omega, dmmap.beta2[s], dmmap.beta3[s], dmmap.sigma[s],
+                             dmmap.gamma, run * dz, run)
         j += run
         if every and j % every == 0:
-            a = a * math.exp(dmmap.gamma * dmmap.z_amp)
+            a = a * lumped_gain(dmmap)
     return a
 
 

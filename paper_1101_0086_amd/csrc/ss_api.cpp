@@ -24,6 +24,8 @@ struct ss_plan {
     int device = 0;
     int64_t n = 0;
     double dt = 0, dz = 0, gamma = 0, z_amp = 0;
+    double g0 = 0, alpha = 0;  // distributed gain g0 exp(-alpha (z_amp - zeta)), or g0 = 0
+    double lumped = 1;         // amplitude factor of a lumped amplifier
     int precision = 0;
     size_t elem = 8;
     std::vector<double> sigma;
@@ -90,7 +92,6 @@ int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz, int32_t 
     *out = nullptr;
     int st = validate_map_c(map);
     if (st) return st;
-    if (map->raman_g0 > 0) return fail_status(MPA_EUNSUPPORTED, "split-step plans do not model distributed gain");
     if (n < 64 || (n & (n - 1)) != 0 || n > (int64_t(1) << 30))
         return fail_status(MPA_EINVAL, "n must be a power of two in [64, 2^30]");
     if (!(dt > 0) || !std::isfinite(dt) || !(dz > 0) || !std::isfinite(dz))
@@ -114,6 +115,11 @@ int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz, int32_t 
     p->dz = dz;
     p->gamma = map->gamma;
     p->z_amp = map->z_amp;
+    p->g0 = map->raman_g0;
+    p->alpha = map->raman_alpha;
+    // the lumped amplifier makes up what the loss and the distributed gain leave over a period
+    const double dist = p->g0 > 0 ? p->g0 / p->alpha * (1.0 - std::exp(-p->alpha * p->z_amp)) : 0.0;
+    p->lumped = std::exp(p->gamma * p->z_amp - dist);
     p->precision = precision;
     p->elem = precision == MPA_C64 ? 8 : 16;
     p->sigma.assign(map->sigma, map->sigma + map->n_seg);
@@ -190,6 +196,51 @@ int ss_plan_destroy(ss_plan* plan) {
     return MPA_OK;
 }
 
+// int G over [zeta, zeta + h] inside one amplifier period (zeta: position in it)
+static double gain_integral(const ss_plan* p, double zeta, double h) {
+    double g = -p->gamma * h;
+    if (p->g0 > 0)
+        g += p->g0 / p->alpha * (std::exp(-p->alpha * (p->z_amp - zeta - h)) - std::exp(-p->alpha * (p->z_amp - zeta)));
+    return g;
+}
+
+// Distributed gain: G depends on z, so every step is its own symmetric
+// product (linear half step, kick, linear half step), each half step scaled
+// by exp(int G) over its own interval; one launch per step.
+static bool run_steps_gain(ss_plan* p, void* field, int s, int64_t j, int64_t run, bool amp_end, hipStream_t stream) {
+    const double ln = 1.0 / (double)p->n;
+    const double h = 0.5 * p->dz;
+    const void* half_ph = (const char*)p->tables + (size_t)(2 * s) * p->n * p->elem;
+    const void* full_ph = (const char*)p->tables + (size_t)(2 * s + 1) * p->n * p->elem;
+    for (int64_t k = 0; k < run; ++k) {
+        int64_t r = (j + k) % p->amp;
+        if (r < 0) r += p->amp;
+        const double zeta = r * p->dz;
+        const double hs = std::exp(gain_integral(p, zeta, h)) * ln;
+        double es = std::exp(gain_integral(p, zeta + h, h)) * ln;
+        if (amp_end && k == run - 1) es *= p->lumped;
+        if (p->large) {
+            if (!run_large(p, field, half_ph, full_ph, 1, p->sigma[s] * p->dz, hs, hs, es, stream)) return false;
+            continue;
+        }
+        mpa::SSRunArgs a;
+        a.field = field;
+        a.n = p->n;
+        a.half_ph = half_ph;
+        a.full_ph = full_ph;
+        a.twiddle = p->twiddle;
+        a.steps = 1;
+        a.sigma_dz = p->sigma[s] * p->dz;
+        a.half_scale = hs;
+        a.full_scale = hs;
+        a.end_scale = es;
+        a.precision = p->precision;
+        a.stream = stream;
+        if (mpa::launch_ss_run_small(a) != hipSuccess) return false;
+    }
+    return true;
+}
+
 int ss_propagate(ss_plan* p, void* field, double z0, double z1, void* stream) {
     if (!p || !field) return fail_status(MPA_EINVAL, "NULL plan or field");
     const int64_t j0 = grid_index_c(z0, p->dz), j1 = grid_index_c(z1, p->dz);
@@ -215,7 +266,13 @@ int ss_propagate(ss_plan* p, void* field, double z0, double z1, void* stream) {
             if (left < run) run = left;
         }
         const bool amp_end = p->amp > 0 && ((j + run) % p->amp) == 0;
-        const double gain = amp_end ? std::exp(p->gamma * p->z_amp) : 1.0;
+        if (p->g0 > 0) {
+            if (!run_steps_gain(p, field, s, j, run, amp_end, (hipStream_t)stream))
+                return fail_status(MPA_EDEVICE, "split-step launch failed");
+            j += run;
+            continue;
+        }
+        const double gain = amp_end ? p->lumped : 1.0;
         const double hs = std::exp(-0.5 * p->gamma * p->dz) * ln;
         const double fs = std::exp(-p->gamma * p->dz) * ln;
         const void* half_ph = (const char*)p->tables + (size_t)(2 * s) * p->n * p->elem;

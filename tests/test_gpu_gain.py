@@ -2,7 +2,7 @@
 lumped amplifiers) through the C ABI against the FP64 oracle: full window
 and blocked plans, both precisions, across a span change, an amplifier and a
 period start; the reverse pass against the oracle gradient; split-step plans
-refuse the profile; a batch with the profile."""
+with the profile against the oracle's split-step; a batch with the profile."""
 import math
 
 import numpy as np
@@ -83,11 +83,28 @@ def test_reverse_pass_with_distributed_gain():
     assert np.linalg.norm(pg - ref_p) < 1e-9 * np.linalg.norm(ref_p)
 
 
-def test_split_step_refuses_distributed_gain():
+@pytest.mark.parametrize("n,prec", [(1 << 12, 1), (1 << 12, 0), (1 << 14, 1), (1 << 14, 0)])
+def test_split_step_with_distributed_gain(n, prec):
+    """Split-step plans with distributed gain (one symmetric step per launch,
+    each half step scaled by exp(int G) over its interval), the one-workgroup
+    and the four-step paths, across a span change, an amplifier and a period
+    start, against the oracle's split-step with the same G."""
     import paper_1101_0086_amd as P
-    with pytest.raises(P.MPAError) as e:
-        P.SSPlan(4096, 10 / 256, _raman(dm_map()), 0.01)
-    assert e.value.status == -6
+    dt = 10.0 / 1024
+    a = wdm_field(Grid(n, dt), n // 128, 4, "ook", np.random.default_rng(60))
+    dmm = _raman(dm_map(beta3=0.1))
+    dz = 0.5 / 400
+    z0, z1 = 1.0 - 6 * dz, 1.0 + 5 * dz
+    say("split-step distributed gain", n, prec)
+    plan = P.SSPlan(n, dt, dmm, dz, prec)
+    x = to_dev(a, prec)
+    plan.propagate(x, z0, z1)
+    got = to_host(x)
+    plan.close()
+    ref = O.ss_propagate(a, dt, dmm, dz, z0, z1)
+    assert rel_l2(got, ref) < TOL[prec]
+    # without the profile the result differs by far more than the tolerance
+    assert rel_l2(O.ss_propagate(a, dt, dm_map(beta3=0.1), dz, z0, z1), ref) > 1e-3
 
 
 def test_batch_with_distributed_gain():
