@@ -35,7 +35,7 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
   central finite differences of the forward functions above, across a
   span change, an amplifier and the dispersion-dependent roll-off.
 * the FP32 rounding pattern of the GPU path has no oracle: FP32 results
-  are judged against this FP64 oracle ("parity unpinned" for the FP32
+  are compared with this FP64 oracle ("parity unpinned" for the FP32
   rounding pattern itself).
 """
 from .nlse import (DMMapSpec, paper_fft, paper_ifft, omega_grid, beta_phase,
