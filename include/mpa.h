@@ -293,10 +293,10 @@ int mpa_graph_destroy(mpa_graph* graph);
 /* Split-step comparator plan (Eq. 4): step dz must divide every span and
  * z_amp.  Half steps of adjacent split-steps are merged into one spectral
  * multiply; the nonlinear sub-step multiplies by exp(i sigma |A|^2 dz).
- * With distributed gain (raman_g0 > 0) G depends on z: every step is then
- * its own symmetric product, each linear half step scaled by exp(int G)
- * over its interval (one launch per step), and a lumped amplifier applies
- * the factor of mpa_map's rule.                                              */
+ * With distributed gain (raman_g0 > 0) G depends on z: each linear half
+ * step is scaled by exp(int G) over its own interval (N >= 8192: adjacent
+ * half steps merged as without it; N <= 4096: one symmetric step per
+ * launch), and a lumped amplifier applies the factor of mpa_map's rule.     */
 typedef struct ss_plan ss_plan;
 
 int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz,

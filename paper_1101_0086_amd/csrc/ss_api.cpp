@@ -54,7 +54,8 @@ static void ss_free(ss_plan* p) {
 // column FFT, [row: phase (half first, then full); column: inverse FFT, kick, FFT] x steps,
 // row: final half phase (with the gain), column inverse FFT.
 static bool run_large(ss_plan* p, void* field, const void* half_ph, const void* full_ph, int64_t steps,
-                      double sdz, double hs, double fs, double es, hipStream_t stream) {
+                      double sdz, double hs, double fs, double es, hipStream_t stream,
+                      const double* fs_step = nullptr) {
     mpa::SSLargeArgs a;
     a.field = field;
     a.n = p->n;
@@ -77,7 +78,7 @@ static bool run_large(ss_plan* p, void* field, const void* half_ph, const void* 
         a.mode = mpa::SS_COL_MID;
         if (mpa::launch_ss_cols(a) != hipSuccess) return false;
         a.phase = j < steps ? full_ph : half_ph;
-        a.scale = j < steps ? fs : es;
+        a.scale = j < steps ? (fs_step ? fs_step[j - 1] : fs) : es;   // fs_step: per merged full step
         if (mpa::launch_ss_rows(a) != hipSuccess) return false;
     }
     a.mode = mpa::SS_COL_LAST;
@@ -204,14 +205,28 @@ static double gain_integral(const ss_plan* p, double zeta, double h) {
     return g;
 }
 
-// Distributed gain: G depends on z, so every step is its own symmetric
-// product (linear half step, kick, linear half step), each half step scaled
-// by exp(int G) over its own interval; one launch per step.
+// Distributed gain: G depends on z, so each linear half step is scaled by
+// exp(int G) over its own interval.  The four-step path merges adjacent half
+// steps as without it (one full step between kicks k and k+1 covers
+// [zeta_k + dz/2, zeta_k + 3 dz/2]), with per-step scales; the one-workgroup
+// path runs one symmetric step per launch.
 static bool run_steps_gain(ss_plan* p, void* field, int s, int64_t j, int64_t run, bool amp_end, hipStream_t stream) {
     const double ln = 1.0 / (double)p->n;
     const double h = 0.5 * p->dz;
     const void* half_ph = (const char*)p->tables + (size_t)(2 * s) * p->n * p->elem;
     const void* full_ph = (const char*)p->tables + (size_t)(2 * s + 1) * p->n * p->elem;
+    if (p->large) {
+        int64_t r0 = j % p->amp;
+        if (r0 < 0) r0 += p->amp;
+        const double zeta0 = r0 * p->dz;
+        std::vector<double> fsv(run > 1 ? (size_t)(run - 1) : 0);
+        for (int64_t k = 0; k + 1 < run; ++k) fsv[k] = std::exp(gain_integral(p, zeta0 + (k + 0.5) * p->dz, p->dz)) * ln;
+        const double hs = std::exp(gain_integral(p, zeta0, h)) * ln;
+        double es = std::exp(gain_integral(p, zeta0 + (run - 0.5) * p->dz, h)) * ln;
+        if (amp_end) es *= p->lumped;
+        return run_large(p, field, half_ph, full_ph, run, p->sigma[s] * p->dz, hs, hs, es, stream,
+                         fsv.empty() ? nullptr : fsv.data());
+    }
     for (int64_t k = 0; k < run; ++k) {
         int64_t r = (j + k) % p->amp;
         if (r < 0) r += p->amp;
@@ -219,10 +234,6 @@ static bool run_steps_gain(ss_plan* p, void* field, int s, int64_t j, int64_t ru
         const double hs = std::exp(gain_integral(p, zeta, h)) * ln;
         double es = std::exp(gain_integral(p, zeta + h, h)) * ln;
         if (amp_end && k == run - 1) es *= p->lumped;
-        if (p->large) {
-            if (!run_large(p, field, half_ph, full_ph, 1, p->sigma[s] * p->dz, hs, hs, es, stream)) return false;
-            continue;
-        }
         mpa::SSRunArgs a;
         a.field = field;
         a.n = p->n;
