@@ -27,18 +27,37 @@ DEVICE = ["-x", "hip", "--offload-arch=gfx950",
 HOST = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include"]
 
 
+# Block sizes compiled into the long-step kernels (the C++ dispatchers list
+# the same sizes).  The launchers of each (precision, block size) pair of the
+# files below are compiled as separate objects (-DMPA_SPLIT plus
+# -DMPA_PART_T / -DMPA_PART_B), so that the template instantiations build in
+# parallel; the object without a part holds the dispatching code.
+BLOCKS = (512, 1024, 2048, 4096)
+SPLIT = ("mpa_kernels.hip", "adjoint_kernels.hip")
+
+
 def _sources():
     out = []
     for f in sorted(os.listdir(CSRC)):
+        src = os.path.join(CSRC, f)
         if f.endswith(".hip"):
-            out.append((os.path.join(CSRC, f), DEVICE))
+            if f in SPLIT:
+                out.append((src, DEVICE + ["-DMPA_SPLIT"], f + ".o"))
+                for t in ("float", "double"):
+                    for b in BLOCKS:
+                        out.append((src, DEVICE + ["-DMPA_SPLIT", f"-DMPA_PART_T={t}", f"-DMPA_PART_B={b}"],
+                                    f"{f}.{t}{b}.o"))
+            else:
+                out.append((src, DEVICE, f + ".o"))
         elif f.endswith(".cpp"):
-            out.append((os.path.join(CSRC, f), HOST))
+            out.append((src, HOST, f + ".o"))
+    # longest compiles first
+    out.sort(key=lambda x: 0 if "MPA_PART_T" in " ".join(x[1]) and "adjoint" in x[0] else 1)
     return out
 
 
-def _compile(src, flags):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+def _compile(src, flags, objname):
+    obj = os.path.join(BUILD, objname)
     cmd = [HIPCC] + COMMON + flags + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -46,7 +65,8 @@ def _compile(src, flags):
     return obj, r.stderr
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    jobs = jobs or min(16, os.cpu_count() or 8)
     os.makedirs(BUILD, exist_ok=True)
     srcs = _sources()
     with cf.ThreadPoolExecutor(max_workers=min(jobs, len(srcs))) as ex:

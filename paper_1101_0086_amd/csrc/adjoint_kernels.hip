@@ -114,6 +114,7 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ fin, const cx<double>* __rest
     }
 }
 
+#if !defined(MPA_PART_T)
 // g_in[i] = sum over the windows b containing sample i of g_blk[b][i - (b C - H) mod N],
 // per field of a batch (offset != nullptr: instance by binary search over the
 // offsets, its items from item_base); workgroup 0 also adds the work items'
@@ -192,7 +193,19 @@ __global__ void zero_kernel(double* __restrict__ p, long long count) {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0.0;
 }
+#endif  // !MPA_PART_T
 
+// The launchers of one (T, B) pair are compiled in a translation unit of
+// their own when the build splits this file (MPA_SPLIT: the dispatching code
+// is compiled with only their declarations; each part, MPA_PART_T and
+// MPA_PART_B, instantiates one pair), so that the instantiations compile in
+// parallel.  Compiled without MPA_SPLIT the file is self-contained.
+template <typename T, int B>
+hipError_t adjoint_nit(const AdjointStepArgs& a);
+template <typename T, int B>
+int adjoint_occupancy(int n_iter);
+
+#if !defined(MPA_SPLIT) || defined(MPA_PART_T)
 template <typename T, int B, int NIT>
 static hipError_t adjoint_typed(const AdjointStepArgs& a) {
     const BatchItems* bt = a.batch;
@@ -214,7 +227,7 @@ static hipError_t adjoint_typed(const AdjointStepArgs& a) {
 }
 
 template <typename T, int B>
-static hipError_t adjoint_nit(const AdjointStepArgs& a) {
+hipError_t adjoint_nit(const AdjointStepArgs& a) {
     switch (a.n_iter) {
         case 1: return adjoint_typed<T, B, 1>(a);
         case 2: return adjoint_typed<T, B, 2>(a);
@@ -225,6 +238,28 @@ static hipError_t adjoint_nit(const AdjointStepArgs& a) {
     }
 }
 
+// workgroups of the reverse kernel resident on one CU at once (0: unknown)
+template <typename T, int B>
+int adjoint_occupancy(int n_iter) {
+    const void* f = nullptr;
+    switch (n_iter) {
+        case 1: f = reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, B, 1>); break;
+        case 2: f = reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, B, 2>); break;
+        case 3: f = reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, B, 3>); break;
+        case 4: f = reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, B, 4>); break;
+        case 5: f = reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, B, 5>); break;
+        default: return 0;
+    }
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, B / PTS, 0) != hipSuccess) n = 0;
+    return n;
+}
+#endif
+
+#if defined(MPA_PART_T)
+template hipError_t adjoint_nit<MPA_PART_T, MPA_PART_B>(const AdjointStepArgs&);
+template int adjoint_occupancy<MPA_PART_T, MPA_PART_B>(int);
+#else
 template <typename T>
 static hipError_t adjoint_b(const AdjointStepArgs& a) {
     switch (a.block) {
@@ -238,17 +273,13 @@ static hipError_t adjoint_b(const AdjointStepArgs& a) {
 
 template <typename T>
 static int per_cu_b(int block, int n_iter) {
-    int n = 0;
-    auto q = [&](const void* f) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block / PTS, 0) != hipSuccess) n = 0;
-    };
-#define MPA_ADJ_OCC(BB, NN) \
-    if (block == BB && n_iter == NN) q(reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, BB, NN>));
-#define MPA_ADJ_OCC_B(BB) MPA_ADJ_OCC(BB, 1) MPA_ADJ_OCC(BB, 2) MPA_ADJ_OCC(BB, 3) MPA_ADJ_OCC(BB, 4) MPA_ADJ_OCC(BB, 5)
-    MPA_ADJ_OCC_B(512) MPA_ADJ_OCC_B(1024) MPA_ADJ_OCC_B(2048) MPA_ADJ_OCC_B(4096)
-#undef MPA_ADJ_OCC_B
-#undef MPA_ADJ_OCC
-    return n;
+    switch (block) {
+        case 512: return adjoint_occupancy<T, 512>(n_iter);
+        case 1024: return adjoint_occupancy<T, 1024>(n_iter);
+        case 2048: return adjoint_occupancy<T, 2048>(n_iter);
+        case 4096: return adjoint_occupancy<T, 4096>(n_iter);
+        default: return 0;
+    }
 }
 
 int adjoint_workgroups_per_cu(int precision, int block, int n_iter) {
@@ -304,5 +335,7 @@ hipError_t launch_zero(double* p, int64_t count, hipStream_t stream) {
     hipLaunchKernelGGL(zero_kernel, dim3(grid), dim3(tpb), 0, stream, p, (long long)count);
     return hipGetLastError();
 }
+
+#endif  // MPA_PART_T
 
 }  // namespace mpa

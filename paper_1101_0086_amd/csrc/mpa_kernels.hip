@@ -100,12 +100,15 @@ mpa_batch_kernel(const cx<T>* __restrict__ fin, cx<T>* __restrict__ fout,
     }
 }
 
-template <typename T>
-__global__ void copy_field_kernel(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, long long count) {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) dst[i] = src[i];
-}
+// The launchers of one (T, B) pair are compiled in a translation unit of
+// their own when the build splits this file (MPA_SPLIT: the dispatching code
+// sees only their declarations; each part, MPA_PART_T and MPA_PART_B,
+// instantiates one pair), so that the instantiations compile in parallel.
+// Compiled without MPA_SPLIT the file is self-contained.
+template <typename T, int B>
+hipError_t launch_nit(const BlockStepArgs& a);
 
+#if !defined(MPA_SPLIT) || defined(MPA_PART_T)
 template <typename T>
 static StepTables<T> tables_of(const BlockStepArgs& a) {
     return StepTables<T>{static_cast<const cx<T>*>(a.phase), static_cast<const cx<double>*>(a.phase_last),
@@ -135,7 +138,7 @@ static hipError_t launch_typed(const BlockStepArgs& a) {
 }
 
 template <typename T, int B>
-static hipError_t launch_nit(const BlockStepArgs& a) {
+hipError_t launch_nit(const BlockStepArgs& a) {
     switch (a.n_iter) {
         case 1: return launch_typed<T, B, 1>(a);
         case 2: return launch_typed<T, B, 2>(a);
@@ -144,6 +147,17 @@ static hipError_t launch_nit(const BlockStepArgs& a) {
         case 5: return launch_typed<T, B, 5>(a);
         default: return hipErrorInvalidValue;
     }
+}
+
+#endif
+
+#if defined(MPA_PART_T)
+template hipError_t launch_nit<MPA_PART_T, MPA_PART_B>(const BlockStepArgs&);
+#else
+template <typename T>
+__global__ void copy_field_kernel(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, long long count) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) dst[i] = src[i];
 }
 
 template <typename T>
@@ -228,5 +242,7 @@ hipError_t launch_phase_table(void* table, int precision, int B, int rows, const
                            static_cast<cx<double>*>(table), B, rows, coef, mask);
     return hipGetLastError();
 }
+
+#endif  // MPA_PART_T
 
 }  // namespace mpa
