@@ -40,7 +40,8 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
 """
 from .nlse import (DMMapSpec, paper_fft, paper_ifft, omega_grid, beta_phase,
                    linear_step, mpa_long_step, mpa_blocked_long_step,
-                   block_partition, block_taper, block_mask, halo_rate, mpa_step, mpa_propagate, ss_long_step,
+                   block_partition, block_taper, block_mask, halo_rate, group_delay_range,
+                   halo_excursion, mpa_step, mpa_propagate, ss_long_step,
                    ss_long_step_gain,
                    ss_propagate, reference_propagate, if_trapezoid_long_step,
                    span_of_long_step, rel_l2)
@@ -49,7 +50,8 @@ from .adjoint import (mpa_long_step_vjp, mpa_blocked_long_step_vjp, mpa_propagat
 
 __all__ = ["DMMapSpec", "paper_fft", "paper_ifft", "omega_grid", "beta_phase",
            "linear_step", "mpa_long_step", "mpa_blocked_long_step",
-           "block_partition", "block_taper", "block_mask", "halo_rate", "mpa_step", "mpa_propagate", "ss_long_step",
+           "block_partition", "block_taper", "block_mask", "halo_rate", "group_delay_range",
+           "halo_excursion", "mpa_step", "mpa_propagate", "ss_long_step",
            "ss_long_step_gain",
            "ss_propagate", "reference_propagate", "if_trapezoid_long_step",
            "span_of_long_step", "rel_l2", "mpa_long_step_vjp", "mpa_blocked_long_step_vjp",

@@ -37,16 +37,16 @@ def _raised_cosine_slope(x):
     return np.where((x > 0) & (x < 1), -0.5 * math.pi * np.sin(math.pi * np.clip(x, 0, 1)), 0.0)
 
 
-def block_mask_grad(omega_b, beta2, beta3, L, halo, dt):
+def block_mask_grad(omega_b, beta2, beta3, L, halo, dt, shift=0):
     """Derivatives of ``nlse.block_mask`` with respect to beta2 and beta3.
 
     Only the first roll-off depends on them, through
-    g = |u| L / (halo dt), u = beta2 omega + beta3 omega^2 / 2:
+    g = |u| / (halo dt), u = (beta2 omega + beta3 omega^2 / 2) L - shift dt:
     dg/dbeta2 = sign(u) omega L / (halo dt), dg/dbeta3 = sign(u) omega^2 L / (2 halo dt)."""
-    u = beta2 * omega_b + 0.5 * beta3 * omega_b ** 2
+    u = (beta2 * omega_b + 0.5 * beta3 * omega_b ** 2) * L - shift * dt
     scale = L / (halo * dt)
     width = MASK_STOP - MASK_PASS
-    x1 = (np.abs(u) * scale - MASK_PASS) / width
+    x1 = (np.abs(u) / (halo * dt) - MASK_PASS) / width
     r = np.abs(omega_b) * dt / math.pi
     other = _raised_cosine_drop((r - NYQ_PASS) / (NYQ_STOP - NYQ_PASS))
     dm_dg = _raised_cosine_slope(x1) / width * other
@@ -131,7 +131,7 @@ def mpa_long_step_vjp(a_z0, omega, beta2, beta3, sigma, gamma, L, M, n_iter, g_o
 
 
 def mpa_blocked_long_step_vjp(a_z0, dt, block, halo, beta2, beta3, sigma, gamma, L, M,
-                              n_iter, g_out, int_g=None):
+                              n_iter, g_out, int_g=None, shift=0):
     """VJP of ``nlse.mpa_blocked_long_step`` (tapered windows, roll-off,
     cores stitched): window gradients are the core of g_out, zero elsewhere;
     the input gradient adds every window's contribution."""
@@ -141,14 +141,15 @@ def mpa_blocked_long_step_vjp(a_z0, dt, block, halo, beta2, beta3, sigma, gamma,
                                  n_iter, g_out, int_g=int_g)
     omega_b = omega_grid(block, dt)
     taper = block_taper(block, halo)
-    mask = block_mask(omega_b, beta2, beta3, L, halo, dt) if halo > 0 else None
-    mask_grad = block_mask_grad(omega_b, beta2, beta3, L, halo, dt) if halo > 0 else None
+    mask = block_mask(omega_b, beta2, beta3, L, halo, dt, shift) if halo > 0 else None
+    mask_grad = block_mask_grad(omega_b, beta2, beta3, L, halo, dt, shift) if halo > 0 else None
     g_in = np.zeros(n, dtype=np.complex128)
     ds = d2 = d3 = 0.0
-    for w0, c0, clen in block_partition(n, block, halo):
+    lead = halo + shift
+    for w0, c0, clen in block_partition(n, block, halo, shift):
         idx = (w0 + np.arange(block)) % n
         gw = np.zeros(block, dtype=np.complex128)
-        gw[halo:halo + clen] = g_out[c0:c0 + clen]
+        gw[lead:lead + clen] = g_out[c0:c0 + clen]
         ga, s_, b2_, b3_ = mpa_long_step_vjp(a_z0[idx] * taper, omega_b, beta2, beta3, sigma,
                                              gamma, L, M, n_iter, gw, out_mask=mask,
                                              mask_grad=mask_grad, int_g=int_g)
@@ -159,7 +160,7 @@ def mpa_blocked_long_step_vjp(a_z0, dt, block, halo, beta2, beta3, sigma, gamma,
     return g_in, ds, d2, d3
 
 
-def mpa_propagate_vjp(a, dt, dmmap, L, M, n_iter, z0, z1, g_out, block=0, halo=0):
+def mpa_propagate_vjp(a, dt, dmmap, L, M, n_iter, z0, z1, g_out, block=0, halo=0, shift=0):
     """Gradient through ``nlse.mpa_propagate``: returns (G(a), dl/dsigma per
     span, dl/dbeta2 per span, dl/dbeta3 per span).  The forward is re-run storing the input of
     every long step."""
@@ -168,7 +169,7 @@ def mpa_propagate_vjp(a, dt, dmmap, L, M, n_iter, z0, z1, g_out, block=0, halo=0
     inputs = []
     for m in range(m0, m1):
         inputs.append(a)
-        a = mpa_step(a, dt, dmmap, L, M, n_iter, m, block, halo)
+        a = mpa_step(a, dt, dmmap, L, M, n_iter, m, block, halo, shift)
     nspan = len(dmmap.seg_len)
     g_sigma = np.zeros(nspan)
     g_beta2 = np.zeros(nspan)
@@ -181,7 +182,8 @@ def mpa_propagate_vjp(a, dt, dmmap, L, M, n_iter, z0, z1, g_out, block=0, halo=0
             g = g * lumped_gain(dmmap)
         g, ds, d2, d3 = mpa_blocked_long_step_vjp(
             inputs[m - m0], dt, block or len(a), halo, dmmap.beta2[s], dmmap.beta3[s],
-            dmmap.sigma[s], dmmap.gamma, L, M, n_iter, g, int_g=long_step_gain(dmmap, L, M, m))
+            dmmap.sigma[s], dmmap.gamma, L, M, n_iter, g, int_g=long_step_gain(dmmap, L, M, m),
+            shift=shift)
         g_sigma[s] += ds
         g_beta2[s] += d2
         g_beta3[s] += d3

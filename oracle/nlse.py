@@ -166,13 +166,18 @@ def if_trapezoid_long_step(a_z0: np.ndarray, omega: np.ndarray, beta2: float,
 # Time blocking (not in the paper; the partition rule the library uses)
 # --------------------------------------------------------------------------
 
-def block_partition(n: int, block: int, halo: int) -> List[Tuple[int, int, int]]:
-    """Blocks of ``block`` samples overlapping by ``halo`` per side.
+def block_partition(n: int, block: int, halo: int, shift: int = 0) -> List[Tuple[int, int, int]]:
+    """Blocks of ``block`` samples overlapping by ``2 halo``.
 
     Block b owns the core [b C, min((b+1) C, n)) with C = block - 2 halo and
-    reads the periodic window starting at b C - halo.  Returns
-    (window_start, core_start, core_len) per block.  block = n (halo = 0)
-    gives the single full window.
+    reads the periodic window starting at b C - halo - shift: the core sits
+    halo + shift samples into its window, so a window shift moves the window
+    towards earlier times by ``shift`` samples (halo + shift before the core,
+    halo - shift after it).  Content travels towards later times when its
+    group delay beta2 omega + beta3 omega^2 / 2 is positive, so a shift near
+    the middle of the band's group delay over L keeps the core's domain of
+    dependence centred in its window.  Returns (window_start, core_start,
+    core_len) per block.  block = n (halo = 0) gives the single full window.
     """
     if block == n and halo == 0:
         return [(0, 0, n)]
@@ -181,7 +186,7 @@ def block_partition(n: int, block: int, halo: int) -> List[Tuple[int, int, int]]
     out = []
     for b in range(nb):
         c0 = b * core
-        out.append((c0 - halo, c0, min(core, n - c0)))
+        out.append((c0 - halo - shift, c0, min(core, n - c0)))
     return out
 
 
@@ -220,7 +225,7 @@ def _raised_cosine_drop(x: np.ndarray) -> np.ndarray:
 
 
 def block_mask(omega_b: np.ndarray, beta2: float, beta3: float, L: float, halo: int,
-               dt: float) -> np.ndarray:
+               dt: float, shift: int = 0) -> np.ndarray:
     """Spectral roll-off applied to each block's spectrum when it is
     reconstructed (step 7 of a blocked long step).
 
@@ -230,10 +235,12 @@ def block_mask(omega_b: np.ndarray, beta2: float, beta3: float, L: float, halo: 
     tapered outer halo, and, when beta3 != 0, content at the grid's Nyquist
     frequency, where the odd beta3 term makes beta(omega) jump between
     +pi/dt and -pi/dt.  The mask is the product of two raised-cosine
-    roll-offs: in g = |beta2 omega + beta3 omega^2 / 2| L / (halo dt), from 1
-    at g = 0.35 to 0 at g = 0.5 (the halo rule keeps the signal band at
-    g <= 0.25), and in |omega| dt / pi, from 1 at 0.8 to 0 at 0.9."""
-    g = np.abs(beta2 * omega_b + 0.5 * beta3 * omega_b ** 2) * L / (halo * dt)
+    roll-offs: in g = |(beta2 omega + beta3 omega^2 / 2) L - shift dt| / (halo dt)
+    (the displacement of content over the long step relative to the window
+    shift, in units of the halo duration), from 1 at g = 0.35 to 0 at
+    g = 0.5 (the halo rule keeps the signal band at g <= 0.25), and in
+    |omega| dt / pi, from 1 at 0.8 to 0 at 0.9."""
+    g = np.abs((beta2 * omega_b + 0.5 * beta3 * omega_b ** 2) * L - shift * dt) / (halo * dt)
     r = np.abs(omega_b) * dt / math.pi
     return (_raised_cosine_drop((g - MASK_PASS) / (MASK_STOP - MASK_PASS))
             * _raised_cosine_drop((r - NYQ_PASS) / (NYQ_STOP - NYQ_PASS)))
@@ -242,27 +249,33 @@ def block_mask(omega_b: np.ndarray, beta2: float, beta3: float, L: float, halo: 
 def mpa_blocked_long_step(a_z0: np.ndarray, dt: float, block: int, halo: int,
                           beta2: float, beta3: float, sigma: float, gamma: float,
                           L: float, M: int, n_iter: int, int_g=None, node_beta=None,
-                          node_sigma=None) -> np.ndarray:
+                          node_sigma=None, shift: int = 0) -> np.ndarray:
     """One MPA long step run independently on every periodic block window
     (frequency grid of the block: omega^B = 2 pi fftfreq(block, dt)), keeping
     each block's core.  Each window is multiplied by :func:`block_taper`
-    first and each block's final spectrum by :func:`block_mask`."""
+    first and each block's final spectrum by :func:`block_mask`.  ``shift``
+    moves every window against its core (see :func:`block_partition`); the
+    core must stay clear of the tapered outer halo/2 samples, |shift| <= halo/2."""
     n = a_z0.shape[0]
     if block == 0 or (block == n and halo == 0):
         return mpa_long_step(a_z0, omega_grid(n, dt), beta2, beta3, sigma, gamma,
                              L, M, n_iter, int_g=int_g, node_beta=node_beta, node_sigma=node_sigma)
+    if abs(shift) > halo // 2:
+        raise ValueError(f"window shift {shift} exceeds halo/2 = {halo // 2}")
     omega_b = omega_grid(block, dt)
     taper = block_taper(block, halo)
+    bet2, bet3 = beta2, beta3
     if node_beta is not None:      # the step's group delay: integrated coefficients over L
-        beta2, beta3 = node_beta[0][-1] / L, node_beta[1][-1] / L
-    mask = block_mask(omega_b, beta2, beta3, L, halo, dt) if halo > 0 else None
+        bet2, bet3 = node_beta[0][-1] / L, node_beta[1][-1] / L
+    mask = block_mask(omega_b, bet2, bet3, L, halo, dt, shift) if halo > 0 else None
     out = np.empty_like(a_z0)
-    for w0, c0, clen in block_partition(n, block, halo):
+    lead = halo + shift
+    for w0, c0, clen in block_partition(n, block, halo, shift):
         idx = (w0 + np.arange(block)) % n
         res = mpa_long_step(a_z0[idx] * taper, omega_b, beta2, beta3, sigma, gamma,
                             L, M, n_iter, out_mask=mask, int_g=int_g, node_beta=node_beta,
                             node_sigma=node_sigma)
-        out[c0:c0 + clen] = res[halo:halo + clen]
+        out[c0:c0 + clen] = res[lead:lead + clen]
     return out
 
 
@@ -270,6 +283,27 @@ def halo_rate(omega_band: float, beta2: float, beta3: float) -> float:
     """Largest group-delay rate |beta2 omega + beta3 omega^2 / 2| over
     |omega| <= omega_band (time shift per unit z of the fastest content)."""
     return abs(beta2) * omega_band + 0.5 * abs(beta3) * omega_band ** 2
+
+
+def group_delay_range(omega_band: float, beta2: float, beta3: float):
+    """(min, max) of the group-delay rate beta2 omega + beta3 omega^2 / 2 over
+    |omega| <= omega_band: the values at both band edges and, when the
+    parabola's vertex -beta2/beta3 lies inside the band, at the vertex."""
+    w = float(omega_band)
+    vals = [beta2 * w + 0.5 * beta3 * w * w, -beta2 * w + 0.5 * beta3 * w * w]
+    if beta3 != 0 and abs(beta2 / beta3) <= w:
+        vals.append(-0.5 * beta2 * beta2 / beta3)
+    return min(vals), max(vals)
+
+
+def halo_excursion(omega_band: float, beta2: float, beta3: float, L: float, shift: int,
+                   dt: float) -> float:
+    """Largest displacement over one long step of content in the band,
+    relative to the window shift: max |(beta2 omega + beta3 omega^2 / 2) L -
+    shift dt| over |omega| <= omega_band (its extremes lie at the ends of the
+    group-delay range)."""
+    lo, hi = group_delay_range(omega_band, beta2, beta3)
+    return max(abs(lo * L - shift * dt), abs(hi * L - shift * dt))
 
 
 # --------------------------------------------------------------------------
@@ -386,7 +420,7 @@ def long_step_gain(dmmap, L: float, M: int, m: int):
 
 
 def mpa_step(a: np.ndarray, dt: float, dmmap, L: float, M: int, n_iter: int,
-             m: int, block: int = 0, halo: int = 0) -> np.ndarray:
+             m: int, block: int = 0, halo: int = 0, shift: int = 0) -> np.ndarray:
     """Long step m ([m L, (m+1) L]), then the lumped gain if an amplifier
     sits at (m+1) L (exp(gamma z_a) without distributed gain)."""
     spans = long_step_spans(dmmap, L, m)
@@ -394,13 +428,13 @@ def mpa_step(a: np.ndarray, dt: float, dmmap, L: float, M: int, n_iter: int,
         s = spans[0]
         out = mpa_blocked_long_step(a, dt, block or a.shape[0], halo, dmmap.beta2[s],
                                     dmmap.beta3[s], dmmap.sigma[s], dmmap.gamma,
-                                    L, M, n_iter, int_g=long_step_gain(dmmap, L, M, m))
+                                    L, M, n_iter, int_g=long_step_gain(dmmap, L, M, m), shift=shift)
     else:
         # the step crosses a span boundary: exact beta integrals, sigma sampled at the nodes
         node_beta, node_sigma = step_coefficients(dmmap, L, M, m)
         out = mpa_blocked_long_step(a, dt, block or a.shape[0], halo, 0.0, 0.0, 0.0, dmmap.gamma,
                                     L, M, n_iter, int_g=long_step_gain(dmmap, L, M, m),
-                                    node_beta=node_beta, node_sigma=node_sigma)
+                                    node_beta=node_beta, node_sigma=node_sigma, shift=shift)
     every = _amp_every(dmmap, L)
     if every and (m + 1) % every == 0:
         out = out * lumped_gain(dmmap)
@@ -415,11 +449,11 @@ def _grid_index(z: float, h: float) -> int:
 
 
 def mpa_propagate(a: np.ndarray, dt: float, dmmap, L: float, M: int, n_iter: int,
-                  z0: float, z1: float, block: int = 0, halo: int = 0) -> np.ndarray:
+                  z0: float, z1: float, block: int = 0, halo: int = 0, shift: int = 0) -> np.ndarray:
     """March long steps from z0 to z1 (both on the long-step grid)."""
     m0, m1 = _grid_index(z0, L), _grid_index(z1, L)
     for m in range(m0, m1):
-        a = mpa_step(a, dt, dmmap, L, M, n_iter, m, block, halo)
+        a = mpa_step(a, dt, dmmap, L, M, n_iter, m, block, halo, shift)
     return a
 
 

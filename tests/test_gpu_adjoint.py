@@ -26,14 +26,33 @@ pytestmark = pytest.mark.gpu
 # forward and the reverse pass run in FP32 (unit roundoff 6e-8, FFT error
 # about 2e-7 relative), the output-sized gradient and the carry in FP64.  The
 # field gradient stays within 1e-5.  The parameter derivatives are compared
-# as one vector (sigma, beta2, beta3 of every span) relative to its norm,
-# within 1e-3: the beta2 and beta3 derivatives weight every frequency by
-# omega^2 z / 2 and omega^3 z / 6, which amplifies the FP32 rounding noise
-# of the nearly empty spectrum up to |omega| = pi / dt (a beta3 derivative
-# of 0.16 is off by 7e-4 on the 4096-mode case, 0.5 %, while the FP64 plan
-# matches to 1e-9).
+# as one vector (sigma, beta2, beta3 of every span) relative to its norm:
+# within 1e-4 when the loss only looks at the signal band (a target in the
+# band), within 1e-3 when the target carries white noise.  Reason for the
+# second bound: the FP32 transform of |A|^2 A leaves rounding noise of about
+# 1e-7 of its largest value at every frequency, and the beta2 and beta3
+# derivatives weight each frequency's product of that increment with its
+# adjoint by omega^2 z / 2 and omega^3 z / 6; a white-noise target gives the
+# adjoint O(1) content up to |omega| = pi / dt, where the weights exceed the
+# band's by (pi / dt / omega_band)^3 (4096 on the 4096-mode case), so the
+# noise enters the beta3 derivative at ~1e-7 * 4096 relative.  The FP32
+# forward map itself carries that noise, so this is a property of FP32 node
+# evaluations, not of the reverse pass (the FP64 plan matches to 1e-9).
 TOL_G = {1: 1e-10, 0: 1e-5}
-TOL_P = {1: 1e-9, 0: 1e-3}
+TOL_P = {1: 1e-9, 0: 1e-4}
+TOL_P_BROADBAND_F32 = 1e-3
+
+
+def _target(a, dt, rng, scale, noise, band=None):
+    """scale * a plus complex white noise of rms `noise`, or, with `band`,
+    the same noise restricted to |omega| <= band (a loss on the signal band)."""
+    nz = noise * (rng.normal(size=a.size) + 1j * rng.normal(size=a.size))
+    if band is not None:
+        omega = 2 * np.pi * np.fft.fftfreq(a.size, dt)
+        spec = np.fft.fft(nz)
+        spec[np.abs(omega) > band] = 0
+        nz = np.fft.ifft(spec)
+    return scale * a + nz
 
 
 def _plan(grid, dmmap, L, M, nit, block, halo, prec, band=0.0):
@@ -49,12 +68,14 @@ def _gpu_grad(plan, a, g_out, z0, z1, prec, store_steps=0):
     return to_host(x), to_host(g), pg.cpu().numpy()
 
 
-def _compare(prec, got_g, got_p, ref_g, ref_p):
+def _compare(prec, got_g, got_p, ref_g, ref_p, broadband=False):
     eg = rel_l2(got_g, ref_g)
     ref_p = np.asarray(ref_p)
     ep = float(np.linalg.norm(got_p - ref_p) / np.linalg.norm(ref_p))
+    say("gradient errors", prec, "field", eg, "parameters", ep, "broadband" if broadband else "in band")
+    tol_p = TOL_P_BROADBAND_F32 if (broadband and prec == 0) else TOL_P[prec]
     assert eg < TOL_G[prec], ("field gradient", eg)
-    assert ep < TOL_P[prec], ("parameter derivatives", ep, got_p, ref_p)
+    assert ep < tol_p, ("parameter derivatives", ep, got_p, ref_p)
 
 
 def _oracle(a, dt, dmmap, L, M, nit, z0, z1, target, block=0, halo=0):
@@ -64,20 +85,20 @@ def _oracle(a, dt, dmmap, L, M, nit, z0, z1, target, block=0, halo=0):
     return out, g_out, g, np.stack([gs, g2, g3])
 
 
-@pytest.mark.parametrize("prec", [1, 0])
-def test_full_window_across_span_amplifier_and_period(prec):
+@pytest.mark.parametrize("prec,band", [(1, None), (0, None), (0, 10.0)])
+def test_full_window_across_span_amplifier_and_period(prec, band):
     w = WORKLOADS["dm1ch_n4096_f64"]
     s = w.mpa
     a = w.field()
     rng = np.random.default_rng(11)
-    target = a * 0.8 + 0.05 * (rng.normal(size=a.size) + 1j * rng.normal(size=a.size))
+    target = _target(a, w.grid.dt, rng, 0.8, 0.05, band)
     z0, z1 = 0.4, 1.1                      # span change at 0.5, amplifier and period start at 1.0
     _, g_out, ref_g, ref_p = _oracle(a, w.grid.dt, w.dmmap, s.L, s.M, s.n_iter, z0, z1, target)
     say("adjoint full window", prec)
     plan = _plan(w.grid, w.dmmap, s.L, s.M, s.n_iter, 0, 0, prec)
     assert plan.checkpoint_count(z0, z1) == 2
     _, got_g, got_p = _gpu_grad(plan, a, g_out, z0, z1, prec)
-    _compare(prec, got_g, got_p, ref_g, ref_p)
+    _compare(prec, got_g, got_p, ref_g, ref_p, broadband=band is None)
 
 
 def _blocked(block, n=1 << 13, ch=4, seed=7):
@@ -93,19 +114,20 @@ def _blocked(block, n=1 << 13, ch=4, seed=7):
     return grid, a, band, halo, 0.5 / k
 
 
-@pytest.mark.parametrize("block,prec", [(512, 1), (512, 0), (4096, 1), (4096, 0)])
-def test_blocked_across_span_and_amplifier(block, prec):
+@pytest.mark.parametrize("block,prec,inband", [(512, 1, False), (512, 0, False), (512, 0, True),
+                                               (4096, 1, False), (4096, 0, False), (4096, 0, True)])
+def test_blocked_across_span_and_amplifier(block, prec, inband):
     grid, a, band, halo, L = _blocked(block)
     dmmap = dm_map(beta3=0.1)
     rng = np.random.default_rng(12)
-    target = a * 0.9 + 0.02 * (rng.normal(size=a.size) + 1j * rng.normal(size=a.size))
+    target = _target(a, grid.dt, rng, 0.9, 0.02, band if inband else None)
     M, nit = 2, 2
     for z0, z1 in ((0.5 - 2 * L, 0.5 + 2 * L), (1.0 - 2 * L, 1.0 + L)):
         _, g_out, ref_g, ref_p = _oracle(a, grid.dt, dmmap, L, M, nit, z0, z1, target, block, halo)
         say("adjoint blocked", block, prec, z0, z1)
         plan = _plan(grid, dmmap, L, M, nit, block, halo, prec, band)
         _, got_g, got_p = _gpu_grad(plan, a, g_out, z0, z1, prec)
-        _compare(prec, got_g, got_p, ref_g, ref_p)
+        _compare(prec, got_g, got_p, ref_g, ref_p, broadband=not inband)
         plan.close()
 
 
@@ -144,27 +166,43 @@ def test_sweeps_and_nodes(nit):
     _compare(1, got_g, got_p, ref_g, ref_p)
 
 
-@pytest.mark.parametrize("prec", [1, 0])
-def test_c5_full_size_two_long_steps_against_oracle(prec):
+@pytest.mark.parametrize("prec,inband", [(1, False), (0, False), (0, True)])
+def test_c5_full_size_two_long_steps_against_oracle(prec, inband):
     """2^16 modes, 4 OOK channels, B = 2048, H = 256, L = 2.5e-4, M = 2, two
     sweeps, beta3 = 0.1: the launch configuration of the gradient workload."""
     w = WORKLOADS["wdm4_n65536_f32"]
     s = w.mpa
     a = w.field()
     rng = np.random.default_rng(13)
-    target = a + 0.01 * (rng.normal(size=a.size) + 1j * rng.normal(size=a.size))
+    target = _target(a, w.grid.dt, rng, 1.0, 0.01, s.omega_band if inband else None)
     z0, z1 = 0.5 - s.L, 0.5 + s.L
     _, g_out, ref_g, ref_p = _oracle(a, w.grid.dt, w.dmmap, s.L, s.M, s.n_iter, z0, z1, target, s.block, s.halo)
     say("adjoint c5 two steps", prec)
     plan = _plan(w.grid, w.dmmap, s.L, s.M, s.n_iter, s.block, s.halo, prec, s.omega_band)
     _, got_g, got_p = _gpu_grad(plan, a, g_out, z0, z1, prec)
-    _compare(prec, got_g, got_p, ref_g, ref_p)
+    _compare(prec, got_g, got_p, ref_g, ref_p, broadband=not inband)
 
 
-def test_c5_full_period_finite_differences():
-    """Directional derivatives over one whole map period (4000 long steps,
-    FP64 plan) against central differences of the GPU forward: the field
-    along a random direction, and sigma, beta2, beta3 of both spans."""
+# Central differences over one map period: (field step, sigma step, beta2
+# step, beta3 step, tolerance) per precision.  FP64: steps that move the
+# dispersion phase of the signal band (|omega| <= 65) by ~1e-4 rad over a
+# span (linear regime), differences to 1e-6 (field) and 1e-5 (parameters).
+# FP32: the loss of the FP32 forward carries rounding noise of ~1e-7 of its
+# value (measured: differences with a 1e-3 field step were 9e-4 off, i.e. the
+# two losses differed by 7e-8 of the loss beyond the linear change), so the
+# steps are ~100 times larger: a field step of 2e-2 (the loss moves by ~1e-3
+# of itself, noise ~4e-5 of the derivative, truncation of the central
+# difference ~(2e-2)^2 times the nonlinear phase of ~0.05 rad, 2e-5) and
+# parameter steps that move the band's phase by ~1e-2 rad, within 2e-4.
+FD = {1: (1e-5, 1e-4, 1e-7, 4e-9, 1e-6, 1e-5), 0: (2e-2, 1e-2, 1e-5, 4e-7, 2e-4, 2e-4)}
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_c5_full_period_finite_differences(prec):
+    """Directional derivatives over one whole map period (4000 long steps)
+    against central differences of the GPU forward in the same precision:
+    the field along a random direction, and sigma, beta2, beta3 of both
+    spans."""
     import torch
     w = WORKLOADS["wdm4_n65536_f32"]
     s = w.mpa
@@ -172,43 +210,44 @@ def test_c5_full_period_finite_differences():
     rng = np.random.default_rng(14)
     target = a * 0.7
     z0, z1 = 0.0, 1.0
+    eps, h_sig, h_b2, h_b3, tol_g, tol_p = FD[prec]
 
     def loss(dmmap, field):
-        plan = _plan(w.grid, dmmap, s.L, s.M, s.n_iter, s.block, s.halo, 1, s.omega_band)
-        x = to_dev(field, 1)
+        plan = _plan(w.grid, dmmap, s.L, s.M, s.n_iter, s.block, s.halo, prec, s.omega_band)
+        x = to_dev(field, prec)
         plan.propagate(x, z0, z1)
         plan.close()
         return float(np.sum(np.abs(to_host(x) - target) ** 2))
 
-    say("adjoint c5 period: adjoint")
-    plan = _plan(w.grid, w.dmmap, s.L, s.M, s.n_iter, s.block, s.halo, 1, s.omega_band)
-    x = to_dev(a, 1)
+    say("adjoint c5 period: adjoint", prec)
+    plan = _plan(w.grid, w.dmmap, s.L, s.M, s.n_iter, s.block, s.halo, prec, s.omega_band)
+    x = to_dev(a, prec)
     ck = plan.propagate_checkpointed(x, z0, z1)
-    g = 2 * (x - torch.from_numpy(target).to(x.device))
+    g = 2 * (x - torch.from_numpy(target).to(device=x.device, dtype=x.dtype))
     pg = plan.adjoint(ck, g, z0, z1).cpu().numpy()
     g = to_host(g)
     plan.close()
 
     d = rng.normal(size=a.size) + 1j * rng.normal(size=a.size)
     d *= np.linalg.norm(a) / np.linalg.norm(d)
-    eps = 1e-5
-    say("adjoint c5 period: field differences")
+    say("adjoint c5 period: field differences", prec)
     fd = (loss(w.dmmap, a + eps * d) - loss(w.dmmap, a - eps * d)) / (2 * eps)
     ad = float(np.real(np.vdot(g, d)))
-    assert abs(fd - ad) <= 1e-6 * abs(fd), (fd, ad)
-    # steps: a relative 1e-4 for sigma; for beta2 and beta3, steps that move the
-    # dispersion phase of the signal band (|omega| <= 65) by about 1e-4 rad
-    # over a span, so that the differences stay in the linear regime
-    for q, field, h in ((0, "sigma", 1e-4), (1, "beta2", 1e-7), (2, "beta3", 4e-9)):
+    say("field", fd, ad, abs(fd - ad) / abs(fd))
+    bad = [] if abs(fd - ad) <= tol_g * abs(fd) else [("field", fd, ad)]
+    for q, field, h in ((0, "sigma", h_sig), (1, "beta2", h_b2), (2, "beta3", h_b3)):
         for span in (0, 1):
             vals = list(getattr(w.dmmap, field))
             plus, minus = list(vals), list(vals)
             plus[span] += h
             minus[span] -= h
-            say("adjoint c5 period: differences in", field, span)
+            say("adjoint c5 period: differences in", field, span, prec)
             fd = (loss(w.dmmap.__class__(**{**w.dmmap.__dict__, field: tuple(plus)}), a)
                   - loss(w.dmmap.__class__(**{**w.dmmap.__dict__, field: tuple(minus)}), a)) / (2 * h)
-            assert abs(fd - pg[q, span]) <= 1e-5 * abs(fd), (field, span, fd, pg[q, span])
+            say(field, span, fd, pg[q, span], abs(fd - pg[q, span]) / abs(fd))
+            if abs(fd - pg[q, span]) > tol_p * abs(fd):
+                bad.append((field, span, fd, pg[q, span]))
+    assert not bad, bad
 
 
 def test_inner_checkpoints_are_bitwise_identical():

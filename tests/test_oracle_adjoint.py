@@ -2,6 +2,7 @@
 oracle (loss = sum |A_out - A_target|^2, complex directions for the field,
 scalar steps for sigma, beta2, beta3)."""
 import numpy as np
+import pytest
 
 import oracle as O
 from oracle import adjoint as AD
@@ -44,7 +45,10 @@ def test_long_step_vjp_matches_finite_differences():
         _check(lambda v, name=name: _loss(run(**{name: v}), target), val, args[name], 1.0, 1e-6, 1e-6)
 
 
-def test_blocked_and_marched_vjp_matches_finite_differences():
+@pytest.mark.parametrize("shift", [0, 7])
+def test_blocked_and_marched_vjp_matches_finite_differences(shift):
+    """Across the span change; with and without a window shift (the shifted
+    roll-off's beta derivative and the shifted core positions)."""
     rng = np.random.default_rng(1)
     n, dt, B, H = 1024, 10 / 512, 256, 32
     a0 = wdm_field(Grid(n, dt), 4, 2, "ook", rng)
@@ -54,10 +58,11 @@ def test_blocked_and_marched_vjp_matches_finite_differences():
     z0, z1 = 0.5 - 2 * L, 0.5 + 2 * L            # across the span change
 
     def run(a=a0, dmm=dmm):
-        return O.mpa_propagate(a, dt, dmm, L, 2, 2, z0, z1, B, H)
+        return O.mpa_propagate(a, dt, dmm, L, 2, 2, z0, z1, B, H, shift)
 
     out = run()
-    g_a, g_sigma, g_beta2, g_beta3 = AD.mpa_propagate_vjp(a0, dt, dmm, L, 2, 2, z0, z1, 2 * (out - target), B, H)
+    g_a, g_sigma, g_beta2, g_beta3 = AD.mpa_propagate_vjp(a0, dt, dmm, L, 2, 2, z0, z1, 2 * (out - target), B, H,
+                                                          shift)
     d = rng.normal(size=n) + 1j * rng.normal(size=n)
     _check(lambda a: _loss(run(a=a), target), float(np.real(np.vdot(g_a, d))), a0, d, 1e-6, 1e-6)
     for span in (0, 1):

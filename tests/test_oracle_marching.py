@@ -167,3 +167,79 @@ def test_span_schedule_uses_integer_counters():
     assert spans == ([0] * 5 + [1] * 5) * 2
     with pytest.raises(ValueError):
         O.span_of_long_step(dmm, 0.3, 0)
+
+
+# ---- window shift (windows moved against their cores) ----------------------
+
+def _one_sided():
+    """Three channels (band 45) with beta3 = 2: the group-delay rate
+    20 omega + omega^2 over the band runs from -100 to 2925, mostly one-signed.
+    Halo of 10 time units (pulse width 1), so that the taper's own
+    broadening of the content it touches stays far from the core."""
+    n, dt, B, H = 8192, 10 / 512, 2048, 512
+    a = wdm_field(Grid(n, dt), 32, 3, "ook", np.random.default_rng(4))
+    return n, dt, B, H, a, 45.0, 20.0, 2.0
+
+
+def test_group_delay_range_and_excursion():
+    lo, hi = O.group_delay_range(45.0, 20.0, 2.0)
+    om = np.linspace(-45.0, 45.0, 200001)
+    u = 20.0 * om + om ** 2
+    assert abs(lo - u.min()) < 1e-6 and abs(hi - u.max()) < 1e-6
+    assert O.group_delay_range(145.0, 20.0, 0.0) == (-2900.0, 2900.0)
+    L, dt, s = 3e-4, 0.01, 40
+    assert abs(O.halo_excursion(45.0, 20.0, 2.0, L, s, dt) - np.max(np.abs(u * L - s * dt))) < 1e-9
+
+
+def test_block_partition_with_shift():
+    for n, b, h, s in ((4096, 1024, 128, 37), (1 << 14, 4096, 512, -200), (5000, 512, 64, 32)):
+        owned = np.zeros(n, int)
+        for w0, c0, clen in O.block_partition(n, b, h, s):
+            assert w0 == c0 - h - s and 0 < clen <= b - 2 * h
+            owned[c0:c0 + clen] += 1
+        assert np.all(owned == 1)
+
+
+def test_window_shift_centres_the_domain_of_dependence():
+    """sigma = 0 with a one-sided group delay: a long step whose band
+    excursion is a quarter of the halo only once the window is shifted by the
+    middle of the group-delay range reproduces exact linear propagation;
+    unshifted, or shifted the wrong way, the content reaches the tapered
+    outer halo and the blocked result fails."""
+    n, dt, B, H, a, band, b2, b3 = _one_sided()
+    lo, hi = O.group_delay_range(band, b2, b3)
+    L = 0.25 * H * dt / (0.5 * (hi - lo))
+    s = int(round(0.5 * (lo + hi) * L / dt))
+    assert 0 < s <= H // 2
+    assert O.halo_excursion(band, b2, b3, L, s, dt) <= 0.25 * H * dt * 1.01
+    exact = O.linear_step(a, O.omega_grid(n, dt), b2, b3, 0.0, L)
+    errs = {}
+    for shift in (s, 0, -s):
+        out = O.mpa_blocked_long_step(a, dt, B, H, b2, b3, 0.0, 0.0, L, 2, 1, shift=shift)
+        errs[shift] = O.rel_l2(out, exact)
+    assert errs[s] < 1e-9, errs
+    assert errs[0] > 1e-2 and errs[-s] > 1e-1, errs
+    with pytest.raises(ValueError):
+        O.mpa_blocked_long_step(a, dt, B, H, b2, b3, 0.0, 0.0, L, 2, 1, shift=H // 2 + 1)
+
+
+def test_window_shift_equivariance_and_mask():
+    n, dt, B, H = 8192, 10 / 512, 1024, 128
+    C = B - 2 * H
+    a = wdm_field(Grid(n, dt), 16, 2, "ook", np.random.default_rng(2))
+    kw = dict(shift=23)
+    args = (dt, B, H, 20.0, 0.1, 1.0, 0.05, 2e-3, 4, 2)
+    out = O.mpa_blocked_long_step(a, *args, **kw)
+    out_s = O.mpa_blocked_long_step(np.roll(a, 3 * C), *args, **kw)
+    lo, hi = 3 * C, (n // C) * C
+    assert np.max(np.abs(out_s[lo:hi] - np.roll(out, 3 * C)[lo:hi])) == 0.0
+    # the roll-off passes the band once the shifted excursion obeys the halo rule
+    band, b2, b3 = 45.0, 20.0, 2.0
+    glo, ghi = O.group_delay_range(band, b2, b3)
+    L = 0.25 * H * dt / (0.5 * (ghi - glo))
+    s = int(round(0.5 * (glo + ghi) * L / dt))
+    om = O.omega_grid(B, dt)
+    m = O.block_mask(om, b2, b3, L, H, dt, s)
+    assert np.all(m[np.abs(om) <= band] == 1.0)
+    g = np.abs((b2 * om + 0.5 * b3 * om ** 2) * L - s * dt) / (H * dt)
+    assert np.all(m[g >= 0.5] == 0.0) and np.all(m[(g <= 0.35) & (np.abs(om) * dt / math.pi <= 0.8)] == 1.0)
