@@ -40,18 +40,23 @@
  *     the launches race on that scratch.
  *
  * Time blocking (not part of the paper): with block = B < N the window is
- * cut into blocks of B samples that overlap by `halo` samples per side; each
- * block owns the core [b C, min((b+1) C, N)), C = B - 2 halo, runs the long
- * step on its own periodic window (rolled off by an erf taper over its outer
- * halo/2 samples per side) and writes its core back.  The plan rejects a
- * long step whose group-delay excursion over the signal band,
- * (|beta2| w + |beta3| w^2 / 2) L with w = omega_band, exceeds a quarter of
- * the halo duration halo * dt, since the core would then see the block edges.
- * Stitching overlapping windows is not unitary, so each block's spectrum is
- * also rolled off when it is reconstructed: with g = |beta2 omega +
- * beta3 omega^2 / 2| L / (halo dt), by a raised cosine from 1 at g = 0.35 to
- * 0 at g = 0.5, and from 1 at |omega| = 0.8 pi/dt to 0 at 0.9 pi/dt.  Without
- * it, content at the grid's Nyquist frequency grows every long step.
+ * cut into blocks of B samples; each block owns the core [b C, min((b+1) C,
+ * N)), C = B - 2 halo, runs the long step on its own periodic window of B
+ * samples starting at b C - halo - shift (rolled off by an erf taper over
+ * its outer halo/2 samples per side) and writes its core back.  Content of
+ * frequency omega moves towards later times by u(omega) L over a long step,
+ * u = beta2 omega + beta3 omega^2 / 2 (the group delay; with beta3 != 0 it
+ * is one-signed over much of a wide band), so the window shift (samples,
+ * |shift| <= halo/2) moves each window towards earlier times to keep the
+ * core's domain of dependence centred.  The plan rejects a long step whose
+ * excursion over the signal band, max |u(omega) L - shift dt| over
+ * |omega| <= omega_band, exceeds a quarter of the halo duration halo * dt,
+ * since the core would then see the block edges.  Stitching overlapping
+ * windows is not unitary, so each block's spectrum is also rolled off when
+ * it is reconstructed: with g = |u(omega) L - shift dt| / (halo dt), by a
+ * raised cosine from 1 at g = 0.35 to 0 at g = 0.5, and from 1 at
+ * |omega| = 0.8 pi/dt to 0 at 0.9 pi/dt.  Without it, content at the grid's
+ * Nyquist frequency grows every long step.
  */
 #ifndef MPA_H
 #define MPA_H
@@ -142,7 +147,14 @@ typedef struct {
                               check; 0 means the grid's Nyquist frequency        */
     int32_t schedule;      /* mpa_schedule (single-field plans; batches take
                               MPA_WAVEFRONT)                                    */
+    int32_t shift;         /* window shift in samples (time blocks only; 0 for a
+                              full window), |shift| <= halo/2; MPA_SHIFT_AUTO:
+                              the plan takes round(c L / dt), c the middle of
+                              the range of u(omega) over |omega| <= omega_band
+                              and over all spans, clamped to +-halo/2         */
 } mpa_params;
+
+#define MPA_SHIFT_AUTO INT32_MIN
 
 typedef struct mpa_plan mpa_plan;   /* opaque: device tables and workspace */
 
@@ -153,6 +165,7 @@ typedef struct {
     int64_t table_bytes;       /* device bytes of phase/twiddle/taper tables   */
     int64_t workspace_bytes;   /* device bytes of the ping-pong field buffer, plus
                                   the node-parallel state when scheduled so     */
+    int32_t shift;             /* window shift in use (MPA_SHIFT_AUTO resolved) */
 } mpa_plan_info;
 
 /* Validate parameters, build the FP64 dispersion-phase tables on `device`

@@ -10,10 +10,10 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _lib
-from ._lib import MPA_C64, MPA_C128, MPA_NODE_PARALLEL, MPA_WAVEFRONT, MPAError
+from ._lib import MPA_C64, MPA_C128, MPA_NODE_PARALLEL, MPA_SHIFT_AUTO, MPA_WAVEFRONT, MPAError
 
 __all__ = ["MPAPlan", "MPABatchPlan", "Graph", "SSPlan", "MPA_C64", "MPA_C128", "MPA_WAVEFRONT",
-           "MPA_NODE_PARALLEL", "MPAError", "validate"]
+           "MPA_NODE_PARALLEL", "MPA_SHIFT_AUTO", "MPAError", "validate"]
 
 
 def _stream_handle(torch, device):
@@ -29,9 +29,9 @@ def _check_field(field, precision, n):
 
 
 def validate(n, dt, dmmap, L, M, n_iter, block=0, halo=0, precision=MPA_C64, omega_band=0.0,
-             schedule=MPA_WAVEFRONT):
+             schedule=MPA_WAVEFRONT, shift=0):
     """Host-only check of a plan's parameters; raises MPAError if invalid."""
-    p = _lib.make_params(n, dt, L, M, n_iter, block, halo, precision, omega_band, schedule)
+    p = _lib.make_params(n, dt, L, M, n_iter, block, halo, precision, omega_band, schedule, shift)
     m = _lib.MapStruct(dmmap)
     _lib.check(_lib.lib().mpa_plan_validate(C.byref(p), C.byref(m.s)))
 
@@ -40,12 +40,12 @@ class MPAPlan:
     """mpa_plan_create / mpa_step / mpa_propagate."""
 
     def __init__(self, n, dt, dmmap, L, M, n_iter, block=0, halo=0, precision=MPA_C64,
-                 omega_band=0.0, device=0, schedule=MPA_WAVEFRONT):
+                 omega_band=0.0, device=0, schedule=MPA_WAVEFRONT, shift=0):
         self.n, self.precision, self.device = int(n), int(precision), int(device)
         self.L = float(L)
         self.n_seg = len(dmmap.seg_len)
         self.coefficients = tuple(tuple(float(v) for v in getattr(dmmap, f)) for f in ("sigma", "beta2", "beta3"))
-        p = _lib.make_params(n, dt, L, M, n_iter, block, halo, precision, omega_band, schedule)
+        p = _lib.make_params(n, dt, L, M, n_iter, block, halo, precision, omega_band, schedule, shift)
         m = _lib.MapStruct(dmmap)
         h = C.c_void_p()
         _lib.check(_lib.lib().mpa_plan_create(C.byref(p), C.byref(m.s), int(device), C.byref(h)))
@@ -143,13 +143,13 @@ class MPABatchPlan:
     the instances."""
 
     def __init__(self, ns, dt, dmmap, L, M, n_iter, block, halo, precision=MPA_C64,
-                 omega_band=0.0, sigma_scale=None, device=0):
+                 omega_band=0.0, sigma_scale=None, device=0, shift=0):
         self.ns = [int(v) for v in ns]
         self.n = sum(self.ns)
         self.precision, self.device = int(precision), int(device)
         self.n_seg = len(dmmap.seg_len)
         self.coefficients = tuple(tuple(float(v) for v in getattr(dmmap, f)) for f in ("sigma", "beta2", "beta3"))
-        p = _lib.make_params(max(self.ns), dt, L, M, n_iter, block, halo, precision, omega_band)
+        p = _lib.make_params(max(self.ns), dt, L, M, n_iter, block, halo, precision, omega_band, shift=shift)
         m = _lib.MapStruct(dmmap)
         d = _lib.BatchDesc(self.ns, sigma_scale)
         h = C.c_void_p()

@@ -25,6 +25,8 @@ MPA_C128 = 1
 MPA_WAVEFRONT = 0
 MPA_NODE_PARALLEL = 1
 
+MPA_SHIFT_AUTO = -(1 << 31)
+
 # symbols declared in include/mpa.h
 EXPORTED = ("mpa_plan_create", "mpa_plan_destroy", "mpa_plan_get_info", "mpa_plan_validate",
             "mpa_step", "mpa_propagate", "mpa_batch_plan_validate", "mpa_batch_plan_create",
@@ -45,7 +47,8 @@ class mpa_map(C.Structure):
 class mpa_params(C.Structure):
     _fields_ = [("n", C.c_int64), ("dt", C.c_double), ("L", C.c_double), ("M", C.c_int32),
                 ("n_iter", C.c_int32), ("block", C.c_int32), ("halo", C.c_int32),
-                ("precision", C.c_int32), ("omega_band", C.c_double), ("schedule", C.c_int32)]
+                ("precision", C.c_int32), ("omega_band", C.c_double), ("schedule", C.c_int32),
+                ("shift", C.c_int32)]
 
 
 class mpa_batch_desc(C.Structure):
@@ -55,7 +58,7 @@ class mpa_batch_desc(C.Structure):
 class mpa_plan_info(C.Structure):
     _fields_ = [("n", C.c_int64), ("block", C.c_int32), ("halo", C.c_int32),
                 ("core", C.c_int32), ("n_blocks", C.c_int32), ("threads_per_block", C.c_int32),
-                ("table_bytes", C.c_int64), ("workspace_bytes", C.c_int64)]
+                ("table_bytes", C.c_int64), ("workspace_bytes", C.c_int64), ("shift", C.c_int32)]
 
 
 class MPAError(RuntimeError):
@@ -136,9 +139,9 @@ class MapStruct:
 
 
 def make_params(n, dt, L, M, n_iter, block=0, halo=0, precision=MPA_C64, omega_band=0.0,
-                schedule=MPA_WAVEFRONT):
+                schedule=MPA_WAVEFRONT, shift=0):
     return mpa_params(int(n), float(dt), float(L), int(M), int(n_iter), int(block), int(halo),
-                      int(precision), float(omega_band), int(schedule))
+                      int(precision), float(omega_band), int(schedule), int(shift))
 
 
 class BatchDesc:

@@ -11,8 +11,11 @@ also allows a longer long step and gives more blocks (core B - 2H), at the
 price of computing more samples twice.  For every compiled block size B and
 halo B/8, B/4 or 3B/8 the candidate takes the longest long step L = k dz that divides
 every span and the amplifier spacing and keeps the group delay of the
-signal band within the halo rule; the tuner times a few launches of each on
-the GPU and keeps the cheapest per unit distance.
+signal band within the halo rule, with the windows shifted against their
+cores by the middle of the band's group-delay range over L (with beta3 != 0
+the group delay is one-signed over much of a wide band, and the shift
+centres the core's domain of dependence in its window); the tuner times a
+few launches of each on the GPU and keeps the cheapest per unit distance.
 """
 from __future__ import annotations
 
@@ -32,7 +35,35 @@ class Candidate:
     halo: int
     L: float
     M: int
+    shift: int = 0
     seconds_per_unit_z: Optional[float] = None
+
+
+def group_delay_range(omega_band: float, beta2: float, beta3: float):
+    """(min, max) of beta2 omega + beta3 omega^2 / 2 over |omega| <= omega_band."""
+    w = float(omega_band)
+    vals = [beta2 * w + 0.5 * beta3 * w * w, -beta2 * w + 0.5 * beta3 * w * w]
+    if beta3 != 0 and abs(beta2 / beta3) <= w:
+        vals.append(-0.5 * beta2 * beta2 / beta3)
+    return min(vals), max(vals)
+
+
+def window_shift(dmmap, omega_band: float, L: float, dt: float, halo: int) -> int:
+    """The shift the library takes for MPA_SHIFT_AUTO: round(c L / dt), c the
+    middle of the group-delay range over the band and every span, clamped to
+    +-halo/2."""
+    r = [group_delay_range(omega_band, b2, b3) for b2, b3 in zip(dmmap.beta2, dmmap.beta3)]
+    lo, hi = min(x[0] for x in r), max(x[1] for x in r)
+    c = round(0.5 * (lo + hi) * L / dt)
+    return int(max(-(halo // 2), min(halo // 2, c)))
+
+
+def _fits(dmmap, omega_band: float, L: float, dt: float, halo: int, shift: int) -> bool:
+    for b2, b3 in zip(dmmap.beta2, dmmap.beta3):
+        lo, hi = group_delay_range(omega_band, b2, b3)
+        if max(abs(lo * L - shift * dt), abs(hi * L - shift * dt)) > HALO_RULE * halo * dt:
+            return False
+    return True
 
 
 def _steps(length: float, h: float) -> int:
@@ -43,36 +74,39 @@ def _steps(length: float, h: float) -> int:
 
 
 def candidates(n: int, dt: float, dmmap, dz: float, omega_band: float,
-               blocks=BLOCKS, halo_fractions=HALO_FRACTIONS) -> List[Candidate]:
+               blocks=BLOCKS, halo_fractions=HALO_FRACTIONS, shifted: bool = True) -> List[Candidate]:
     """One candidate per block size B <= n and halo B p/q ((p, q) in halo_fractions):
     the longest long step that is a multiple of dz, divides every span (and
-    the amplifier spacing) and satisfies the halo rule for every span."""
+    the amplifier spacing) and satisfies the halo rule for every span, with
+    the windows shifted by :func:`window_shift` (``shifted``) or not."""
     counts = [_steps(s, dz) for s in dmmap.seg_len]
     if dmmap.z_amp > 0:
         counts.append(_steps(dmmap.z_amp, dz))
     g = 0
     for c in counts:
         g = math.gcd(g, c)
-    rate = max(abs(b2) * omega_band + 0.5 * abs(b3) * omega_band ** 2
-               for b2, b3 in zip(dmmap.beta2, dmmap.beta3))
     out = []
     for B in blocks:
         if B > n:
             continue
         for num, den in halo_fractions:
             H = B * num // den
-            lmax = HALO_RULE * H * dt / rate if rate > 0 else float("inf")
-            best = 0
+            best, best_shift = 0, 0
             for k in range(1, g + 1):
-                if g % k == 0 and k * dz <= lmax * (1 - 1e-12):
-                    best = k
+                if g % k:
+                    continue
+                L = k * dz
+                sh = window_shift(dmmap, omega_band, L, dt, H) if shifted else 0
+                if _fits(dmmap, omega_band, L * (1 + 1e-12), dt, H, sh):
+                    best, best_shift = k, sh
             if best:
-                out.append(Candidate(B, H, best * dz, best))
+                out.append(Candidate(B, H, best * dz, best, best_shift))
     return out
 
 
 def autotune(field, dt: float, dmmap, dz: float, n_iter: int, omega_band: float,
-             precision: int = 0, launches: int = 40, blocks=BLOCKS, halo_fractions=HALO_FRACTIONS):
+             precision: int = 0, launches: int = 40, blocks=BLOCKS, halo_fractions=HALO_FRACTIONS,
+             shifted: bool = True):
     """Time every candidate on `field` (a complex CUDA tensor, left
     unchanged) and return (best Candidate, list of all timed candidates)."""
     import torch
@@ -80,11 +114,11 @@ def autotune(field, dt: float, dmmap, dz: float, n_iter: int, omega_band: float,
     from . import MPAPlan
 
     n = field.numel()
-    cands = candidates(n, dt, dmmap, dz, omega_band, blocks, halo_fractions)
+    cands = candidates(n, dt, dmmap, dz, omega_band, blocks, halo_fractions, shifted)
     if not cands:
         raise ValueError("no block size satisfies the halo rule at this dz")
     for c in cands:
-        plan = MPAPlan(n, dt, dmmap, c.L, c.M, n_iter, c.block, c.halo, precision, omega_band)
+        plan = MPAPlan(n, dt, dmmap, c.L, c.M, n_iter, c.block, c.halo, precision, omega_band, shift=c.shift)
         x = field.clone()
         plan.propagate(x, 0.0, 4 * c.L)                 # warm-up
         torch.cuda.synchronize()
@@ -98,7 +132,7 @@ def autotune(field, dt: float, dmmap, dz: float, n_iter: int, omega_band: float,
 
 
 def choose_n_iter(field, dt, dmmap, L: float, M: int, block: int, halo: int, omega_band: float,
-                  precision: int = 0, tol: float = 1e-5, steps: int = 200, max_iter: int = 5):
+                  precision: int = 0, tol: float = 1e-5, steps: int = 200, max_iter: int = 5, shift: int = 0):
     """Smallest number of Picard sweeps whose result after `steps` long steps
     from `field` (a complex CUDA tensor, left unchanged) is within `tol`
     (relative L2) of the result with `max_iter` sweeps.
@@ -116,7 +150,7 @@ def choose_n_iter(field, dt, dmmap, L: float, M: int, block: int, halo: int, ome
     n = field.numel()
     outs = {}
     for nit in range(1, max_iter + 1):
-        plan = MPAPlan(n, dt, dmmap, L, M, nit, block, halo, precision, omega_band)
+        plan = MPAPlan(n, dt, dmmap, L, M, nit, block, halo, precision, omega_band, shift=shift)
         x = field.clone()
         plan.propagate(x, 0.0, steps * L)
         plan.close()

@@ -82,7 +82,7 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ fin, const cx<double>* __rest
                          cx<T>* __restrict__ node_store, cx<double>* __restrict__ last_store,
                          const int2* __restrict__ items, int n_items, const long long* __restrict__ offset,
                          const long long* __restrict__ len, const double* __restrict__ sigma_scale,
-                         long long n_field, int core, int halo, const cx<T>* __restrict__ phase,
+                         long long n_field, int core, int lead, const cx<T>* __restrict__ phase,
                          const cx<double>* __restrict__ phase_last, const T* __restrict__ node_scale,
                          const cx<T>* __restrict__ tw, const cx<double>* __restrict__ tw64,
                          const double* __restrict__ taper, const cx<double>* __restrict__ mask_grad, int M,
@@ -115,13 +115,14 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ fin, const cx<double>* __rest
 }
 
 #if !defined(MPA_PART_T)
-// g_in[i] = sum over the windows b containing sample i of g_blk[b][i - (b C - H) mod N],
+// g_in[i] = sum over the windows b containing sample i of g_blk[b][i - (b C - lead) mod N]
+// (lead = halo + window shift: the samples of a window before its core),
 // per field of a batch (offset != nullptr: instance by binary search over the
 // offsets, its items from item_base); workgroup 0 also adds the work items'
 // parameter derivatives (in item order; sigma weighted by the instance's
 // scale) to param_grad[q * n_seg + span], q = 0 (sigma), 1 (beta2), 2 (beta3).
 __global__ void adjoint_gather_kernel(const cx<double>* __restrict__ g_blk, cx<double>* __restrict__ g_in,
-                                      long long count, int B, int core, int halo, int n_blocks_field,
+                                      long long count, int B, int core, int lead, int n_blocks_field,
                                       const long long* __restrict__ offset, const long long* __restrict__ len,
                                       const int* __restrict__ item_base, int n_inst,
                                       const int2* __restrict__ items, const double* __restrict__ sigma_scale,
@@ -147,15 +148,15 @@ __global__ void adjoint_gather_kernel(const cx<double>* __restrict__ g_blk, cx<d
         cx<double> acc = {0.0, 0.0};
         for (int k = -1; k <= 1; ++k) {
             const long long ip = li + k * n;          // the sample's position relative to the windows
-            // windows b with b C - H <= ip < b C - H + B
-            long long hi = ip + halo;
-            long long lo = ip + halo - B;
+            // windows b with b C - lead <= ip < b C - lead + B
+            long long hi = ip + lead;
+            long long lo = ip + lead - B;
             hi = hi >= 0 ? hi / core : -((-hi + core - 1) / core);
             lo = (lo >= 0 ? lo / core : -((-lo + core - 1) / core)) + 1;
             if (lo < 0) lo = 0;
             if (hi > n_blocks - 1) hi = n_blocks - 1;
             for (long long b = lo; b <= hi; ++b) {
-                const long long t = ip - (b * core - halo);
+                const long long t = ip - (b * core - lead);
                 acc = acc + g_blk[(first + b) * B + t];
             }
         }
@@ -218,7 +219,7 @@ static hipError_t adjoint_typed(const AdjointStepArgs& a) {
                        static_cast<cx<double>*>(a.last_store), bt ? static_cast<const int2*>(bt->items) : nullptr,
                        n_items, bt ? static_cast<const long long*>(bt->offset) : nullptr,
                        bt ? static_cast<const long long*>(bt->len) : nullptr,
-                       bt ? static_cast<const double*>(bt->sigma_scale) : nullptr, (long long)a.n, a.core, a.halo,
+                       bt ? static_cast<const double*>(bt->sigma_scale) : nullptr, (long long)a.n, a.core, a.lead,
                        static_cast<const cx<T>*>(a.phase), static_cast<const cx<double>*>(a.phase_last),
                        static_cast<const T*>(a.node_scale), static_cast<const cx<T>*>(a.twiddle),
                        static_cast<const cx<double>*>(a.twiddle64), static_cast<const double*>(a.taper),
@@ -299,7 +300,7 @@ hipError_t launch_adjoint_gather(const AdjointGatherArgs& a) {
     const BatchItems* bt = a.batch;
     hipLaunchKernelGGL(adjoint_gather_kernel, dim3(grid), dim3(tpb), 0, a.stream,
                        static_cast<const cx<double>*>(a.g_blk), static_cast<cx<double>*>(a.g_in),
-                       (long long)a.count, a.block, a.core, a.halo, a.n_blocks,
+                       (long long)a.count, a.block, a.core, a.lead, a.n_blocks,
                        bt ? static_cast<const long long*>(bt->offset) : nullptr,
                        bt ? static_cast<const long long*>(bt->len) : nullptr,
                        static_cast<const int*>(a.item_base), a.n_inst,

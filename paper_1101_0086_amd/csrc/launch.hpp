@@ -31,7 +31,9 @@ struct BlockStepArgs {
     const void* in;          // field at z0 (N complex of the plan's precision)
     void* out;               // field at z0 + L (must not alias `in`)
     int64_t n;
-    int32_t block, halo, core, n_blocks;
+    int32_t block;
+    int32_t lead;            // samples of each window before its core: halo + window shift
+    int32_t core, n_blocks;
     const void* phase;       // (M+1) x B unit phasors e^{i beta(omega_k, z_j)} of the span
     const void* phase_last;  // B FP64 phasors of node M of the span (reconstruction)
     const void* node_scale;  // 2 (M+1) reals per span: c_j = e^{Gamma_j}/B, e_j = dz e^{-Gamma_j}
@@ -63,7 +65,9 @@ struct AdjointStepArgs {
     void* node_store;        // workgroups x n_iter x M x 3 x B complex (plan precision)
     void* last_store;        // workgroups x B FP64 complex
     int64_t n;               // samples of the field (single field)
-    int32_t block, halo, core, n_blocks;
+    int32_t block;
+    int32_t lead;            // samples of each window before its core: halo + window shift
+    int32_t core, n_blocks;
     const void* phase;
     const void* phase_last;
     const void* node_scale;
@@ -92,7 +96,9 @@ struct AdjointGatherArgs {
     const void* g_blk;
     void* g_in;
     int64_t count;           // samples (all fields of a batch)
-    int32_t block, core, halo, n_blocks;   // n_blocks: single field
+    int32_t block, core;
+    int32_t lead;            // samples of each window before its core: halo + window shift
+    int32_t n_blocks;        // single field
     const double* partial;
     double* param_grad;
     int32_t n_seg, span;
@@ -141,10 +147,11 @@ hipError_t launch_phase_table_t(void* table, int precision, int n1, int n2, int 
 // turns = c2[r] k'^2 + c3[r] k'^3 (k' the signed harmonic index),
 // table[r][k] = (cos 2 pi frac(turns), sin 2 pi frac(turns)) stored in the
 // plan precision.  `coef` holds c2[0..rows-1] then c3[0..rows-1] (device).
-// With `mask` (device, g1[0..rows-1] then g2[0..rows-1]) each entry is also
-// multiplied by the block roll-off: with g = |g1 k' + g2 k'^2| (group delay
-// over L in units of the halo duration) and q = 2 |k'| / B (|omega| in units
-// of pi/dt), the factor is d((g - 0.35) / 0.15) d((q - 0.8) / 0.1),
+// With `mask` (device, g1[0..rows-1], g2[0..rows-1], then g0[0..rows-1]) each
+// entry is also multiplied by the block roll-off: with g = |g1 k' + g2 k'^2 -
+// g0| (displacement over L relative to the window shift, in units of the halo
+// duration) and q = 2 |k'| / B (|omega| in units of pi/dt), the factor is
+// d((g - 0.35) / 0.15) d((q - 0.8) / 0.1),
 // d(x) = 1 for x <= 0, 0 for x >= 1, (1 + cos pi x) / 2 between.
 hipError_t launch_phase_table(void* table, int precision, int B, int rows,
                               const double* coef, const double* mask, hipStream_t stream);

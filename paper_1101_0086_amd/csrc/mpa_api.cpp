@@ -237,6 +237,7 @@ struct mpa_plan {
     mpa_params prm{};
     int device = 0;
     int block = 0, halo = 0, core = 0, n_blocks = 0;
+    int shift = 0;                      // window shift (samples): windows start at b C - halo - shift
     size_t elem = 8;                    // bytes per complex sample
     std::vector<double> beta2, beta3, sigma;
     double gamma = 0, z_amp = 0, raman_g0 = 0, raman_alpha = 0;
@@ -285,7 +286,21 @@ static void plan_free(mpa_plan* p) {
     delete p;
 }
 
-static int validate_params(const mpa_params* p, const mpa_map* map, Schedule* sched) {
+// Range [lo, hi] of the group-delay rate u = beta2 omega + beta3 omega^2 / 2
+// over |omega| <= w: the values at both band edges and, when the parabola's
+// vertex -beta2 / beta3 lies inside the band, at the vertex.
+static void group_delay_range(double beta2, double beta3, double w, double* lo, double* hi) {
+    double a = beta2 * w + 0.5 * beta3 * w * w, b = -beta2 * w + 0.5 * beta3 * w * w;
+    *lo = std::min(a, b);
+    *hi = std::max(a, b);
+    if (beta3 != 0.0 && std::fabs(beta2 / beta3) <= w) {
+        const double v = -0.5 * beta2 * beta2 / beta3;
+        *lo = std::min(*lo, v);
+        *hi = std::max(*hi, v);
+    }
+}
+
+static int validate_params(const mpa_params* p, const mpa_map* map, Schedule* sched, int* shift_out = nullptr) {
     if (!p) return fail(MPA_EINVAL, "params is NULL");
     int st = validate_map(map);
     if (st) return st;
@@ -301,8 +316,11 @@ static int validate_params(const mpa_params* p, const mpa_map* map, Schedule* sc
     if (p->schedule != MPA_WAVEFRONT && p->schedule != MPA_NODE_PARALLEL)
         return fail(MPA_EINVAL, "schedule = %d is not MPA_WAVEFRONT or MPA_NODE_PARALLEL", p->schedule);
     const bool full = (p->block == 0 || (p->block == p->n && p->halo == 0));
+    int shift = 0;
     if (full) {
         if (p->halo != 0) return fail(MPA_EINVAL, "halo must be 0 for a full-window plan");
+        if (p->shift != 0 && p->shift != MPA_SHIFT_AUTO)
+            return fail(MPA_EINVAL, "shift must be 0 for a full-window plan");
     } else {
         if (!is_pow2(p->block) || p->block > p->n)
             return fail(MPA_EINVAL, "block = %d must be a power of two <= n", p->block);
@@ -316,15 +334,36 @@ static int validate_params(const mpa_params* p, const mpa_map* map, Schedule* sc
     if (!full) {
         const double pi = 3.14159265358979323846;
         const double w = p->omega_band > 0 ? p->omega_band : pi / p->dt;
+        double lo = 0, hi = 0;
         for (int i = 0; i < map->n_seg; ++i) {
-            const double rate = std::fabs(map->beta2[i]) * w + 0.5 * std::fabs(map->beta3[i]) * w * w;
-            if (rate * p->L > 0.25 * p->halo * p->dt)
+            double l, h;
+            group_delay_range(map->beta2[i], map->beta3[i], w, &l, &h);
+            lo = i ? std::min(lo, l) : l;
+            hi = i ? std::max(hi, h) : h;
+        }
+        const int lim = p->halo / 2;
+        if (p->shift == MPA_SHIFT_AUTO) {
+            const double c = std::nearbyint(0.5 * (lo + hi) * p->L / p->dt);
+            shift = (int)std::max(-(double)lim, std::min((double)lim, c));
+        } else {
+            if (p->shift < -lim || p->shift > lim)
+                return fail(MPA_EINVAL, "shift = %d must satisfy |shift| <= halo / 2 = %d", p->shift, lim);
+            shift = p->shift;
+        }
+        // the excursion of every span's band relative to the shift (a step across a span
+        // boundary moves content by a convex combination of the spans' displacements)
+        for (int i = 0; i < map->n_seg; ++i) {
+            double l, h;
+            group_delay_range(map->beta2[i], map->beta3[i], w, &l, &h);
+            const double ex = std::max(std::fabs(l * p->L - shift * p->dt), std::fabs(h * p->L - shift * p->dt));
+            if (ex > 0.25 * p->halo * p->dt)
                 return fail(MPA_EHALO,
-                            "span %d: group-delay excursion %g over L exceeds a quarter of the halo "
-                            "duration %g",
-                            i, rate * p->L, p->halo * p->dt);
+                            "span %d: group-delay excursion %g over L (window shift %d) exceeds a quarter of "
+                            "the halo duration %g",
+                            i, ex, shift, p->halo * p->dt);
         }
     }
+    if (shift_out) *shift_out = shift;
     const int B = full ? (int)p->n : p->block;
     if (full && p->n > 4096) {
         // the four-step full-window path
@@ -351,7 +390,8 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
     if (!out) return fail(MPA_EINVAL, "out is NULL");
     *out = nullptr;
     Schedule sched;
-    int st = validate_params(params, map, &sched);
+    int shift = 0;
+    int st = validate_params(params, map, &sched, &shift);
     if (st) return st;
     st = check_device(device);
     if (st) return st;
@@ -364,6 +404,7 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
     const bool full = (params->block == 0 || (params->block == params->n && params->halo == 0));
     p->block = full ? (int)params->n : params->block;
     p->halo = full ? 0 : params->halo;
+    p->shift = full ? 0 : shift;
     p->core = p->block - 2 * p->halo;
     p->n_blocks = (int)((params->n + p->core - 1) / p->core);
     p->elem = params->precision == MPA_C64 ? 8 : 16;
@@ -456,9 +497,9 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
     }
 
     // the node-M rows again, in FP64, times the block roll-off (blocked plans):
-    // g = |beta2 omega + beta3 omega^2 / 2| L / (H dt) with omega = 2 pi k' / (B dt)
+    // g = |(beta2 omega + beta3 omega^2 / 2) L - shift dt| / (H dt) with omega = 2 pi k' / (B dt)
     // (for a boundary-crossing step, beta2 L and beta3 L are the integrals over the step)
-    std::vector<double> coef_last(2 * (size_t)TT), mask_last(2 * (size_t)TT);
+    std::vector<double> coef_last(2 * (size_t)TT), mask_last(3 * (size_t)TT);
     for (int t = 0; t < TT; ++t) {
         coef_last[t] = coef[(size_t)t * (M + 1) + M];
         coef_last[TT + t] = coef[rows + (size_t)t * (M + 1) + M];
@@ -469,6 +510,7 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
             const double i3 = t < S ? p->beta3[t] * params->L : p->sched.straddles[t - S].b3[M];
             mask_last[t] = i2 * w1 * hdt;
             mask_last[TT + t] = 0.5 * i3 * w1 * w1 * hdt;
+            mask_last[2 * TT + t] = (double)p->shift / p->halo;
         }
     }
     DevBuf dcoef, dlast, dmask;
@@ -572,6 +614,7 @@ int mpa_plan_get_info(const mpa_plan* p, mpa_plan_info* info) {
     info->n = p->prm.n;
     info->block = p->block;
     info->halo = p->halo;
+    info->shift = p->shift;
     info->core = p->core;
     info->n_blocks = p->n_blocks;
     info->threads_per_block = mpa::threads_per_block(p->prm.precision, p->block);
@@ -598,7 +641,7 @@ static int launch_long_step(mpa_plan* p, const void* in, void* out, int64_t m, h
     a.out = out;
     a.n = p->prm.n;
     a.block = p->block;
-    a.halo = p->halo;
+    a.lead = p->halo + p->shift;
     a.core = p->core;
     a.n_blocks = p->n_blocks;
     a.phase = (const char*)p->phase + (size_t)s * (M + 1) * p->block * p->elem;
@@ -771,8 +814,9 @@ static int adjoint_setup(const AdjTarget& t) {
     if (p->halo > 0 && !p->adj_mask) {
         // e^{i beta_M(omega)} times the derivatives of the block roll-off with respect to
         // beta2 and beta3: the roll-off is d((g - 0.35) / 0.15) d((q - 0.8) / 0.1) with
-        // g = |u| L / (halo dt), u = beta2 omega + beta3 omega^2 / 2, q = |omega| dt / pi,
-        // d(x) = (1 + cos pi x) / 2 on (0, 1), so d' = -(pi / 2) sin(pi x) there.
+        // g = |v| / (halo dt), v = (beta2 omega + beta3 omega^2 / 2) L - shift dt, q = |omega| dt / pi,
+        // d(x) = (1 + cos pi x) / 2 on (0, 1), so d' = -(pi / 2) sin(pi x) there;
+        // dg/dbeta2 = sign(v) omega L / (halo dt), dg/dbeta3 = sign(v) omega^2 L / (2 halo dt).
         const double pi = 3.14159265358979323846;
         const double bdt = B * p->prm.dt;
         const double w1 = 2.0 * pi / bdt;
@@ -786,9 +830,10 @@ static int adjoint_setup(const AdjTarget& t) {
             for (int k = 0; k < B; ++k) {
                 const double kp = k < B / 2 ? k : k - B;
                 const double om = w1 * kp;
-                const double u = p->beta2[s] * om + 0.5 * p->beta3[s] * om * om;
-                const double sg = (u > 0) - (u < 0);
-                const double x1 = (std::fabs(u) * hd - 0.35) / 0.15;
+                const double v = (p->beta2[s] * om + 0.5 * p->beta3[s] * om * om) * p->prm.L -
+                                 p->shift * p->prm.dt;
+                const double sg = (v > 0) - (v < 0);
+                const double x1 = (std::fabs(v) / (p->halo * p->prm.dt) - 0.35) / 0.15;
                 const double dm_dg = slope(x1) / 0.15 * drop((2.0 * std::fabs(kp) / B - 0.8) / 0.1);
                 const double dm2 = dm_dg * sg * om * hd, dm3 = dm_dg * sg * 0.5 * om * om * hd;
                 const double turns = c2 * kp * kp + c3 * kp * kp * kp;
@@ -829,7 +874,7 @@ static int adjoint_long_step(const AdjTarget& t, const void* in, const void* g_o
     a.last_store = t.w->last;
     a.n = p->prm.n;
     a.block = p->block;
-    a.halo = p->halo;
+    a.lead = p->halo + p->shift;
     a.core = p->core;
     a.n_blocks = p->n_blocks;
     a.phase = (const char*)p->phase + (size_t)s * (M + 1) * p->block * p->elem;
@@ -857,7 +902,7 @@ static int adjoint_long_step(const AdjTarget& t, const void* in, const void* g_o
     g.count = t.count;
     g.block = p->block;
     g.core = p->core;
-    g.halo = p->halo;
+    g.lead = p->halo + p->shift;
     g.n_blocks = p->n_blocks;
     g.partial = (const double*)t.w->partial;
     g.param_grad = param_grad;

@@ -59,7 +59,7 @@ struct StepTables {
 template <typename T, int B, int NIT>
 __global__ void __launch_bounds__(B / PTS)
 mpa_block_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long long n, int core,
-                 int halo, const cx<T>* __restrict__ phase, const cx<double>* __restrict__ phase_last,
+                 int lead, const cx<T>* __restrict__ phase, const cx<double>* __restrict__ phase_last,
                  const T* __restrict__ node_scale, const cx<T>* __restrict__ tw,
                  const cx<double>* __restrict__ tw64, const double* __restrict__ taper, int M, T sigma,
                  double out_scale) {
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(B / PTS)
 mpa_batch_kernel(const cx<T>* __restrict__ fin, cx<T>* __restrict__ fout,
                  const int2* __restrict__ items, int n_items, const long long* __restrict__ offset,
                  const long long* __restrict__ len, const double* __restrict__ sigma_scale, int core,
-                 int halo, const cx<T>* __restrict__ phase, const cx<double>* __restrict__ phase_last,
+                 int lead, const cx<T>* __restrict__ phase, const cx<double>* __restrict__ phase_last,
                  const T* __restrict__ node_scale, const cx<T>* __restrict__ tw,
                  const cx<double>* __restrict__ tw64, const double* __restrict__ taper, int M,
                  double sigma_span, double out_scale) {
@@ -122,7 +122,7 @@ static hipError_t launch_typed(const BlockStepArgs& a) {
         const StepTables<T> t = tables_of<T>(a);
         hipLaunchKernelGGL((mpa_block_kernel<T, B, NIT>), dim3(a.n_blocks), dim3(B / PTS), 0, a.stream,
                            static_cast<const cx<T>*>(a.in), static_cast<cx<T>*>(a.out), (long long)a.n,
-                           a.core, a.halo, t.phase, t.phase_last, t.node_scale, t.tw, t.tw64, t.taper, a.M,
+                           a.core, a.lead, t.phase, t.phase_last, t.node_scale, t.tw, t.tw64, t.taper, a.M,
                            T(a.sigma), a.out_scale);
     } else {
         const StepTables<T> t = tables_of<T>(a);
@@ -131,7 +131,7 @@ static hipError_t launch_typed(const BlockStepArgs& a) {
                            static_cast<const cx<T>*>(a.in), static_cast<cx<T>*>(a.out),
                            static_cast<const int2*>(b.items), b.n_items, static_cast<const long long*>(b.offset),
                            static_cast<const long long*>(b.len), static_cast<const double*>(b.sigma_scale),
-                           a.core, a.halo, t.phase, t.phase_last, t.node_scale, t.tw, t.tw64, t.taper, a.M,
+                           a.core, a.lead, t.phase, t.phase_last, t.node_scale, t.tw, t.tw64, t.taper, a.M,
                            a.sigma, a.out_scale);
     }
     return hipGetLastError();
@@ -219,8 +219,9 @@ __global__ void phase_table_kernel(cx<T>* __restrict__ out, int B, int rows,
     double s, c;
     sincospi(2.0 * f, &s, &c);
     if (mask) {
-        // block roll-off: group delay over L in halo units, and |omega| in Nyquist units
-        const double g = fabs(fma(mask[rows + r], k2, mask[r] * kp));
+        // block roll-off: displacement over L relative to the window shift in halo
+        // units, and |omega| in Nyquist units
+        const double g = fabs(fma(mask[rows + r], k2, mask[r] * kp) - mask[2 * rows + r]);
         const double nyq = 2.0 * fabs(kp) / B;
         const double m = rc_drop((g - 0.35) / 0.15) * rc_drop((nyq - 0.8) / 0.1);
         s *= m;

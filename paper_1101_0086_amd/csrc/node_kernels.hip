@@ -50,7 +50,7 @@ __device__ __forceinline__ long long wrap(long long g, long long n) {
 template <typename T, int B>
 __global__ void __launch_bounds__(B / PTS)
 np_init_kernel(const cx<T>* __restrict__ in, cx<double>* __restrict__ psi0_buf, cx<T>* __restrict__ h0_buf,
-               long long n, int core, int halo, const T* __restrict__ node_scale, const cx<T>* __restrict__ tw,
+               long long n, int core, int lead, const T* __restrict__ node_scale, const cx<T>* __restrict__ tw,
                const cx<double>* __restrict__ tw64, const double* __restrict__ taper, T sigma) {
     constexpr int R = PTS;
     constexpr int NT = B / R;
@@ -58,7 +58,7 @@ np_init_kernel(const cx<T>* __restrict__ in, cx<double>* __restrict__ psi0_buf, 
     cx<T>* ldsT = reinterpret_cast<cx<T>*>(lds64);
     const int tid = threadIdx.x;
     const long long c0 = (long long)blockIdx.x * core;
-    const long long w0 = c0 - halo;
+    const long long w0 = c0 - lead;
     cx<double> psi0[R];
     cx<T> cur[R];
 #pragma unroll
@@ -135,7 +135,7 @@ np_node_kernel(const cx<double>* __restrict__ psi0_buf, const cx<T>* __restrict_
 template <typename T, int B>
 __global__ void __launch_bounds__(B / PTS)
 np_final_kernel(const cx<double>* __restrict__ psi0_buf, const cx<T>* __restrict__ h0_buf,
-                const cx<T>* __restrict__ u_last, cx<T>* __restrict__ out, long long n, int core, int halo,
+                const cx<T>* __restrict__ u_last, cx<T>* __restrict__ out, long long n, int core, int lead,
                 const cx<double>* __restrict__ phase_last, const cx<double>* __restrict__ tw64, int M,
                 double out_scale) {
     constexpr int R = PTS;
@@ -163,7 +163,7 @@ np_final_kernel(const cx<double>* __restrict__ psi0_buf, const cx<T>* __restrict
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const int t = tid + NT * m;
-        if (t >= halo && t < halo + clen) out[c0 + (t - halo)] = narrow<T>(v[m]);
+        if (t >= lead && t < lead + clen) out[c0 + (t - lead)] = narrow<T>(v[m]);
     }
 }
 
@@ -179,14 +179,14 @@ static hipError_t node_step_typed(const BlockStepArgs& a) {
     const auto* tw = static_cast<const cx<T>*>(a.twiddle);
     const auto* tw64 = static_cast<const cx<double>*>(a.twiddle64);
     hipLaunchKernelGGL((np_init_kernel<T, B>), dim3(a.n_blocks), threads, 0, a.stream, static_cast<const cx<T>*>(a.in),
-                       psi0, h0, (long long)a.n, a.core, a.halo, ns, tw, tw64, static_cast<const double*>(a.taper),
+                       psi0, h0, (long long)a.n, a.core, a.lead, ns, tw, tw64, static_cast<const double*>(a.taper),
                        T(a.sigma));
     const unsigned node_groups = (unsigned)(XCDS * a.M * ((a.n_blocks + XCDS - 1) / XCDS));
     for (int s = 0; s < a.n_iter; ++s)
         hipLaunchKernelGGL((np_node_kernel<T, B>), dim3(node_groups), threads, 0, a.stream, psi0, h0, u[(s + 1) & 1],
                            u[s & 1], a.n_blocks, phase, ns, tw, a.M, T(a.sigma), s == 0 ? 1 : 0);
     hipLaunchKernelGGL((np_final_kernel<T, B>), dim3(a.n_blocks), threads, 0, a.stream, psi0, h0,
-                       u[(a.n_iter - 1) & 1], static_cast<cx<T>*>(a.out), (long long)a.n, a.core, a.halo,
+                       u[(a.n_iter - 1) & 1], static_cast<cx<T>*>(a.out), (long long)a.n, a.core, a.lead,
                        static_cast<const cx<double>*>(a.phase_last), tw64, a.M, a.out_scale);
     return hipGetLastError();
 }

@@ -34,6 +34,15 @@ def rel_l2(a, b) -> float:
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def centred_shift(band, dmmap, L, dt, halo):
+    """Window shift at the middle of the band's group-delay range over L and
+    over the map's spans (the oracle's range), clamped to +-halo/2."""
+    import oracle as O
+    r = [O.group_delay_range(band, b2, b3) for b2, b3 in zip(dmmap.beta2, dmmap.beta3)]
+    c = round(0.5 * (min(x[0] for x in r) + max(x[1] for x in r)) * L / dt)
+    return int(max(-(halo // 2), min(halo // 2, c)))
+
+
 def say(*args):
     """Name the case before a GPU step (flushed, so a fault still shows it)."""
     print("[gpu-case]", *args, file=sys.stderr, flush=True)

@@ -87,6 +87,27 @@ def test_validation_status_codes():
     assert _validate(schedule=2) == L.MPA_EINVAL
 
 
+def test_window_shift_validation():
+    """The bench field (band 145, beta3 = 0.1, group delay -1849..3951 per
+    unit z in both spans): a long step twice the unshifted halo rule's limit
+    passes once the window is shifted by the middle of that range (about
+    1051 L / dt samples), within |shift| <= halo / 2; full windows take no
+    shift; the automatic shift is accepted."""
+    L = _lib()
+    w = WORKLOADS["wdm8_n262144_f32"]
+    dt = w.grid.dt
+    Lb = 4e-4                                       # unshifted 3951 Lb = 1.58 > 0.25 H dt = 1.25
+    sh = int(round(1051.25 * Lb / dt))              # shifted: max |u Lb - sh dt| = 1.16
+    assert _validate(L=Lb) == L.MPA_EHALO
+    assert _validate(L=Lb, shift=sh) == L.MPA_OK
+    assert _validate(L=Lb, shift=-sh) == L.MPA_EHALO
+    assert _validate(L=Lb, shift=L.MPA_SHIFT_AUTO) == L.MPA_OK
+    assert _validate(shift=w.mpa.halo // 2 + 1) == L.MPA_EINVAL
+    assert _validate(shift=-(w.mpa.halo // 2) - 1) == L.MPA_EINVAL
+    assert _validate(n=4096, block=0, halo=0, L=0.05, shift=3) == L.MPA_EINVAL
+    assert _validate(n=4096, block=0, halo=0, L=0.05, shift=L.MPA_SHIFT_AUTO) == L.MPA_OK
+
+
 def test_error_message_and_status_strings():
     L = _lib()
     assert _validate(L=1e-3) == L.MPA_EHALO

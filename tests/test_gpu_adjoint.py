@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from tests.gpu_util import rel_l2, say, to_dev, to_host
+from tests.gpu_util import centred_shift, rel_l2, say, to_dev, to_host
 from workloads import WORKLOADS, Grid, dm_map, wdm_field
 
 pytestmark = pytest.mark.gpu
@@ -55,9 +55,9 @@ def _target(a, dt, rng, scale, noise, band=None):
     return scale * a + nz
 
 
-def _plan(grid, dmmap, L, M, nit, block, halo, prec, band=0.0):
+def _plan(grid, dmmap, L, M, nit, block, halo, prec, band=0.0, shift=0):
     import paper_1101_0086_amd as P
-    return P.MPAPlan(grid.n, grid.dt, dmmap, L, M, nit, block, halo, prec, band)
+    return P.MPAPlan(grid.n, grid.dt, dmmap, L, M, nit, block, halo, prec, band, shift=shift)
 
 
 def _gpu_grad(plan, a, g_out, z0, z1, prec, store_steps=0):
@@ -78,10 +78,10 @@ def _compare(prec, got_g, got_p, ref_g, ref_p, broadband=False):
     assert ep < tol_p, ("parameter derivatives", ep, got_p, ref_p)
 
 
-def _oracle(a, dt, dmmap, L, M, nit, z0, z1, target, block=0, halo=0):
-    out = O.mpa_propagate(a, dt, dmmap, L, M, nit, z0, z1, block, halo)
+def _oracle(a, dt, dmmap, L, M, nit, z0, z1, target, block=0, halo=0, shift=0):
+    out = O.mpa_propagate(a, dt, dmmap, L, M, nit, z0, z1, block, halo, shift)
     g_out = 2 * (out - target)
-    g, gs, g2, g3 = O.mpa_propagate_vjp(a, dt, dmmap, L, M, nit, z0, z1, g_out, block, halo)
+    g, gs, g2, g3 = O.mpa_propagate_vjp(a, dt, dmmap, L, M, nit, z0, z1, g_out, block, halo, shift)
     return out, g_out, g, np.stack([gs, g2, g3])
 
 
@@ -128,6 +128,25 @@ def test_blocked_across_span_and_amplifier(block, prec, inband):
         plan = _plan(grid, dmmap, L, M, nit, block, halo, prec, band)
         _, got_g, got_p = _gpu_grad(plan, a, g_out, z0, z1, prec)
         _compare(prec, got_g, got_p, ref_g, ref_p, broadband=not inband)
+        plan.close()
+
+
+@pytest.mark.parametrize("block,prec", [(512, 1), (4096, 1), (4096, 0)])
+def test_shifted_windows(block, prec):
+    """Windows shifted against their cores (the shifted roll-off's beta
+    derivatives, shifted gather of the window gradients) across the span
+    change and an amplifier."""
+    grid, a, band, halo, L = _blocked(block)
+    dmmap = dm_map(beta3=0.1)
+    sh = centred_shift(band, dmmap, L, grid.dt, halo)
+    rng = np.random.default_rng(17)
+    target = _target(a, grid.dt, rng, 0.9, 0.02, band)
+    for z0, z1 in ((0.5 - 2 * L, 0.5 + 2 * L), (1.0 - 2 * L, 1.0 + L)):
+        _, g_out, ref_g, ref_p = _oracle(a, grid.dt, dmmap, L, 2, 2, z0, z1, target, block, halo, sh)
+        say("adjoint shifted", block, prec, sh, z0, z1)
+        plan = _plan(grid, dmmap, L, 2, 2, block, halo, prec, band, sh)
+        _, got_g, got_p = _gpu_grad(plan, a, g_out, z0, z1, prec)
+        _compare(prec, got_g, got_p, ref_g, ref_p)
         plan.close()
 
 
@@ -184,17 +203,18 @@ def test_c5_full_size_two_long_steps_against_oracle(prec, inband):
 
 
 # Central differences over one map period: (field step, sigma step, beta2
-# step, beta3 step, tolerance) per precision.  FP64: steps that move the
-# dispersion phase of the signal band (|omega| <= 65) by ~1e-4 rad over a
-# span (linear regime), differences to 1e-6 (field) and 1e-5 (parameters).
-# FP32: the loss of the FP32 forward carries rounding noise of ~1e-7 of its
-# value (measured: differences with a 1e-3 field step were 9e-4 off, i.e. the
-# two losses differed by 7e-8 of the loss beyond the linear change), so the
-# steps are ~100 times larger: a field step of 2e-2 (the loss moves by ~1e-3
-# of itself, noise ~4e-5 of the derivative, truncation of the central
-# difference ~(2e-2)^2 times the nonlinear phase of ~0.05 rad, 2e-5) and
-# parameter steps that move the band's phase by ~1e-2 rad, within 2e-4.
-FD = {1: (1e-5, 1e-4, 1e-7, 4e-9, 1e-6, 1e-5), 0: (2e-2, 1e-2, 1e-5, 4e-7, 2e-4, 2e-4)}
+# step, beta3 step, tolerance, relative noise of the loss) per precision.
+# FP64: steps that move the dispersion phase of the signal band
+# (|omega| <= 65) by ~1e-4 rad over a span (linear regime), differences to
+# 1e-6 (field) and 1e-5 (parameters).  FP32: the loss of the FP32 forward
+# carries rounding noise (measured: ~7e-8 of the loss, from the field
+# differences with a 1e-3 step, 9e-4 off), so the steps are ~100 times
+# larger (a 2e-2 field step moves the loss by ~1e-3 of itself; parameter
+# steps move the band's phase by ~1e-2 rad) and each difference is allowed
+# 1e-4 plus three times its own noise, 1e-7 loss / (2 h |difference|): the
+# sigma derivative (~7 against a loss of ~300) resolves to ~6e-4 at h = 1e-2,
+# the field and beta derivatives to ~1e-5.
+FD = {1: (1e-5, 1e-4, 1e-7, 4e-9, 1e-6, 1e-5, 0.0), 0: (2e-2, 1e-2, 1e-5, 4e-7, 1e-4, 1e-4, 1e-7)}
 
 
 @pytest.mark.parametrize("prec", [1, 0])
@@ -210,7 +230,7 @@ def test_c5_full_period_finite_differences(prec):
     rng = np.random.default_rng(14)
     target = a * 0.7
     z0, z1 = 0.0, 1.0
-    eps, h_sig, h_b2, h_b3, tol_g, tol_p = FD[prec]
+    eps, h_sig, h_b2, h_b3, tol_g, tol_p, noise = FD[prec]
 
     def loss(dmmap, field):
         plan = _plan(w.grid, dmmap, s.L, s.M, s.n_iter, s.block, s.halo, prec, s.omega_band)
@@ -231,10 +251,11 @@ def test_c5_full_period_finite_differences(prec):
     d = rng.normal(size=a.size) + 1j * rng.normal(size=a.size)
     d *= np.linalg.norm(a) / np.linalg.norm(d)
     say("adjoint c5 period: field differences", prec)
+    l0 = loss(w.dmmap, a)
     fd = (loss(w.dmmap, a + eps * d) - loss(w.dmmap, a - eps * d)) / (2 * eps)
     ad = float(np.real(np.vdot(g, d)))
     say("field", fd, ad, abs(fd - ad) / abs(fd))
-    bad = [] if abs(fd - ad) <= tol_g * abs(fd) else [("field", fd, ad)]
+    bad = [] if abs(fd - ad) <= tol_g * abs(fd) + 3 * noise * l0 / (2 * eps) else [("field", fd, ad)]
     for q, field, h in ((0, "sigma", h_sig), (1, "beta2", h_b2), (2, "beta3", h_b3)):
         for span in (0, 1):
             vals = list(getattr(w.dmmap, field))
@@ -245,7 +266,7 @@ def test_c5_full_period_finite_differences(prec):
             fd = (loss(w.dmmap.__class__(**{**w.dmmap.__dict__, field: tuple(plus)}), a)
                   - loss(w.dmmap.__class__(**{**w.dmmap.__dict__, field: tuple(minus)}), a)) / (2 * h)
             say(field, span, fd, pg[q, span], abs(fd - pg[q, span]) / abs(fd))
-            if abs(fd - pg[q, span]) > tol_p * abs(fd):
+            if abs(fd - pg[q, span]) > tol_p * abs(fd) + 3 * noise * l0 / (2 * h):
                 bad.append((field, span, fd, pg[q, span]))
     assert not bad, bad
 

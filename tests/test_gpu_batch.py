@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from tests.gpu_util import TOL_F64, rel_l2, say, to_dev, to_host
+from tests.gpu_util import centred_shift, TOL_F64, rel_l2, say, to_dev, to_host
 from workloads import Grid, dm_map
 from workloads.wdm import _fast_wdm_field
 
@@ -51,6 +51,27 @@ def test_batch_equals_single_runs_bitwise():
     bp.close()
     for a, n, sc, g in zip(fields, ns, scales, got):
         p = P.MPAPlan(n, DT, dmm.with_sigma(sc), L, 2, 2, block, halo, P.MPA_C64, BAND)
+        y = to_dev(a, 0)
+        p.propagate(y, 0.5 - 2 * L, 0.5 + 3 * L)
+        assert np.array_equal(to_host(y), g)
+        p.close()
+
+
+def test_batch_with_shifted_windows_equals_single_runs():
+    import paper_1101_0086_amd as P
+    ns = [8192, 4096, 16384]
+    scales = [1.0, 0.7, 1.6]
+    fields, block, halo, L = _case(ns, seed=31)
+    dmm = dm_map(beta3=0.1)
+    sh = centred_shift(BAND, dmm, L, DT, halo)
+    say("batch shifted", ns, sh)
+    bp = P.MPABatchPlan(ns, DT, dmm, L, 2, 2, block, halo, P.MPA_C64, BAND, sigma_scale=scales, shift=sh)
+    x = to_dev(np.concatenate(fields), 0)
+    bp.propagate(x, 0.5 - 2 * L, 0.5 + 3 * L)
+    got = [to_host(v) for v in bp.split(x)]
+    bp.close()
+    for a, n, sc, g in zip(fields, ns, scales, got):
+        p = P.MPAPlan(n, DT, dmm.with_sigma(sc), L, 2, 2, block, halo, P.MPA_C64, BAND, shift=sh)
         y = to_dev(a, 0)
         p.propagate(y, 0.5 - 2 * L, 0.5 + 3 * L)
         assert np.array_equal(to_host(y), g)

@@ -21,14 +21,14 @@ pytestmark = pytest.mark.gpu
 TOL = {0: TOL_F32, 1: TOL_F64}
 
 
-def _plan(w_or_grid, dmmap, L, M, nit, block, halo, prec, omega_band=0.0):
+def _plan(w_or_grid, dmmap, L, M, nit, block, halo, prec, omega_band=0.0, shift=0):
     import paper_1101_0086_amd as P
     g = w_or_grid
-    return P.MPAPlan(g.n, g.dt, dmmap, L, M, nit, block, halo, prec, omega_band)
+    return P.MPAPlan(g.n, g.dt, dmmap, L, M, nit, block, halo, prec, omega_band, shift=shift)
 
 
-def _run_mpa(a, grid, dmmap, L, M, nit, block, halo, prec, z0, z1, omega_band=0.0):
-    plan = _plan(grid, dmmap, L, M, nit, block, halo, prec, omega_band)
+def _run_mpa(a, grid, dmmap, L, M, nit, block, halo, prec, z0, z1, omega_band=0.0, shift=0):
+    plan = _plan(grid, dmmap, L, M, nit, block, halo, prec, omega_band, shift)
     x = to_dev(a, prec)
     plan.propagate(x, z0, z1)
     out = to_host(x)
@@ -90,6 +90,50 @@ def test_blocked_across_span_and_amplifier(block, prec):
         assert rel_l2(got, ref) < TOL[prec]
 
 
+def _shifted_case(block, n=1 << 15, bits=32, ch=8, seed=3):
+    """As _blocked_case, with the window shifted by the middle of the band's
+    group-delay range over L (beta2 = +20 and -19.8, beta3 = 0.1), which
+    admits the longest L dividing the spans within the halo rule."""
+    dt = 10.0 / 1024
+    grid = Grid(n, dt)
+    a = wdm_field(grid, bits, ch, "ook", np.random.default_rng(seed))
+    band = 0.5 * (ch - 1) * 40 + 5
+    halo = block // 8
+    ranges = [O.group_delay_range(band, b2, 0.1) for b2 in (20.0, -19.8)]
+    lo, hi = min(r[0] for r in ranges), max(r[1] for r in ranges)
+    k = 1
+    while True:
+        L = 0.5 / k
+        sh = int(round(0.5 * (lo + hi) * L / dt))
+        if abs(sh) <= halo // 2 and all(O.halo_excursion(band, b2, 0.1, L, sh, dt) <= 0.25 * halo * dt
+                                        for b2 in (20.0, -19.8)):
+            return grid, a, band, halo, L, sh
+        k += 1
+
+
+@pytest.mark.parametrize("block", [1024, 4096])
+@pytest.mark.parametrize("prec", [1, 0])
+def test_window_shift_across_span_and_amplifier(block, prec):
+    """Windows moved against their cores: the shifted partition, the shifted
+    roll-off and a long step longer than the unshifted halo rule admits,
+    across the span change and an amplifier; the plan's automatic choice of
+    the shift equals the middle of the group-delay range over both spans."""
+    import paper_1101_0086_amd as P
+    grid, a, band, halo, L, sh = _shifted_case(block)
+    assert sh != 0
+    dmm = dm_map(beta3=0.1)
+    with pytest.raises(P.MPAError):       # unshifted, the same long step breaks the halo rule
+        P.validate(grid.n, grid.dt, dmm, L, 2, 2, block, halo, prec, band)
+    plan = _plan(grid, dmm, L, 2, 2, block, halo, prec, band, P.MPA_SHIFT_AUTO)
+    assert plan.info()["shift"] == sh
+    plan.close()
+    for z0 in (0.5 - 2 * L, 1.0 - 2 * L):
+        say("shifted", block, prec, z0, sh)
+        got = _run_mpa(a, grid, dmm, L, 2, 2, block, halo, prec, z0, z0 + 4 * L, band, sh)
+        ref = O.mpa_propagate(a, grid.dt, dmm, L, 2, 2, z0, z0 + 4 * L, block, halo, sh)
+        assert rel_l2(got, ref) < TOL[prec]
+
+
 @pytest.mark.parametrize("nit", [1, 3, 4, 5])
 @pytest.mark.parametrize("M", [1, 3])
 def test_sweeps_and_nodes(nit, M):
@@ -139,6 +183,9 @@ def test_resume_step_and_determinism():
     ("wdm8_n262144_f32", dict(block=2048, halo=512, L=3.125e-4, M=5)),
     ("wdm8_n262144_f32", dict(block=4096, halo=1536, L=6.25e-4, M=10)),
     ("wdm32_n4194304_f32", dict(block=4096, halo=1024, L=1.5625e-5, M=2)),
+    # shifted windows at the same dz
+    ("wdm32_n4194304_f32", dict(block=4096, halo=512, L=1.5625e-5, M=2, shift=96)),
+    ("wdm32_n4194304_f32", dict(block=2048, halo=256, L=7.8125e-6, M=1, shift=48)),
 ])
 def test_full_size_sampled_blocks(name, over):
     """The benchmark's 2^18-mode 8-channel workload and the 2^22-mode
@@ -155,18 +202,19 @@ def test_full_size_sampled_blocks(name, over):
     a = w.field()
     say("full size sampled blocks", name, w.grid.n)
     got = _run_mpa(a, w.grid, w.dmmap, s.L, s.M, s.n_iter, s.block, s.halo, 0, 0.0, s.L,
-                   s.omega_band)
-    parts = O.block_partition(w.grid.n, s.block, s.halo)
+                   s.omega_band, s.shift)
+    parts = O.block_partition(w.grid.n, s.block, s.halo, s.shift)
     omega_b = O.omega_grid(s.block, w.grid.dt)
     taper = O.block_taper(s.block, s.halo)
     b2, b3 = w.dmmap.beta2[0], w.dmmap.beta3[0]
-    mask = O.block_mask(omega_b, b2, b3, s.L, s.halo, w.grid.dt)
+    mask = O.block_mask(omega_b, b2, b3, s.L, s.halo, w.grid.dt, s.shift)
+    lead = s.halo + s.shift
     for b in (0, len(parts) // 2, len(parts) - 1):
         w0, c0, clen = parts[b]
         idx = (w0 + np.arange(s.block)) % w.grid.n
         res = O.mpa_long_step(a[idx] * taper, omega_b, b2, b3, w.dmmap.sigma[0], w.dmmap.gamma,
                               s.L, s.M, s.n_iter, out_mask=mask)
-        ref = res[s.halo:s.halo + clen]
+        ref = res[lead:lead + clen]
         assert rel_l2(got[c0:c0 + clen], ref) < TOL_F32, b
 
 

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from tests.gpu_util import TOL_F32, TOL_F64, rel_l2, say, to_dev, to_host
+from tests.gpu_util import centred_shift, TOL_F32, TOL_F64, rel_l2, say, to_dev, to_host
 from workloads import WORKLOADS, Grid, dm_map, wdm_field
 
 pytestmark = pytest.mark.gpu
@@ -27,9 +27,9 @@ def _same(wf, npl, prec):
         assert np.abs(wf - npl).max() <= 1e-14 * np.abs(wf).max()
 
 
-def _run(a, grid, dmmap, L, M, nit, block, halo, prec, z0, z1, band, schedule):
+def _run(a, grid, dmmap, L, M, nit, block, halo, prec, z0, z1, band, schedule, shift=0):
     import paper_1101_0086_amd as P
-    plan = P.MPAPlan(grid.n, grid.dt, dmmap, L, M, nit, block, halo, prec, band, schedule=schedule)
+    plan = P.MPAPlan(grid.n, grid.dt, dmmap, L, M, nit, block, halo, prec, band, schedule=schedule, shift=shift)
     x = to_dev(a, prec)
     plan.propagate(x, z0, z1)
     out = to_host(x)
@@ -62,6 +62,23 @@ def test_bitwise_equal_to_wavefront_and_close_to_oracle(block, M, nit, prec):
     npl = _run(a, grid, dmmap, L, M, nit, block, halo, prec, z0, z1, band, P.MPA_NODE_PARALLEL)
     _same(wf, npl, prec)
     ref = O.mpa_propagate(a, grid.dt, dmmap, L, M, nit, z0, z1, block, halo)
+    assert rel_l2(npl, ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_shifted_windows(prec):
+    """Windows shifted against their cores: the node-parallel schedule's
+    gather and scatter follow the same shift."""
+    import paper_1101_0086_amd as P
+    grid, a, band, halo, L = _blocked(2048)
+    dmmap = dm_map(beta3=0.1)
+    sh = centred_shift(band, dmmap, L, grid.dt, halo)   # middle of the band's group delay over L
+    z0, z1 = 0.5 - 2 * L, 0.5 + 2 * L
+    say("node-parallel shifted", prec, sh)
+    wf = _run(a, grid, dmmap, L, 2, 2, 2048, halo, prec, z0, z1, band, P.MPA_WAVEFRONT, sh)
+    npl = _run(a, grid, dmmap, L, 2, 2, 2048, halo, prec, z0, z1, band, P.MPA_NODE_PARALLEL, sh)
+    _same(wf, npl, prec)
+    ref = O.mpa_propagate(a, grid.dt, dmmap, L, 2, 2, z0, z1, 2048, halo, sh)
     assert rel_l2(npl, ref) < TOL[prec]
 
 

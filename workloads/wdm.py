@@ -83,13 +83,15 @@ class Grid:
 class MPASettings:
     """Long step L, M quadrature intervals per long step, n_iter Picard sweeps,
     time blocks of ``block`` points with ``halo`` points of overlap per side
-    (``block = 0`` means one block covering the whole window)."""
+    (``block = 0`` means one block covering the whole window), windows moved
+    ``shift`` samples against their cores."""
     L: float
     M: int
     n_iter: int
     block: int = 0
     halo: int = 0
     omega_band: float = 0.0   # highest |omega| carrying signal (halo rule); 0 = grid edge
+    shift: int = 0
 
 
 def _periodic_offsets(t: np.ndarray, centre: float, window: float) -> np.ndarray:
