@@ -136,7 +136,7 @@ def test_autotuner_picks_a_valid_plan():
     best, cands = autotune(x, DT, dmm, 1.25e-4, 2, BAND, launches=8)
     assert best in cands and all(c.seconds_per_unit_z > 0 for c in cands)
     assert np.array_equal(to_host(x), to_host(to_dev(a, 0)))        # input left unchanged
-    plan = P.MPAPlan(n, DT, dmm, best.L, best.M, 2, best.block, best.halo, P.MPA_C64, BAND)
+    plan = P.MPAPlan(n, DT, dmm, best.L, best.M, 2, best.block, best.halo, P.MPA_C64, BAND, shift=best.shift)
     plan.propagate(x, 0.0, 2 * best.L)
     plan.close()
 
