@@ -195,6 +195,32 @@ int mpa_step(mpa_plan* plan, void* field, double z0, void* stream);
  * the state carried between long steps is the field alone.                  */
 int mpa_propagate(mpa_plan* plan, void* field, double z0, double z1, void* stream);
 
+/* ---- allocation-free march ------------------------------------------------
+ *
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the march
+ * of mpa_propagate without a plan, in place on `field`, on the calling
+ * thread's current device.  It allocates nothing: the phase tables, node
+ * scalars, twiddles, taper and the march's second field are built by kernels
+ * on `stream` in a per-device static array of MPA_NOALLOC_SCRATCH_BYTES (held
+ * by the library until the process ends; its device address is resolved once
+ * per device, on the first call there).  All calls on one device share that
+ * array: calls that overlap in time on one device (two streams, two host
+ * threads) race on it and must be ordered by the caller.  Every call
+ * rewrites the parts it reads before reading them.
+ * Accepts what mpa_plan_create accepts, except: schedule MPA_WAVEFRONT only,
+ * a full window of at most 4096 modes, no distributed gain, no long steps
+ * across span boundaries, at most MPA_NOALLOC_MAX_SEG spans
+ * (MPA_EUNSUPPORTED); the field plus the tables, n (complex) + n_seg
+ * (M + 1) B (complex) + n_seg B (FP64 complex) + about 5 B values, must fit
+ * the array (MPA_EINVAL otherwise; 2^22 FP32 modes with 4096-blocks fit).
+ * Results equal those of mpa_propagate on a plan of the same parameters up
+ * to the last bits of the table rounding.                                  */
+#define MPA_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+#define MPA_NOALLOC_MAX_SEG 8
+int mpa_propagate_noalloc(const mpa_params* params, const mpa_map* map, void* field, double z0, double z1,
+                          void* stream);
+
 /* ---- gradients (reverse pass) --------------------------------------------
  *
  * Gradients of a real loss l through mpa_propagate, obtained by running the

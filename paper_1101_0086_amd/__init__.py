@@ -13,7 +13,7 @@ from . import _lib
 from ._lib import MPA_C64, MPA_C128, MPA_NODE_PARALLEL, MPA_SHIFT_AUTO, MPA_WAVEFRONT, MPAError
 
 __all__ = ["MPAPlan", "MPABatchPlan", "Graph", "SSPlan", "MPA_C64", "MPA_C128", "MPA_WAVEFRONT",
-           "MPA_NODE_PARALLEL", "MPA_SHIFT_AUTO", "MPAError", "validate"]
+           "MPA_NODE_PARALLEL", "MPA_SHIFT_AUTO", "MPAError", "validate", "propagate_noalloc"]
 
 
 def _stream_handle(torch, device):
@@ -34,6 +34,23 @@ def validate(n, dt, dmmap, L, M, n_iter, block=0, halo=0, precision=MPA_C64, ome
     p = _lib.make_params(n, dt, L, M, n_iter, block, halo, precision, omega_band, schedule, shift)
     m = _lib.MapStruct(dmmap)
     _lib.check(_lib.lib().mpa_plan_validate(C.byref(p), C.byref(m.s)))
+
+
+def propagate_noalloc(field, dt, dmmap, L, M, n_iter, z0, z1, block=0, halo=0, precision=MPA_C64,
+                      omega_band=0.0, shift=0):
+    """mpa_propagate_noalloc: the march without a plan and without device
+    allocation, in place on `field` (its length is N), on the field's device
+    and torch's current stream."""
+    import torch
+    if not field.is_cuda:
+        raise ValueError("field must be a CUDA tensor")
+    _check_field(field, precision, field.numel())
+    p = _lib.make_params(field.numel(), dt, L, M, n_iter, block, halo, precision, omega_band, shift=shift)
+    m = _lib.MapStruct(dmmap)
+    with torch.cuda.device(field.device):
+        _lib.check(_lib.lib().mpa_propagate_noalloc(C.byref(p), C.byref(m.s), C.c_void_p(field.data_ptr()),
+                                                    float(z0), float(z1), _stream_handle(torch, field.device)))
+    return field
 
 
 class MPAPlan:

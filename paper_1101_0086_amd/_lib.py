@@ -34,7 +34,8 @@ EXPORTED = ("mpa_plan_create", "mpa_plan_destroy", "mpa_plan_get_info", "mpa_pla
             "mpa_graph_capture", "mpa_batch_graph_capture", "mpa_graph_launch", "mpa_graph_destroy",
             "ss_plan_create", "ss_plan_destroy", "ss_propagate", "mpa_status_string", "mpa_last_error",
             "mpa_checkpoint_count", "mpa_propagate_checkpointed", "mpa_adjoint",
-            "mpa_batch_checkpoint_count", "mpa_batch_propagate_checkpointed", "mpa_batch_adjoint")
+            "mpa_batch_checkpoint_count", "mpa_batch_propagate_checkpointed", "mpa_batch_adjoint",
+            "mpa_propagate_noalloc")
 
 
 class mpa_map(C.Structure):
@@ -90,6 +91,7 @@ def lib() -> C.CDLL:
     h.mpa_plan_validate.argtypes = [C.POINTER(mpa_params), C.POINTER(mpa_map)]
     h.mpa_step.argtypes = [vp, vp, dp, vp]
     h.mpa_propagate.argtypes = [vp, vp, dp, dp, vp]
+    h.mpa_propagate_noalloc.argtypes = [C.POINTER(mpa_params), C.POINTER(mpa_map), vp, dp, dp, vp]
     h.mpa_batch_plan_validate.argtypes = [C.POINTER(mpa_params), C.POINTER(mpa_map), C.POINTER(mpa_batch_desc)]
     h.mpa_batch_plan_create.argtypes = [C.POINTER(mpa_params), C.POINTER(mpa_map), C.POINTER(mpa_batch_desc),
                                         C.c_int, C.POINTER(vp)]

@@ -156,4 +156,28 @@ hipError_t launch_phase_table_t(void* table, int precision, int n1, int n2, int 
 hipError_t launch_phase_table(void* table, int precision, int B, int rows,
                               const double* coef, const double* mask, hipStream_t stream);
 
+// ---- allocation-free entry point ----------------------------------------------
+
+// Bytes of the per-device scratch array of mpa_propagate_noalloc.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr int NOALLOC_MAX_SEG = 8;
+
+// Device address of this device's scratch array (resolved once per device
+// with that device current); hipSuccess or the runtime's error.
+hipError_t noalloc_scratch(int device, void** ptr);
+
+// Tables of a plan without distributed gain or boundary-crossing steps,
+// computed on the device from the parameters (the same definitions as plan
+// creation): node scalars (one row, node precision), twiddles (node
+// precision and FP64), taper, and the phase-table coefficients for
+// launch_phase_table (coef: S (M+1) rows, coef_last: S rows, mask: 3 S,
+// written only when halo > 0).
+struct StepTableParams {
+    int32_t B, M, S, halo, shift, precision;
+    double dt, L, gamma;
+    double beta2[NOALLOC_MAX_SEG], beta3[NOALLOC_MAX_SEG];
+};
+hipError_t launch_step_tables(const StepTableParams& p, void* node_scale, void* twiddle, void* twiddle64,
+                              double* taper, double* coef, double* coef_last, double* mask, hipStream_t stream);
+
 }  // namespace mpa

@@ -1342,6 +1342,135 @@ int mpa_graph_destroy(mpa_graph* g) {
     return MPA_OK;
 }
 
+// ---- allocation-free march -----------------------------------------------------
+
+// Layout of the scratch array: the march's second field, then the tables of
+// every span (as a plan holds them), each part 256-byte aligned.
+namespace {
+struct NoallocLayout {
+    size_t work, phase, last, ns, tw, tw64, taper, coef, coef_last, mask, total;
+};
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+static NoallocLayout noalloc_layout(int64_t n, int B, int M, int S, size_t elem) {
+    NoallocLayout l;
+    const size_t rsz = elem / 2;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    l.work = take((size_t)n * elem);
+    l.phase = take((size_t)S * (M + 1) * B * elem);
+    l.last = take((size_t)S * B * 16);
+    l.ns = take(2 * (size_t)(M + 1) * rsz);
+    l.tw = take((size_t)B * elem);
+    l.tw64 = take((size_t)B * 16);
+    l.taper = take((size_t)B * 8);
+    l.coef = take(2 * (size_t)S * (M + 1) * 8);
+    l.coef_last = take(2 * (size_t)S * 8);
+    l.mask = take(3 * (size_t)S * 8);
+    l.total = o;
+    return l;
+}
+}  // namespace
+
+int mpa_propagate_noalloc(const mpa_params* params, const mpa_map* map, void* field, double z0, double z1,
+                          void* stream) {
+    if (!field) return fail(MPA_EINVAL, "field is NULL");
+    Schedule sched;
+    int shift = 0;
+    int st = validate_params(params, map, &sched, &shift);
+    if (st) return st;
+    const bool full = (params->block == 0 || (params->block == params->n && params->halo == 0));
+    if (params->schedule != MPA_WAVEFRONT || (full && params->n > 4096))
+        return fail(MPA_EUNSUPPORTED, "the allocation-free march runs the fused kernel only (blocks, or one "
+                                      "window of at most 4096 modes)");
+    if (map->raman_g0 > 0 || !sched.straddles.empty())
+        return fail(MPA_EUNSUPPORTED, "the allocation-free march takes neither distributed gain nor long steps "
+                                      "across span boundaries");
+    if (map->n_seg > mpa::NOALLOC_MAX_SEG)
+        return fail(MPA_EUNSUPPORTED, "the allocation-free march takes at most %d spans", mpa::NOALLOC_MAX_SEG);
+    const int B = full ? (int)params->n : params->block;
+    const int halo = full ? 0 : params->halo;
+    const int M = params->M, S = map->n_seg;
+    const size_t elem = params->precision == MPA_C64 ? 8 : 16;
+    const NoallocLayout lay = noalloc_layout(params->n, B, M, S, elem);
+    if (lay.total > mpa::NOALLOC_SCRATCH_BYTES)
+        return fail(MPA_EINVAL, "field and tables need %zu bytes, more than the %zu-byte scratch", lay.total,
+                    mpa::NOALLOC_SCRATCH_BYTES);
+    const int64_t m0 = grid_index(z0, params->L), m1 = grid_index(z1, params->L);
+    if (m0 == INT64_MIN || m1 == INT64_MIN)
+        return fail(MPA_EALIGN, "z0 = %g or z1 = %g is not a multiple of L = %g", z0, z1, params->L);
+    if (m1 < m0) return fail(MPA_EINVAL, "z1 < z0");
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return fail(MPA_EDEVICE, "no current HIP device");
+    void* base = nullptr;
+    if (mpa::noalloc_scratch(device, &base) != hipSuccess)
+        return fail(MPA_EDEVICE, "the scratch array of device %d is not available", device);
+    if (m1 == m0) return MPA_OK;
+    hipStream_t hs = (hipStream_t)stream;
+    char* b = static_cast<char*>(base);
+    // tables, on the caller's stream (kernels only: the call can be captured)
+    mpa::StepTableParams tp{};
+    tp.B = B;
+    tp.M = M;
+    tp.S = S;
+    tp.halo = halo;
+    tp.shift = full ? 0 : shift;
+    tp.precision = params->precision;
+    tp.dt = params->dt;
+    tp.L = params->L;
+    tp.gamma = map->gamma;
+    for (int i = 0; i < S; ++i) {
+        tp.beta2[i] = map->beta2[i];
+        tp.beta3[i] = map->beta3[i];
+    }
+    if (mpa::launch_step_tables(tp, b + lay.ns, b + lay.tw, b + lay.tw64, (double*)(b + lay.taper),
+                                (double*)(b + lay.coef), (double*)(b + lay.coef_last), (double*)(b + lay.mask),
+                                hs) != hipSuccess ||
+        mpa::launch_phase_table(b + lay.phase, params->precision, B, S * (M + 1), (const double*)(b + lay.coef),
+                                nullptr, hs) != hipSuccess ||
+        mpa::launch_phase_table(b + lay.last, MPA_C128, B, S, (const double*)(b + lay.coef_last),
+                                halo > 0 ? (const double*)(b + lay.mask) : nullptr, hs) != hipSuccess)
+        return fail(MPA_EDEVICE, "table launch failed");
+    const double lumped = std::exp(map->gamma * map->z_amp);
+    const double out_scale = std::exp(-map->gamma * params->L) / B;
+    void* src = field;
+    void* dst = b + lay.work;
+    for (int64_t m = m0; m < m1; ++m) {
+        const int sp = sched.span_of(m);
+        mpa::BlockStepArgs a;
+        a.in = src;
+        a.out = dst;
+        a.n = params->n;
+        a.block = B;
+        a.lead = halo + (full ? 0 : shift);
+        a.core = B - 2 * halo;
+        a.n_blocks = (int)((params->n + a.core - 1) / a.core);
+        a.phase = b + lay.phase + (size_t)sp * (M + 1) * B * elem;
+        a.phase_last = b + lay.last + (size_t)sp * B * 16;
+        a.node_scale = b + lay.ns;
+        a.twiddle = b + lay.tw;
+        a.twiddle64 = b + lay.tw64;
+        a.taper = b + lay.taper;
+        a.M = M;
+        a.n_iter = params->n_iter;
+        a.sigma = map->sigma[sp];
+        a.out_scale = out_scale * (sched.amp_after(m) ? lumped : 1.0);
+        a.precision = params->precision;
+        a.batch = nullptr;
+        a.nodes = nullptr;
+        a.stream = hs;
+        const hipError_t e = mpa::launch_block_step(a);
+        if (e != hipSuccess) return fail(MPA_EDEVICE, "block step launch failed: %s", hipGetErrorString(e));
+        std::swap(src, dst);
+    }
+    if (src != field && mpa::launch_copy_field(src, field, params->n, params->precision, hs) != hipSuccess)
+        return fail(MPA_EDEVICE, "copy back failed");
+    return MPA_OK;
+}
+
 const char* mpa_status_string(int status) {
     switch (status) {
         case MPA_OK: return "MPA_OK";

@@ -29,6 +29,8 @@
 // both more accurate and cheaper than compensated FP32 sums.  Phases
 // e^{i beta} are built in FP64 (argument reduced in turns) and rounded to T
 // for the node evaluations.
+#include <algorithm>
+
 #include "block_fft.hpp"
 #include "launch.hpp"
 
@@ -241,6 +243,73 @@ hipError_t launch_phase_table(void* table, int precision, int B, int rows, const
     else
         hipLaunchKernelGGL(phase_table_kernel<double>, dim3(grid), dim3(tpb), 0, stream,
                            static_cast<cx<double>*>(table), B, rows, coef, mask);
+    return hipGetLastError();
+}
+
+// ---- tables of the allocation-free entry point --------------------------------
+
+__global__ void step_tables_kernel(StepTableParams p, void* __restrict__ node_scale, void* __restrict__ tw,
+                                   cx<double>* __restrict__ tw64, double* __restrict__ taper,
+                                   double* __restrict__ coef, double* __restrict__ coef_last,
+                                   double* __restrict__ mask) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const double pi = 3.14159265358979323846;
+    const int B = p.B, M = p.M, S = p.S;
+    const double dz = p.L / M;
+    const double bdt = (double)B * p.dt;
+    const bool f32 = p.precision == 0;
+    if (idx < B) {
+        // twiddle exp(+2 pi i k / B) and the erf taper over the outer halo/2 samples
+        double s, c;
+        sincospi(2.0 * idx / B, &s, &c);
+        tw64[idx] = cx<double>{c, s};
+        if (f32) static_cast<cx<float>*>(tw)[idx] = cx<float>{float(c), float(s)};
+        else static_cast<cx<double>*>(tw)[idx] = cx<double>{c, s};
+        const int W = p.halo / 2;
+        double t = 1.0;
+        const int e = idx < W ? idx : (idx >= B - W ? B - 1 - idx : -1);
+        if (e >= 0) t = 0.5 * (1.0 + erf(8.0 * ((e + 0.5) / W - 0.5)));
+        taper[idx] = t;
+    }
+    const int rows = S * (M + 1);
+    if (idx < rows) {
+        // beta / (2 pi) = c2 k'^2 + c3 k'^3 at node j of span s
+        const int s = idx / (M + 1), j = idx - s * (M + 1);
+        coef[idx] = pi * (p.beta2[s] * (j * dz)) / (bdt * bdt);
+        coef[rows + idx] = (2.0 * pi * pi / 3.0) * (p.beta3[s] * (j * dz)) / (bdt * bdt * bdt);
+    }
+    if (idx <= M) {
+        // c_j = e^{Gamma_j} / B, e_j = dz e^{-Gamma_j}, Gamma_j = -gamma j dz
+        const double g = -p.gamma * idx * dz;
+        const double c = exp(g) / B, e = dz * exp(-g);
+        if (f32) {
+            static_cast<float*>(node_scale)[2 * idx] = float(c);
+            static_cast<float*>(node_scale)[2 * idx + 1] = float(e);
+        } else {
+            static_cast<double*>(node_scale)[2 * idx] = c;
+            static_cast<double*>(node_scale)[2 * idx + 1] = e;
+        }
+    }
+    if (idx < S) {
+        coef_last[idx] = pi * (p.beta2[idx] * (M * dz)) / (bdt * bdt);
+        coef_last[S + idx] = (2.0 * pi * pi / 3.0) * (p.beta3[idx] * (M * dz)) / (bdt * bdt * bdt);
+        if (p.halo > 0) {
+            // block roll-off coefficients: g = |g1 k' + g2 k'^2 - g0|
+            const double w1 = 2.0 * pi / bdt, hdt = 1.0 / (p.halo * p.dt);
+            mask[idx] = p.beta2[idx] * p.L * w1 * hdt;
+            mask[S + idx] = 0.5 * (p.beta3[idx] * p.L) * w1 * w1 * hdt;
+            mask[2 * S + idx] = (double)p.shift / p.halo;
+        }
+    }
+}
+
+hipError_t launch_step_tables(const StepTableParams& p, void* node_scale, void* twiddle, void* twiddle64,
+                              double* taper, double* coef, double* coef_last, double* mask, hipStream_t stream) {
+    if (p.S < 1 || p.S > NOALLOC_MAX_SEG || p.B < 1 || p.M < 1) return hipErrorInvalidValue;
+    const int count = std::max(std::max(p.B, p.S * (p.M + 1)), p.M + 1);
+    const int tpb = 256;
+    hipLaunchKernelGGL(step_tables_kernel, dim3((count + tpb - 1) / tpb), dim3(tpb), 0, stream, p, node_scale,
+                       twiddle, static_cast<cx<double>*>(twiddle64), taper, coef, coef_last, mask);
     return hipGetLastError();
 }
 
