@@ -332,6 +332,15 @@ int mpa_graph_destroy(mpa_graph* graph);
 /* Split-step comparator plan (Eq. 4): step dz must divide every span and
  * z_amp.  Half steps of adjacent split-steps are merged into one spectral
  * multiply; the nonlinear sub-step multiplies by exp(i sigma |A|^2 dz).
+ * Precision: the field is stored as float2 (MPA_C64) or double2 (MPA_C128)
+ * between the passes over it; the arithmetic, twiddles, phase tables and
+ * scales are FP64 for both, so an MPA_C64 run differs from an MPA_C128 run
+ * only by the rounding of the stored field (random from step to step, so it
+ * grows like the square root of the number of steps).  N <= 4096: one
+ * workgroup runs a whole span in registers; 8192 <= N <= 2^22: two passes
+ * over the field per step (four-step transforms, N = N1 N2 with
+ * N1 = min(2^floor(log2 N / 2), 1024)).  The plan also holds the phase tables
+ * (2 n_seg N FP64 complex).
  * With distributed gain (raman_g0 > 0) G depends on z: each linear half
  * step is scaled by exp(int G) over its own interval (N >= 8192: adjacent
  * half steps merged as without it; N <= 4096: one symmetric step per

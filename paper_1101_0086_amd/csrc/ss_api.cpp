@@ -31,8 +31,8 @@ struct ss_plan {
     std::vector<double> sigma;
     std::vector<int64_t> span_steps;
     int64_t period = 0, amp = 0;
-    void* tables = nullptr;    // per span: half-step then full-step phasors (N each)
-    void* twiddle = nullptr;   // small path: N phasors
+    void* tables = nullptr;    // per span: half-step then full-step phasors (N each, FP64)
+    void* twiddle = nullptr;   // small path: N phasors (FP64; every table is FP64 for both precisions)
     bool large = false;        // four-step path
     int n1 = 0, n2 = 0, split = 0;
     void* tw1 = nullptr;       // large path twiddles
@@ -131,7 +131,7 @@ int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz, int32_t 
     const int S = map->n_seg;
     const int rows = 2 * S;
     p->large = !mpa::ss_small_supported(precision, n);
-    const size_t tbytes = (size_t)rows * n * p->elem;
+    const size_t tbytes = (size_t)rows * n * 16;
     const double pi = 3.14159265358979323846;
     const double ndt = (double)n * dt;
     std::vector<double> coef(2 * (size_t)rows);
@@ -153,11 +153,7 @@ int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz, int32_t 
     };
     auto upload = [&](void** dst, const std::vector<double>& v) {
         const size_t cnt = v.size();
-        if (hipMalloc(dst, cnt * (precision == MPA_C64 ? 4 : 8)) != hipSuccess) return false;
-        if (precision == MPA_C64) {
-            std::vector<float> f(v.begin(), v.end());
-            return hipMemcpy(*dst, f.data(), cnt * 4, hipMemcpyHostToDevice) == hipSuccess;
-        }
+        if (hipMalloc(dst, cnt * 8) != hipSuccess) return false;
         return hipMemcpy(*dst, v.data(), cnt * 8, hipMemcpyHostToDevice) == hipSuccess;
     };
     bool ok = hipMalloc(&p->tables, tbytes) == hipSuccess;
@@ -169,14 +165,15 @@ int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz, int32_t 
     ok = hipMalloc(&dcoef, coef.size() * 8) == hipSuccess &&
          hipMemcpy(dcoef, coef.data(), coef.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
     if (!p->large) {
-        if (ok) ok = mpa::launch_phase_table(p->tables, precision, (int)n, rows, (const double*)dcoef, nullptr, 0) == hipSuccess;
+        if (ok) ok = mpa::launch_phase_table(p->tables, MPA_C128, (int)n, rows, (const double*)dcoef, nullptr, 0) ==
+                     hipSuccess;
         if (ok) ok = upload(&p->twiddle, phasors(n, 1.0, (double)n));
     } else {
         mpa::ss_large_shape(n, &p->n1, &p->n2);
         int lg = 0;
         while ((int64_t(1) << lg) < n) ++lg;
         p->split = lg / 2;
-        if (ok) ok = mpa::launch_phase_table_t(p->tables, precision, p->n1, p->n2, rows, (const double*)dcoef, 0) ==
+        if (ok) ok = mpa::launch_phase_table_t(p->tables, MPA_C128, p->n1, p->n2, rows, (const double*)dcoef, 0) ==
                      hipSuccess;
         if (ok) ok = upload(&p->tw1, phasors(p->n1, 1.0, p->n1)) && upload(&p->tw2, phasors(p->n2, 1.0, p->n2)) &&
                      upload(&p->twl, phasors(int64_t(1) << p->split, 1.0, (double)n)) &&
@@ -213,8 +210,8 @@ static double gain_integral(const ss_plan* p, double zeta, double h) {
 static bool run_steps_gain(ss_plan* p, void* field, int s, int64_t j, int64_t run, bool amp_end, hipStream_t stream) {
     const double ln = 1.0 / (double)p->n;
     const double h = 0.5 * p->dz;
-    const void* half_ph = (const char*)p->tables + (size_t)(2 * s) * p->n * p->elem;
-    const void* full_ph = (const char*)p->tables + (size_t)(2 * s + 1) * p->n * p->elem;
+    const void* half_ph = (const char*)p->tables + (size_t)(2 * s) * p->n * 16;
+    const void* full_ph = (const char*)p->tables + (size_t)(2 * s + 1) * p->n * 16;
     if (p->large) {
         int64_t r0 = j % p->amp;
         if (r0 < 0) r0 += p->amp;
@@ -286,8 +283,8 @@ int ss_propagate(ss_plan* p, void* field, double z0, double z1, void* stream) {
         const double gain = amp_end ? p->lumped : 1.0;
         const double hs = std::exp(-0.5 * p->gamma * p->dz) * ln;
         const double fs = std::exp(-p->gamma * p->dz) * ln;
-        const void* half_ph = (const char*)p->tables + (size_t)(2 * s) * p->n * p->elem;
-        const void* full_ph = (const char*)p->tables + (size_t)(2 * s + 1) * p->n * p->elem;
+        const void* half_ph = (const char*)p->tables + (size_t)(2 * s) * p->n * 16;
+        const void* full_ph = (const char*)p->tables + (size_t)(2 * s + 1) * p->n * 16;
         if (p->large) {
             if (!run_large(p, field, half_ph, full_ph, run, p->sigma[s] * p->dz, hs, fs, hs * gain,
                            (hipStream_t)stream))

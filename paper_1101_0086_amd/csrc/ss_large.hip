@@ -9,6 +9,20 @@
 // row kernel (row FFT, spectral phase of the linear sub-step, row inverse
 // FFT) followed by a column kernel (column inverse FFT, exact nonlinear kick
 // A exp(i sigma |A|^2 dz), column FFT): two passes over the field in HBM.
+//
+// The field is stored in ST (float or double) between the passes; the
+// arithmetic, the twiddles (including the N-point twiddle w_N^{n2 k1},
+// formed in FP64 from two sqrt(N)-point tables), the phase tables and the
+// scales are FP64 for both storage types.  Rounding a constant to FP32 would
+// bias every step alike, so that the error would grow linearly with the
+// number of steps; rounding the evolving field when it is stored does not.
+//
+// Shape: N1 = min(2^floor(log2(N)/2), 1024) rows of the column transform,
+// N2 = N / N1 <= 4096 points per row.  A column workgroup takes TC adjacent
+// columns (TC N1 <= 8192 points, so that each row segment it reads is
+// 64-128 contiguous bytes), and the column groups are dealt to the eight XCDs
+// in contiguous runs (workgroup b runs on XCD b mod 8), so that the groups
+// sharing a cache line of a row share that XCD's L2.
 #include "block_fft.hpp"
 #include "ss.hpp"
 
@@ -16,85 +30,99 @@ namespace mpa {
 
 constexpr int SL_PTS = 8;
 
-template <typename T>
-__device__ __forceinline__ cx<T> big_twiddle(const cx<T>* __restrict__ twl,
-                                             const cx<T>* __restrict__ twh, int split, int j) {
+__device__ __forceinline__ cx<double> big_twiddle(const cx<double>* __restrict__ twl,
+                                                  const cx<double>* __restrict__ twh, int split, int j) {
     return cmul(twh[j >> split], twl[j & ((1 << split) - 1)]);
 }
 
-template <typename T>
-__device__ __forceinline__ cx<T> kick_sl(cx<T> a, T sdz) {
-    const T phi = sdz * norm2(a);
-    T s, c;
-    if constexpr (sizeof(T) == 4) {
-        sincosf(phi, &s, &c);
+// A exp(i phi), phi = sigma dz |A|^2.  For |phi| <= 1/64 (every step of a
+// weakly nonlinear link) sin and cos are their Taylor polynomials through
+// phi^7 and phi^8 (truncation below 2e-22 relative); larger phi takes the
+// library's sincos.
+__device__ __forceinline__ cx<double> kick_sl(cx<double> a, double sdz) {
+    const double phi = sdz * norm2(a);
+    double s, c;
+    if (fabs(phi) <= 0.015625) {
+        const double p2 = phi * phi;
+        s = phi * (1.0 - p2 / 6.0 * (1.0 - p2 / 20.0 * (1.0 - p2 / 42.0)));
+        c = 1.0 - p2 / 2.0 * (1.0 - p2 / 12.0 * (1.0 - p2 / 30.0 * (1.0 - p2 / 56.0)));
     } else {
         sincos(phi, &s, &c);
     }
-    return cmul(a, cx<T>{c, s});
+    return cmul(a, cx<double>{c, s});
 }
 
+template <typename ST>
+__device__ __forceinline__ cx<double> load_w(const cx<ST>& x) { return {double(x.re), double(x.im)}; }
+
+template <typename ST>
+__device__ __forceinline__ cx<ST> store_n(cx<double> x) { return {ST(x.re), ST(x.im)}; }
+
 // TR rows of N2 points per workgroup; thread layout tid = r NT2 + t.
-template <typename T, int N2, int TR>
+template <typename ST, int N2, int TR>
 __global__ void __launch_bounds__(TR * N2 / SL_PTS)
-ss_rows_kernel(cx<T>* __restrict__ y, int n1, const cx<T>* __restrict__ tw2,
-               const cx<T>* __restrict__ twl, const cx<T>* __restrict__ twh, int split,
-               const cx<T>* __restrict__ phase, T scl) {
+ss_rows_kernel(cx<ST>* __restrict__ y, int n1, const cx<double>* __restrict__ tw2,
+               const cx<double>* __restrict__ twl, const cx<double>* __restrict__ twh, int split,
+               const cx<double>* __restrict__ phase, double scl) {
     constexpr int R = SL_PTS, NT = N2 / R;
-    __shared__ cx<T> lds[TR * lds_elems<N2>()];
+    __shared__ cx<double> lds[TR * lds_elems<N2>()];
     const int r = threadIdx.x / NT, t = threadIdx.x - r * NT;
     const int k1 = blockIdx.x * TR + r;
-    cx<T>* row = y + (size_t)k1 * N2;
-    const cx<T>* prow = phase + (size_t)k1 * N2;
-    cx<T> v[R];
+    cx<ST>* row = y + (size_t)k1 * N2;
+    const cx<double>* prow = phase + (size_t)k1 * N2;
+    cx<double> v[R];
 #pragma unroll
-    for (int m = 0; m < R; ++m) v[m] = row[t + NT * m];
-    block_fft<T, N2, R, +1>(v, lds + r * lds_elems<N2>(), tw2, t);
+    for (int m = 0; m < R; ++m) v[m] = load_w(row[t + NT * m]);
+    block_fft<double, N2, R, +1>(v, lds + r * lds_elems<N2>(), tw2, t);
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = scale(cmul(v[m], prow[t + NT * m]), scl);
-    block_fft<T, N2, R, -1>(v, lds + r * lds_elems<N2>(), tw2, t);
+    block_fft<double, N2, R, -1>(v, lds + r * lds_elems<N2>(), tw2, t);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const int n2 = t + NT * m;
-        row[n2] = cmulc(v[m], big_twiddle(twl, twh, split, n2 * k1));
+        row[n2] = store_n<ST>(cmulc(v[m], big_twiddle(twl, twh, split, n2 * k1)));
     }
 }
 
 // TC columns of N1 points per workgroup; thread layout tid = t TC + c so that
 // consecutive lanes read consecutive columns of one row.
-template <typename T, int N1, int TC, int MODE>
+template <typename ST, int N1, int TC, int MODE>
 __global__ void __launch_bounds__(TC * N1 / SL_PTS)
-ss_cols_kernel(cx<T>* __restrict__ y, int n2, const cx<T>* __restrict__ tw1,
-               const cx<T>* __restrict__ twl, const cx<T>* __restrict__ twh, int split, T sdz) {
+ss_cols_kernel(cx<ST>* __restrict__ y, int n2, const cx<double>* __restrict__ tw1,
+               const cx<double>* __restrict__ twl, const cx<double>* __restrict__ twh, int split, double sdz) {
     constexpr int R = SL_PTS, NT = N1 / R;
-    __shared__ cx<T> lds[TC * lds_elems<N1>()];
+    __shared__ cx<double> lds[TC * lds_elems<N1>()];
+    // column group of this workgroup: contiguous runs of groups per XCD
+    const int groups = gridDim.x, b = blockIdx.x;
+    const int grp = (groups % 8 == 0) ? (b % 8) * (groups / 8) + b / 8 : b;
     const int c = threadIdx.x % TC, t = threadIdx.x / TC;
-    const int col = blockIdx.x * TC + c;
-    cx<T>* my = lds + c * lds_elems<N1>();
-    cx<T> v[R];
+    const int col = grp * TC + c;
+    cx<double>* my = lds + c * lds_elems<N1>();
+    cx<double> v[R];
 #pragma unroll
-    for (int m = 0; m < R; ++m) v[m] = y[(size_t)(t + NT * m) * n2 + col];
+    for (int m = 0; m < R; ++m) v[m] = load_w(y[(size_t)(t + NT * m) * n2 + col]);
     if constexpr (MODE != SS_COL_FIRST) {
-        block_fft<T, N1, R, -1>(v, my, tw1, t);      // x[N2 n1 + n2], n1 = t + NT m
+        block_fft<double, N1, R, -1, true>(v, my, tw1, t);      // x[N2 n1 + n2], n1 = t + NT m
     }
     if constexpr (MODE == SS_COL_MID) {
 #pragma unroll
         for (int m = 0; m < R; ++m) v[m] = kick_sl(v[m], sdz);
     }
     if constexpr (MODE != SS_COL_LAST) {
-        block_fft<T, N1, R, +1>(v, my, tw1, t);      // Y[k1][n2], k1 = t + NT m
+        block_fft<double, N1, R, +1, true>(v, my, tw1, t);      // Y[k1][n2], k1 = t + NT m
 #pragma unroll
         for (int m = 0; m < R; ++m) v[m] = cmul(v[m], big_twiddle(twl, twh, split, col * (t + NT * m)));
     }
 #pragma unroll
-    for (int m = 0; m < R; ++m) y[(size_t)(t + NT * m) * n2 + col] = v[m];
+    for (int m = 0; m < R; ++m) y[(size_t)(t + NT * m) * n2 + col] = store_n<ST>(v[m]);
 }
 
 void ss_large_shape(int64_t n, int* n1, int* n2) {
     int lg = 0;
     while ((int64_t(1) << lg) < n) ++lg;
-    *n1 = 1 << (lg / 2);
-    *n2 = (int)(n >> (lg / 2));
+    const int l1 = lg / 2 < 10 ? lg / 2 : 10;
+    *n1 = 1 << l1;
+    *n2 = (int)(n >> l1);
 }
 
 bool ss_large_supported(int precision, int64_t n) {
@@ -104,26 +132,24 @@ bool ss_large_supported(int precision, int64_t n) {
 template <typename T, int N2>
 static hipError_t rows_t(const SSLargeArgs& a) {
     // at least one wave per workgroup; one row per workgroup from N2 = 512 up
-    // (a sweep at 2^18 modes: 4.7 us per pass with one row, 6.5 with four)
     constexpr int TR = (512 / N2) > 1 ? (512 / N2) : 1;
     if (a.n1 % TR) return hipErrorInvalidValue;
     hipLaunchKernelGGL((ss_rows_kernel<T, N2, TR>), dim3(a.n1 / TR), dim3(TR * N2 / SL_PTS), 0, a.stream,
-                       static_cast<cx<T>*>(a.field), a.n1, static_cast<const cx<T>*>(a.tw2),
-                       static_cast<const cx<T>*>(a.twl), static_cast<const cx<T>*>(a.twh), a.split,
-                       static_cast<const cx<T>*>(a.phase), T(a.scale));
+                       static_cast<cx<T>*>(a.field), a.n1, static_cast<const cx<double>*>(a.tw2),
+                       static_cast<const cx<double>*>(a.twl), static_cast<const cx<double>*>(a.twh), a.split,
+                       static_cast<const cx<double>*>(a.phase), a.scale);
     return hipGetLastError();
 }
 
 template <typename T, int N1, int MODE>
 static hipError_t cols_tm(const SSLargeArgs& a) {
-    // 2048 points per workgroup: at 2^18 modes four columns (11.4 us per pass)
-    // beat sixteen (31.4 us, only 32 workgroups) and one or two (14.1, 12.2 us)
-    constexpr int TC = (2048 / N1) > 16 ? 16 : ((2048 / N1) < 1 ? 1 : (2048 / N1));
+    // TC adjacent columns, TC N1 <= 8192 points (FP64 exchange buffer <= 147 KB)
+    constexpr int TC = (8192 / N1) > 16 ? 16 : ((8192 / N1) < 1 ? 1 : (8192 / N1));
     if (a.n2 % TC) return hipErrorInvalidValue;
     hipLaunchKernelGGL((ss_cols_kernel<T, N1, TC, MODE>), dim3(a.n2 / TC), dim3(TC * N1 / SL_PTS), 0,
-                       a.stream, static_cast<cx<T>*>(a.field), a.n2, static_cast<const cx<T>*>(a.tw1),
-                       static_cast<const cx<T>*>(a.twl), static_cast<const cx<T>*>(a.twh), a.split,
-                       T(a.sigma_dz));
+                       a.stream, static_cast<cx<T>*>(a.field), a.n2, static_cast<const cx<double>*>(a.tw1),
+                       static_cast<const cx<double>*>(a.twl), static_cast<const cx<double>*>(a.twh), a.split,
+                       a.sigma_dz);
     return hipGetLastError();
 }
 
@@ -145,6 +171,7 @@ static hipError_t rows_p(const SSLargeArgs& a) {
         case 512: return rows_t<T, 512>(a);
         case 1024: return rows_t<T, 1024>(a);
         case 2048: return rows_t<T, 2048>(a);
+        case 4096: return rows_t<T, 4096>(a);
         default: return hipErrorInvalidValue;
     }
 }
@@ -157,7 +184,6 @@ static hipError_t cols_p(const SSLargeArgs& a) {
         case 256: return cols_t<T, 256>(a);
         case 512: return cols_t<T, 512>(a);
         case 1024: return cols_t<T, 1024>(a);
-        case 2048: return cols_t<T, 2048>(a);
         default: return hipErrorInvalidValue;
     }
 }
