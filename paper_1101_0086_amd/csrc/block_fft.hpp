@@ -160,7 +160,7 @@ __device__ __forceinline__ void fft_from(cx<T> (&v)[R], cx<T>* lds,
 // passed the barrier before this read.  A call ends having read
 // buf[(E - 1) % 2] (E exchanges); the caller's next call must start writing
 // the other buffer, so for odd E the two pointers are swapped on return.
-template <typename T, int B, int R, int r, int p, int SIGN, bool FROM_LDS, bool TO_LDS>
+template <typename T, int B, int R, int r, int p, int SIGN, bool FROM_LDS, bool TO_LDS, bool COLD>
 __device__ __forceinline__ void fft_pass_db(cx<T> (&v)[R], const cx<T>* lds_in, cx<T>* lds_out,
                                             const cx<T>* __restrict__ tw, int tid) {
     constexpr int NT = B / R;
@@ -173,7 +173,8 @@ __device__ __forceinline__ void fft_pass_db(cx<T> (&v)[R], const cx<T>* lds_in, 
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         const int i = tid + u * NT;
-        const int k = i & (p - 1);
+        int k = i & (p - 1);
+        if constexpr (COLD) asm volatile("" : "+v"(k));   // twiddles loaded here, not kept live
         cx<T> x[r];
 #pragma unroll
         for (int q = 0; q < r; ++q) x[q] = v[u + q * NB];
@@ -198,7 +199,7 @@ __device__ __forceinline__ void fft_pass_db(cx<T> (&v)[R], const cx<T>* lds_in, 
     }
 }
 
-template <typename T, int B, int R, int SIGN, int P, int S>
+template <typename T, int B, int R, int SIGN, int P, int S, bool COLD>
 __device__ __forceinline__ void fft_from_db(cx<T> (&v)[R], cx<T>* buf0, cx<T>* buf1,
                                             const cx<T>* __restrict__ tw, int tid) {
     constexpr int r = pass_radix<B, P>();
@@ -207,8 +208,8 @@ __device__ __forceinline__ void fft_from_db(cx<T> (&v)[R], cx<T>* buf0, cx<T>* b
     // pass S reads buf[(S - 1) % 2] and writes buf[S % 2]
     cx<T>* in = (S % 2) ? buf0 : buf1;
     cx<T>* out = (S % 2) ? buf1 : buf0;
-    fft_pass_db<T, B, R, r, P, SIGN, !first, !last>(v, in, out, tw, tid);
-    if constexpr (!last) fft_from_db<T, B, R, SIGN, P * r, S + 1>(v, buf0, buf1, tw, tid);
+    fft_pass_db<T, B, R, r, P, SIGN, !first, !last, COLD>(v, in, out, tw, tid);
+    if constexpr (!last) fft_from_db<T, B, R, SIGN, P * r, S + 1, COLD>(v, buf0, buf1, tw, tid);
 }
 
 template <int B, int P>
@@ -220,12 +221,12 @@ constexpr int exchanges() {
 
 // B-point transform through two LDS buffers (each lds_elems<B>() elements);
 // see fft_pass_db.  Every LDS access made before the call must have passed
-// a barrier if it touched either buffer.
-template <typename T, int B, int R, int SIGN>
+// a barrier if it touched either buffer.  COLD as for block_fft.
+template <typename T, int B, int R, int SIGN, bool COLD = false>
 __device__ __forceinline__ void block_fft_db(cx<T> (&v)[R], cx<T>*& buf0, cx<T>*& buf1,
                                              const cx<T>* __restrict__ tw, int tid) {
     static_assert((B & (B - 1)) == 0 && B >= 64, "power-of-two block");
-    fft_from_db<T, B, R, SIGN, 1, 0>(v, buf0, buf1, tw, tid);
+    fft_from_db<T, B, R, SIGN, 1, 0, COLD>(v, buf0, buf1, tw, tid);
     if constexpr (exchanges<B, 1>() % 2 == 1) {
         cx<T>* t = buf0;
         buf0 = buf1;

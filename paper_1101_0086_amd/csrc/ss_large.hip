@@ -19,8 +19,9 @@
 //
 // Shape: N1 = min(2^floor(log2(N)/2), 1024) rows of the column transform,
 // N2 = N / N1 <= 4096 points per row.  A column workgroup takes TC adjacent
-// columns (TC N1 <= 8192 points, so that each row segment it reads is
-// 64-128 contiguous bytes), and the column groups are dealt to the eight XCDs
+// columns (TC N1 <= 8192 points and TC <= N2 / 128, so that each row segment
+// it reads is 16-128 contiguous bytes while at least 128 workgroups share the
+// work), and the column groups are dealt to the eight XCDs
 // in contiguous runs (workgroup b runs on XCD b mod 8), so that the groups
 // sharing a cache line of a row share that XCD's L2.
 #include "block_fft.hpp"
@@ -73,10 +74,10 @@ ss_rows_kernel(cx<ST>* __restrict__ y, int n1, const cx<double>* __restrict__ tw
     cx<double> v[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = load_w(row[t + NT * m]);
-    block_fft<double, N2, R, +1>(v, lds + r * lds_elems<N2>(), tw2, t);
+    block_fft<double, N2, R, +1, true>(v, lds + r * lds_elems<N2>(), tw2, t);
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = scale(cmul(v[m], prow[t + NT * m]), scl);
-    block_fft<double, N2, R, -1>(v, lds + r * lds_elems<N2>(), tw2, t);
+    block_fft<double, N2, R, -1, true>(v, lds + r * lds_elems<N2>(), tw2, t);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const int n2 = t + NT * m;
@@ -141,16 +142,38 @@ static hipError_t rows_t(const SSLargeArgs& a) {
     return hipGetLastError();
 }
 
-template <typename T, int N1, int MODE>
-static hipError_t cols_tm(const SSLargeArgs& a) {
-    // TC adjacent columns, TC N1 <= 8192 points (FP64 exchange buffer <= 147 KB)
-    constexpr int TC = (8192 / N1) > 16 ? 16 : ((8192 / N1) < 1 ? 1 : (8192 / N1));
+template <typename T, int N1, int TC, int MODE>
+static hipError_t cols_tcm(const SSLargeArgs& a) {
     if (a.n2 % TC) return hipErrorInvalidValue;
     hipLaunchKernelGGL((ss_cols_kernel<T, N1, TC, MODE>), dim3(a.n2 / TC), dim3(TC * N1 / SL_PTS), 0,
                        a.stream, static_cast<cx<T>*>(a.field), a.n2, static_cast<const cx<double>*>(a.tw1),
                        static_cast<const cx<double>*>(a.twl), static_cast<const cx<double>*>(a.twh), a.split,
                        a.sigma_dz);
     return hipGetLastError();
+}
+
+// Columns per workgroup: as many as keep TC N1 <= 8192 points (FP64 exchange
+// buffer <= 147 KB) and at most 16, but no more than leave N2 / 128 column
+// groups (enough workgroups to spread over the 256 CUs); at least 2.
+template <typename T, int N1, int MODE>
+static hipError_t cols_tm(const SSLargeArgs& a) {
+    constexpr int cap = (8192 / N1) > 16 ? 16 : (8192 / N1);
+    int tc = a.n2 / 128;
+    if (tc > cap) tc = cap;
+    if (tc < 2) tc = 2;
+    switch (tc) {
+        case 2: return cols_tcm<T, N1, 2, MODE>(a);
+        case 3: return cols_tcm<T, N1, 2, MODE>(a);
+        case 4: case 5: case 6: case 7:
+            if constexpr (cap >= 4) return cols_tcm<T, N1, 4, MODE>(a);
+            else return cols_tcm<T, N1, 2, MODE>(a);
+        case 8: case 9: case 10: case 11: case 12: case 13: case 14: case 15:
+            if constexpr (cap >= 8) return cols_tcm<T, N1, 8, MODE>(a);
+            else return cols_tcm<T, N1, cap >= 4 ? 4 : 2, MODE>(a);
+        default:
+            if constexpr (cap >= 16) return cols_tcm<T, N1, 16, MODE>(a);
+            else return cols_tcm<T, N1, cap >= 8 ? 8 : (cap >= 4 ? 4 : 2), MODE>(a);
+    }
 }
 
 template <typename T, int N1>

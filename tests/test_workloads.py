@@ -40,6 +40,9 @@ def test_workload_geometry_is_consistent():
         for seg in w.dmmap.seg_len:
             assert abs(round(seg / s.L) * s.L - seg) < 1e-12
         if s.block:
-            assert s.block > 2 * s.halo and w.grid.n % 2 == 0
-            rate = abs(w.dmmap.beta2[0]) * s.omega_band + 0.5 * abs(w.dmmap.beta3[0]) * s.omega_band ** 2
-            assert rate * s.L <= 0.25 * s.halo * w.grid.dt
+            assert s.block > 2 * s.halo and w.grid.n % 2 == 0 and abs(s.shift) <= s.halo // 2
+            # group-delay rate over the band, relative to the window shift (both spans)
+            for b2, b3 in zip(w.dmmap.beta2, w.dmmap.beta3):
+                om = np.linspace(-s.omega_band, s.omega_band, 20001)
+                u = b2 * om + 0.5 * b3 * om ** 2
+                assert np.max(np.abs(u * s.L - s.shift * w.grid.dt)) <= 0.25 * s.halo * w.grid.dt

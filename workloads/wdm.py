@@ -216,12 +216,14 @@ WORKLOADS = {
         MPASettings(L=2.5e-4, M=4, n_iter=2, block=4096, halo=512,
                     omega_band=_omega_sig(8)),
         "f32", 2, _omega_sig(8)),
-    # 32-channel QPSK WDM, 2^22 modes
+    # 32-channel QPSK WDM, 2^22 modes; dz = 7.8125e-6, block size, overlap and
+    # window shift as the autotuner picks them at that dz (4096-blocks, 1024-halo,
+    # four dz per long step, windows moved 192 samples against their cores)
     "wdm32_n4194304_f32": Workload(
         "wdm32_n4194304_f32", Grid(1 << 22, T_BIT / 4096), 1024, 32, "qpsk",
         dm_map(beta3=0.1), 200,
-        MPASettings(L=7.8125e-6, M=1, n_iter=2, block=4096, halo=512,
-                    omega_band=_omega_sig(32)),
+        MPASettings(L=3.125e-5, M=4, n_iter=2, block=4096, halo=1024,
+                    omega_band=_omega_sig(32), shift=192),
         "f32", 3, _omega_sig(32)),
     # 4-channel, 2^16 modes (the gradient workload's forward)
     "wdm4_n65536_f32": Workload(
