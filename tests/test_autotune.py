@@ -47,7 +47,7 @@ def test_shifted_candidates_are_valid_maximal_and_longer():
     from paper_1101_0086_amd import _lib as L
     from paper_1101_0086_amd.autotune import candidates, window_shift
     w = WORKLOADS["wdm32_n4194304_f32"]
-    dz = w.mpa.L
+    dz = w.mpa.L / w.mpa.M
     plain = {(c.block, c.halo): c for c in candidates(w.grid.n, w.grid.dt, w.dmmap, dz, w.mpa.omega_band,
                                                         shifted=False)}
     cands = candidates(w.grid.n, w.grid.dt, w.dmmap, dz, w.mpa.omega_band)
@@ -65,5 +65,7 @@ def test_shifted_candidates_are_valid_maximal_and_longer():
         assert base is None or c.L >= base.L
         longer += base is None or c.L > base.L
     assert longer >= 3
-    # the 4096-block, 512-halo candidate takes two dz per long step instead of one
-    assert {(c.block, c.halo): c for c in cands}[(4096, 512)].M == 2
+    # the 4096-block, 512-halo candidate takes two dz per long step instead of one,
+    # and the 1024-halo one four (the workload's configuration)
+    by = {(c.block, c.halo): c for c in cands}
+    assert by[(4096, 512)].M == 2 and by[(4096, 1024)].M == w.mpa.M and by[(4096, 1024)].shift == w.mpa.shift
