@@ -129,7 +129,7 @@ def main():
     ap.add_argument("--profile-pass", action="store_true",
                     help="for rocprofv3 --kernel-trace: 40 headline launches, 20 split-steps of each precision")
     ap.add_argument("--pmc-pass", action="store_true",
-                    help="for rocprofv3 --pmc: a 64 MiB copy (counter calibration), then 20 headline launches")
+                    help="for rocprofv3 --pmc: a 512 MiB copy (counter calibration), then 20 headline launches")
     ap.add_argument("--pmc-grad", action="store_true",
                     help="for rocprofv3 --pmc: 20 reverse long steps of the 2^16-mode gradient workload")
     args = ap.parse_args()
@@ -168,11 +168,15 @@ def main():
 
     if args.pmc_pass or args.profile_pass:
         if args.pmc_pass:
-            big = torch.zeros(1 << 23, dtype=torch.complex64, device="cuda:0")     # 64 MiB
+            # counter calibration: one copy of 512 MiB whose source was written
+            # first in a 2 GiB fill, so that the 256 MiB last-level cache no
+            # longer holds it (a copy of a cache-resident source fetches nothing)
+            src = torch.ones(1 << 28, dtype=torch.complex64, device="cuda:0")      # 2 GiB
+            dst = torch.empty(1 << 26, dtype=torch.complex64, device="cuda:0")     # 512 MiB
             torch.cuda.synchronize()
-            copy = big.clone()               # one copy kernel: reads 64 MiB, writes 64 MiB
+            dst.copy_(src[: 1 << 26])        # one copy kernel: reads 512 MiB, writes 512 MiB
             torch.cuda.synchronize()
-            del copy
+            del src, dst
         plan.propagate(x, 0.0, (20 if args.pmc_pass else 40) * s.L)
         torch.cuda.synchronize()
         if args.profile_pass:
@@ -184,7 +188,7 @@ def main():
                 torch.cuda.synchronize()
                 ss.close()
         plan.close()
-        print(json.dumps({"pmc_pass" if args.pmc_pass else "profile_pass": True, "copy_bytes": 1 << 26}),
+        print(json.dumps({"pmc_pass" if args.pmc_pass else "profile_pass": True, "copy_bytes": 1 << 29}),
               flush=True)
         return
 

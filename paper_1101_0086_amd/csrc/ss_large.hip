@@ -78,10 +78,14 @@ ss_rows_kernel(cx<ST>* __restrict__ y, int n1, const cx<double>* __restrict__ tw
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = scale(cmul(v[m], prow[t + NT * m]), scl);
     block_fft<double, N2, R, -1, true>(v, lds + r * lds_elems<N2>(), tw2, t);
+    // w_N^{n2 k1} for n2 = t + NT m: w_N^{t k1} (w_N^{NT k1})^m, two table
+    // lookups per thread instead of one per point
+    cx<double> w = big_twiddle(twl, twh, split, t * k1);
+    const cx<double> step = big_twiddle(twl, twh, split, NT * k1);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        const int n2 = t + NT * m;
-        row[n2] = store_n<ST>(cmulc(v[m], big_twiddle(twl, twh, split, n2 * k1)));
+        row[t + NT * m] = store_n<ST>(cmulc(v[m], w));
+        w = cmul(w, step);
     }
 }
 
@@ -111,8 +115,14 @@ ss_cols_kernel(cx<ST>* __restrict__ y, int n2, const cx<double>* __restrict__ tw
     }
     if constexpr (MODE != SS_COL_LAST) {
         block_fft<double, N1, R, +1, true>(v, my, tw1, t);      // Y[k1][n2], k1 = t + NT m
+        // w_N^{col k1} for k1 = t + NT m, as in the row kernel
+        cx<double> w = big_twiddle(twl, twh, split, col * t);
+        const cx<double> step = big_twiddle(twl, twh, split, col * NT);
 #pragma unroll
-        for (int m = 0; m < R; ++m) v[m] = cmul(v[m], big_twiddle(twl, twh, split, col * (t + NT * m)));
+        for (int m = 0; m < R; ++m) {
+            v[m] = cmul(v[m], w);
+            w = cmul(w, step);
+        }
     }
 #pragma unroll
     for (int m = 0; m < R; ++m) y[(size_t)(t + NT * m) * n2 + col] = store_n<ST>(v[m]);
