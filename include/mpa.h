@@ -74,7 +74,9 @@ typedef enum {
     MPA_EDEVICE = -3,      /* no usable gfx950 device, or a HIP runtime error        */
     MPA_EALIGN = -4,       /* z0/z1 off the step grid, or a step not dividing a span */
     MPA_EHALO = -5,        /* halo too small for the long step (see above)           */
-    MPA_EUNSUPPORTED = -6  /* valid request outside the sizes compiled in    */
+    MPA_EUNSUPPORTED = -6, /* valid request outside the sizes compiled in            */
+    MPA_ENONFINITE = -7,   /* the field holds NaN or Inf (mpa_check_field)           */
+    MPA_EDIVERGE = -8      /* the Picard sweeps do not contract (mpa_picard_residuals) */
 } mpa_status;
 
 typedef enum {
@@ -194,6 +196,26 @@ int mpa_step(mpa_plan* plan, void* field, double z0, void* stream);
 /* March long steps from z0 to z1 (both multiples of L, z1 >= z0) in place;
  * the state carried between long steps is the field alone.                  */
 int mpa_propagate(mpa_plan* plan, void* field, double z0, double z1, void* stream);
+
+/* ---- failure detection ------------------------------------------------------
+ *
+ * Non-finite scan: counts the NaN or Inf components of the plan's field
+ * (N samples) on `stream` and waits for the stream; MPA_ENONFINITE when there
+ * is any, else MPA_OK.                                                       */
+int mpa_check_field(const mpa_plan* plan, const void* field, void* stream);
+
+/* Picard residuals of one long step (Eq. 6; the sweep count and its floor
+ * (L / z_nl)^(n+1) discussed after Eq. 7): from `field` at z0 (a multiple of
+ * L; the field is not modified), the long step's output A^(k) after k sweeps,
+ * k = 0..n_iter (k = 0: the linear step), and
+ *   residuals[k - 1] = ||A^(k) - A^(k-1)|| / ||A^(k)||   (host array of n_iter).
+ * For a contracting iteration (L well below the nonlinear length) they fall
+ * geometrically.  Returns MPA_EDIVERGE when some residual does not fall below
+ * the one before it, MPA_ENONFINITE when an iterate is not finite (its
+ * residual is NaN), else MPA_OK.  Runs n_iter + 1 long steps and waits for
+ * `stream`; the first call allocates a second field of N samples, kept by the
+ * plan.                                                                       */
+int mpa_picard_residuals(mpa_plan* plan, const void* field, double z0, double* residuals, void* stream);
 
 /* ---- allocation-free march ------------------------------------------------
  *

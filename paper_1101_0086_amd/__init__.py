@@ -85,6 +85,23 @@ class MPAPlan:
                                             float(z1), _stream_handle(torch, field.device)))
         return field
 
+    def check_field(self, field):
+        """mpa_check_field: raises MPAError (MPA_ENONFINITE) if the field holds NaN or Inf."""
+        torch = _check_field(field, self.precision, self.n)
+        _lib.check(_lib.lib().mpa_check_field(self._h, C.c_void_p(field.data_ptr()),
+                                              _stream_handle(torch, field.device)))
+
+    def picard_residuals(self, field, z0, n_iter):
+        """mpa_picard_residuals: (status, residuals) of the long step at z0;
+        status is MPA_OK, MPA_EDIVERGE or MPA_ENONFINITE (other errors raise)."""
+        torch = _check_field(field, self.precision, self.n)
+        r = (C.c_double * n_iter)()
+        st = _lib.lib().mpa_picard_residuals(self._h, C.c_void_p(field.data_ptr()), float(z0), r,
+                                             _stream_handle(torch, field.device))
+        if st not in (_lib.MPA_OK, _lib.MPA_EDIVERGE, _lib.MPA_ENONFINITE):
+            _lib.check(st)
+        return st, list(r)
+
     def checkpoint_count(self, z0, z1):
         c = C.c_int64()
         _lib.check(_lib.lib().mpa_checkpoint_count(self._h, float(z0), float(z1), C.byref(c)))

@@ -18,6 +18,8 @@ MPA_EDEVICE = -3
 MPA_EALIGN = -4
 MPA_EHALO = -5
 MPA_EUNSUPPORTED = -6
+MPA_ENONFINITE = -7
+MPA_EDIVERGE = -8
 
 MPA_C64 = 0
 MPA_C128 = 1
@@ -35,7 +37,7 @@ EXPORTED = ("mpa_plan_create", "mpa_plan_destroy", "mpa_plan_get_info", "mpa_pla
             "ss_plan_create", "ss_plan_destroy", "ss_propagate", "mpa_status_string", "mpa_last_error",
             "mpa_checkpoint_count", "mpa_propagate_checkpointed", "mpa_adjoint",
             "mpa_batch_checkpoint_count", "mpa_batch_propagate_checkpointed", "mpa_batch_adjoint",
-            "mpa_propagate_noalloc")
+            "mpa_propagate_noalloc", "mpa_check_field", "mpa_picard_residuals")
 
 
 class mpa_map(C.Structure):
@@ -92,6 +94,8 @@ def lib() -> C.CDLL:
     h.mpa_step.argtypes = [vp, vp, dp, vp]
     h.mpa_propagate.argtypes = [vp, vp, dp, dp, vp]
     h.mpa_propagate_noalloc.argtypes = [C.POINTER(mpa_params), C.POINTER(mpa_map), vp, dp, dp, vp]
+    h.mpa_check_field.argtypes = [vp, vp, vp]
+    h.mpa_picard_residuals.argtypes = [vp, vp, dp, C.POINTER(C.c_double), vp]
     h.mpa_batch_plan_validate.argtypes = [C.POINTER(mpa_params), C.POINTER(mpa_map), C.POINTER(mpa_batch_desc)]
     h.mpa_batch_plan_create.argtypes = [C.POINTER(mpa_params), C.POINTER(mpa_map), C.POINTER(mpa_batch_desc),
                                         C.c_int, C.POINTER(vp)]

@@ -156,6 +156,16 @@ hipError_t launch_phase_table_t(void* table, int precision, int n1, int n2, int 
 hipError_t launch_phase_table(void* table, int precision, int B, int rows,
                               const double* coef, const double* mask, hipStream_t stream);
 
+// ---- field statistics ----------------------------------------------------------
+
+// Workgroups of the first reduction pass (partial holds 3 STATS_PARTS doubles).
+constexpr int STATS_PARTS = 1024;
+// out[0] = sum |a - b|^2 (0 when b is null), out[1] = sum |a|^2 over the
+// finite samples, out[2] = number of non-finite components of a; a fixed
+// summation order (deterministic).  partial and out are device memory.
+hipError_t launch_field_stats(const void* a, const void* b, int64_t n, int precision, double* partial,
+                              double* out, hipStream_t stream);
+
 // ---- allocation-free entry point ----------------------------------------------
 
 // Bytes of the per-device scratch array of mpa_propagate_noalloc.

@@ -270,6 +270,10 @@ struct mpa_plan {
     // reverse pass: workspace of the plan's own field, roll-off derivative tables
     AdjWork adj;
     void* adj_mask = nullptr;           // n_seg x 2 x B FP64 complex (blocked plans)
+    // diagnostics: reduction partials and result (3 STATS_PARTS + 3 doubles), and a
+    // second field for the Picard residuals (allocated by their first call)
+    void* diag = nullptr;
+    void* diag_field = nullptr;
 };
 
 static void plan_free(mpa_plan* p) {
@@ -278,7 +282,7 @@ static void plan_free(mpa_plan* p) {
     (void)hipDeviceSynchronize();
     for (void* q : {p->phase, p->phase_last, p->node_scale, p->twiddle, p->twiddle64, p->taper, p->work,
                     p->adj_mask, p->nodes.psi0, p->nodes.half_u0, p->nodes.u[0], p->nodes.u[1],
-                    p->w_psi0, p->w_sums, p->w_cur, p->w_work, p->w_work64})
+                    p->w_psi0, p->w_sums, p->w_cur, p->w_work, p->w_work64, p->diag, p->diag_field})
         if (q) (void)hipFree(q);
     for (void* q : p->w_tw)
         if (q) (void)hipFree(q);
@@ -440,7 +444,8 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
     if (hipMalloc(&p->phase, phase_bytes) != hipSuccess || hipMalloc(&p->phase_last, last_bytes) != hipSuccess ||
         hipMalloc(&p->node_scale, ns_bytes) != hipSuccess || hipMalloc(&p->twiddle, tw_bytes) != hipSuccess ||
         hipMalloc(&p->twiddle64, tw64_bytes) != hipSuccess || hipMalloc(&p->taper, tp_bytes) != hipSuccess ||
-        hipMalloc(&p->work, work_bytes) != hipSuccess) {
+        hipMalloc(&p->work, work_bytes) != hipSuccess ||
+        hipMalloc(&p->diag, (3 * (size_t)mpa::STATS_PARTS + 3) * sizeof(double)) != hipSuccess) {
         plan_free(p);
         return fail(MPA_ENOMEM, "device allocation of %zu bytes failed", (size_t)p->table_bytes + work_bytes);
     }
@@ -631,8 +636,11 @@ static int gain_row(const mpa_plan* p, int64_t m, int s) {
     return (int)r;
 }
 
+// One long step m from `in` to `out`.  nit > 0 runs that many Picard sweeps
+// instead of the plan's; linear = true sets sigma to 0 (the linear step,
+// the zeroth Picard iterate).
 static int launch_long_step(mpa_plan* p, const void* in, void* out, int64_t m, hipStream_t stream,
-                            const mpa::BatchItems* batch = nullptr) {
+                            const mpa::BatchItems* batch = nullptr, int nit = 0, bool linear = false) {
     const int s = p->sched.span_of(m);
     const int M = p->prm.M;
     const double gain = p->sched.amp_after(m) ? p->lumped : 1.0;
@@ -651,8 +659,9 @@ static int launch_long_step(mpa_plan* p, const void* in, void* out, int64_t m, h
     a.twiddle = p->twiddle;
     a.taper = p->taper;
     a.M = M;
-    a.n_iter = p->prm.n_iter;
+    a.n_iter = nit > 0 ? nit : p->prm.n_iter;
     a.sigma = s < (int)p->sigma.size() ? p->sigma[s] : 1.0;   // boundary-crossing steps: sigma in the table
+    if (linear) a.sigma = 0.0;
     a.out_scale = p->row_out[gain_row(p, m, s)] / p->block * gain;
     a.precision = p->prm.precision;
     a.batch = batch;
@@ -684,7 +693,7 @@ static int launch_long_step(mpa_plan* p, const void* in, void* out, int64_t m, h
         w.work = p->w_work;
         w.work64 = p->w_work64;
         w.M = M;
-        w.n_iter = p->prm.n_iter;
+        w.n_iter = a.n_iter;
         w.sigma = a.sigma;
         w.out_scale = a.out_scale;
         w.precision = p->prm.precision;
@@ -734,6 +743,68 @@ int mpa_propagate(mpa_plan* p, void* field, double z0, double z1, void* stream) 
     if (!p || !field) return fail(MPA_EINVAL, "NULL plan or field");
     if (hipSetDevice(p->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
     return march(p, field, p->work, p->prm.n, z0, z1, (hipStream_t)stream, nullptr);
+}
+
+// ---- diagnostics: non-finite scan, Picard residuals ---------------------------------
+
+// out = {sum |a - b|^2, sum |a|^2, non-finite components of a}; waits for the stream.
+static int field_stats(const mpa_plan* p, const void* a, const void* b, hipStream_t s, double out[3]) {
+    double* partial = static_cast<double*>(p->diag);
+    double* dev = partial + 3 * mpa::STATS_PARTS;
+    if (mpa::launch_field_stats(a, b, p->prm.n, p->prm.precision, partial, dev, s) != hipSuccess ||
+        hipMemcpyAsync(out, dev, 3 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(MPA_EDEVICE, "field statistics failed");
+    return MPA_OK;
+}
+
+int mpa_check_field(const mpa_plan* p, const void* field, void* stream) {
+    if (!p || !field) return fail(MPA_EINVAL, "NULL plan or field");
+    if (hipSetDevice(p->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
+    double st[3];
+    const int e = field_stats(p, field, nullptr, (hipStream_t)stream, st);
+    if (e) return e;
+    if (st[2] > 0) return fail(MPA_ENONFINITE, "%.0f non-finite components in the field", st[2]);
+    return MPA_OK;
+}
+
+int mpa_picard_residuals(mpa_plan* p, const void* field, double z0, double* residuals, void* stream) {
+    if (!p || !field || !residuals) return fail(MPA_EINVAL, "NULL plan, field or residuals");
+    const int64_t m = grid_index(z0, p->prm.L);
+    if (m == INT64_MIN) return fail(MPA_EALIGN, "z0 = %g is not a multiple of L = %g", z0, p->prm.L);
+    if (hipSetDevice(p->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
+    if (!p->diag_field && hipMalloc(&p->diag_field, (size_t)p->prm.n * p->elem) != hipSuccess) {
+        p->diag_field = nullptr;
+        return fail(MPA_ENOMEM, "residual workspace allocation failed");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    void* prev = p->work;
+    void* cur = p->diag_field;
+    // iterate 0: the linear step (psi^(0)_M = psi_0)
+    int st = launch_long_step(p, field, prev, m, s, nullptr, 1, true);
+    if (st) return st;
+    const int nit = p->prm.n_iter;
+    bool finite = true;
+    for (int k = 1; k <= nit; ++k) {
+        st = launch_long_step(p, field, cur, m, s, nullptr, k, false);
+        if (st) return st;
+        double v[3];
+        st = field_stats(p, cur, prev, s, v);
+        if (st) return st;
+        residuals[k - 1] = v[1] > 0 ? std::sqrt(v[0] / v[1]) : (v[0] > 0 ? INFINITY : 0.0);
+        if (v[2] > 0) {
+            residuals[k - 1] = NAN;
+            finite = false;
+        }
+        std::swap(prev, cur);
+    }
+    if (!finite) return fail(MPA_ENONFINITE, "a Picard iterate of the long step at z0 = %g is not finite", z0);
+    for (int k = 1; k < nit; ++k)
+        if (!(residuals[k] < residuals[k - 1]))
+            return fail(MPA_EDIVERGE,
+                        "Picard residual grows from sweep %d to %d (%g -> %g) in the long step at z0 = %g", k, k + 1,
+                        residuals[k - 1], residuals[k], z0);
+    return MPA_OK;
 }
 
 // ---- reverse pass (gradients) ----------------------------------------------------
@@ -1480,6 +1551,8 @@ const char* mpa_status_string(int status) {
         case MPA_EALIGN: return "MPA_EALIGN: position or step off the grid";
         case MPA_EHALO: return "MPA_EHALO: halo too small for the long step";
         case MPA_EUNSUPPORTED: return "MPA_EUNSUPPORTED: size or combination not compiled into the library";
+        case MPA_ENONFINITE: return "MPA_ENONFINITE: the field holds a non-finite value";
+        case MPA_EDIVERGE: return "MPA_EDIVERGE: the Picard sweeps do not contract";
         default: return "unknown mpa_status";
     }
 }

@@ -313,6 +313,76 @@ hipError_t launch_step_tables(const StepTableParams& p, void* node_scale, void* 
     return hipGetLastError();
 }
 
+// ---- field statistics (non-finite scan, Picard residuals) ------------------------
+
+constexpr int STATS_TPB = 256;
+
+// Per workgroup: sum |a - b|^2 (b may be null: 0), sum |a|^2 and the number of
+// non-finite components of a, over a grid-stride share of the n samples, in
+// a fixed order; partial[3 w + q].
+template <typename T>
+__global__ void __launch_bounds__(STATS_TPB)
+field_stats_kernel(const cx<T>* __restrict__ a, const cx<T>* __restrict__ b, long long n, double* __restrict__ partial) {
+    __shared__ double red[3][STATS_TPB];
+    double d2 = 0.0, a2 = 0.0, bad = 0.0;
+    const long long stride = (long long)gridDim.x * STATS_TPB;
+    for (long long i = (long long)blockIdx.x * STATS_TPB + threadIdx.x; i < n; i += stride) {
+        const cx<T> x = a[i];
+        const double re = x.re, im = x.im;
+        if (!isfinite(re) || !isfinite(im)) {
+            bad += 1.0;
+            continue;
+        }
+        a2 += re * re + im * im;
+        if (b) {
+            const double dr = re - double(b[i].re), di = im - double(b[i].im);
+            d2 += dr * dr + di * di;
+        }
+    }
+    red[0][threadIdx.x] = d2;
+    red[1][threadIdx.x] = a2;
+    red[2][threadIdx.x] = bad;
+    __syncthreads();
+    for (int h = STATS_TPB / 2; h > 0; h /= 2) {
+        if (threadIdx.x < h)
+            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) partial[3 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// out[q] = sum over the parts of partial[3 w + q], in a fixed order (one workgroup).
+__global__ void __launch_bounds__(STATS_TPB)
+stats_final_kernel(const double* __restrict__ partial, int parts, double* __restrict__ out) {
+    __shared__ double red[3][STATS_TPB];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int w = threadIdx.x; w < parts; w += STATS_TPB)
+        for (int q = 0; q < 3; ++q) acc[q] += partial[3 * w + q];
+    for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int h = STATS_TPB / 2; h > 0; h /= 2) {
+        if (threadIdx.x < h)
+            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_field_stats(const void* a, const void* b, int64_t n, int precision, double* partial,
+                              double* out, hipStream_t stream) {
+    const long long want = (n + STATS_TPB - 1) / STATS_TPB;
+    const int parts = (int)(want < STATS_PARTS ? (want > 0 ? want : 1) : STATS_PARTS);
+    if (precision == 0)
+        hipLaunchKernelGGL(field_stats_kernel<float>, dim3(parts), dim3(STATS_TPB), 0, stream,
+                           static_cast<const cx<float>*>(a), static_cast<const cx<float>*>(b), (long long)n, partial);
+    else
+        hipLaunchKernelGGL(field_stats_kernel<double>, dim3(parts), dim3(STATS_TPB), 0, stream,
+                           static_cast<const cx<double>*>(a), static_cast<const cx<double>*>(b), (long long)n,
+                           partial);
+    hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(STATS_TPB), 0, stream, partial, parts, out);
+    return hipGetLastError();
+}
+
 #endif  // MPA_PART_T
 
 }  // namespace mpa

@@ -114,7 +114,7 @@ def test_error_message_and_status_strings():
     buf = C.create_string_buffer(256)
     n = L.lib().mpa_last_error(buf, 256)
     assert n > 0 and b"halo" in buf.value
-    for s in (0, -1, -2, -3, -4, -5, -6):
+    for s in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert L.lib().mpa_status_string(s).startswith(b"MPA_")
 
 
@@ -131,6 +131,8 @@ def test_null_arguments_rejected():
     assert h.mpa_adjoint(None, None, None, 0.0, 1.0, None, 0, None) == L.MPA_EINVAL
     assert h.mpa_batch_adjoint(None, None, None, 0.0, 1.0, None, 0, None) == L.MPA_EINVAL
     assert h.mpa_batch_propagate_checkpointed(None, None, 0.0, 1.0, None, None) == L.MPA_EINVAL
+    assert h.mpa_check_field(None, None, None) == L.MPA_EINVAL
+    assert h.mpa_picard_residuals(None, None, 0.0, None, None) == L.MPA_EINVAL
     out = C.c_void_p(123)
     assert h.mpa_plan_create(None, None, 0, C.byref(out)) == L.MPA_EINVAL and out.value is None
     assert h.mpa_plan_destroy(None) == L.MPA_OK
