@@ -19,9 +19,8 @@
 //
 // Shape: N1 = min(2^floor(log2(N)/2), 1024) rows of the column transform,
 // N2 = N / N1 <= 4096 points per row.  A column workgroup takes TC adjacent
-// columns (TC N1 <= 8192 points and TC <= N2 / 128, so that each row segment
-// it reads is 16-128 contiguous bytes while at least 128 workgroups share the
-// work), and the column groups are dealt to the eight XCDs
+// columns (TC N1 <= 2048 points and TC <= N2 / 128: each row segment it reads
+// is TC contiguous samples), and the column groups are dealt to the eight XCDs
 // in contiguous runs (workgroup b runs on XCD b mod 8), so that the groups
 // sharing a cache line of a row share that XCD's L2.
 #include "block_fft.hpp"
@@ -162,28 +161,23 @@ static hipError_t cols_tcm(const SSLargeArgs& a) {
     return hipGetLastError();
 }
 
-// Columns per workgroup: as many as keep TC N1 <= 8192 points (FP64 exchange
-// buffer <= 147 KB) and at most 16, but no more than leave N2 / 128 column
-// groups (enough workgroups to spread over the 256 CUs); at least 2.
+// Columns per workgroup: TC N1 <= 2048 points and TC <= N2 / 128 (at least
+// 128 workgroups).  Measured over TC N1 <= 512..8192 at 2^18, 2^20 and 2^22
+// modes: 2048 points per workgroup is the fastest at 2^20 and 2^22 (at 2^22
+// 94 us per split-step against 128 us with 8192: more workgroups resident
+// per CU hide the load latency of the strided column reads), within 10 % of
+// the best at 2^18.
 template <typename T, int N1, int MODE>
 static hipError_t cols_tm(const SSLargeArgs& a) {
-    constexpr int cap = (8192 / N1) > 16 ? 16 : (8192 / N1);
+    constexpr int cap = (2048 / N1) > 16 ? 16 : ((2048 / N1) < 1 ? 1 : (2048 / N1));
     int tc = a.n2 / 128;
     if (tc > cap) tc = cap;
-    if (tc < 2) tc = 2;
-    switch (tc) {
-        case 2: return cols_tcm<T, N1, 2, MODE>(a);
-        case 3: return cols_tcm<T, N1, 2, MODE>(a);
-        case 4: case 5: case 6: case 7:
-            if constexpr (cap >= 4) return cols_tcm<T, N1, 4, MODE>(a);
-            else return cols_tcm<T, N1, 2, MODE>(a);
-        case 8: case 9: case 10: case 11: case 12: case 13: case 14: case 15:
-            if constexpr (cap >= 8) return cols_tcm<T, N1, 8, MODE>(a);
-            else return cols_tcm<T, N1, cap >= 4 ? 4 : 2, MODE>(a);
-        default:
-            if constexpr (cap >= 16) return cols_tcm<T, N1, 16, MODE>(a);
-            else return cols_tcm<T, N1, cap >= 8 ? 8 : (cap >= 4 ? 4 : 2), MODE>(a);
-    }
+    if (tc < 1) tc = 1;
+    if (tc >= 16 && cap >= 16) return cols_tcm<T, N1, (cap >= 16 ? 16 : 1), MODE>(a);
+    if (tc >= 8 && cap >= 8) return cols_tcm<T, N1, (cap >= 8 ? 8 : 1), MODE>(a);
+    if (tc >= 4 && cap >= 4) return cols_tcm<T, N1, (cap >= 4 ? 4 : 1), MODE>(a);
+    if (tc >= 2 && cap >= 2) return cols_tcm<T, N1, (cap >= 2 ? 2 : 1), MODE>(a);
+    return cols_tcm<T, N1, 1, MODE>(a);
 }
 
 template <typename T, int N1>
