@@ -30,7 +30,7 @@
  *     the default stream).  Calls return once the work is enqueued.
  *   - Every function returns an mpa_status (0 on success, < 0 on error).
  *     Argument validation happens on the host before any device call, so a
- *     rejected call has no effect; mpa_last_error() returns a message for
+ *     rejected call has no effect; mpa_last_error_detail() returns a message for
  *     the calling thread's most recent failure.
  *   - A plan is not thread safe: calls on one plan must not overlap in time
  *     on different host threads.  Different plans are independent.
@@ -74,9 +74,9 @@ typedef enum {
     MPA_EDEVICE = -3,      /* no usable gfx950 device, or a HIP runtime error        */
     MPA_EALIGN = -4,       /* z0/z1 off the step grid, or a step not dividing a span */
     MPA_EHALO = -5,        /* halo too small for the long step (see above)           */
-    MPA_EUNSUPPORTED = -6, /* valid request outside the sizes compiled in            */
-    MPA_ENONFINITE = -7,   /* the field holds NaN or Inf (mpa_check_field)           */
-    MPA_EDIVERGE = -8      /* the Picard sweeps do not contract (mpa_picard_residuals) */
+    MPA_ENONFINITE = -6,   /* the field holds NaN or Inf (mpa_check_field)           */
+    MPA_EDIVERGE = -7,     /* the Picard sweeps do not contract (mpa_picard_residuals) */
+    MPA_EUNSUPPORTED = -8  /* valid request outside the sizes compiled in            */
 } mpa_status;
 
 typedef enum {
@@ -374,13 +374,20 @@ int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz,
 int ss_plan_destroy(ss_plan* plan);
 
 /* Split-step from z0 to z1 (multiples of dz), in place.                      */
-int ss_propagate(ss_plan* plan, void* field, double z0, double z1, void* stream);
+int ss_plan_propagate(ss_plan* plan, void* field, double z0, double z1, void* stream);
+
+/* The same without a plan: builds one on the calling thread's current device
+ * (tables of 2 n_seg N FP64 complex, allocated), runs ss_plan_propagate on
+ * `stream`, waits for the stream and frees the plan.  For one-off runs; a
+ * caller that repeats runs keeps a plan instead.                             */
+int ss_propagate(const mpa_map* map, int64_t n, double dt, double dz, int32_t precision,
+                 void* field, double z0, double z1, void* stream);
 
 const char* mpa_status_string(int status);
 
 /* Copies the calling thread's last error message (NUL-terminated, truncated
  * to len bytes) and returns its full length.                                */
-int mpa_last_error(char* buf, int len);
+int mpa_last_error_detail(char* buf, int len);
 
 #ifdef __cplusplus
 }

@@ -13,7 +13,7 @@ from . import _lib
 from ._lib import MPA_C64, MPA_C128, MPA_NODE_PARALLEL, MPA_SHIFT_AUTO, MPA_WAVEFRONT, MPAError
 
 __all__ = ["MPAPlan", "MPABatchPlan", "Graph", "SSPlan", "MPA_C64", "MPA_C128", "MPA_WAVEFRONT",
-           "MPA_NODE_PARALLEL", "MPA_SHIFT_AUTO", "MPAError", "validate", "propagate_noalloc"]
+           "MPA_NODE_PARALLEL", "MPA_SHIFT_AUTO", "MPAError", "validate", "propagate_noalloc", "ss_propagate"]
 
 
 def _stream_handle(torch, device):
@@ -255,8 +255,24 @@ class MPABatchPlan:
     __del__ = close
 
 
+def ss_propagate(field, dt, dmmap, dz, z0, z1):
+    """ss_propagate (Eq. 4) without a plan: the library builds the tables on
+    the field's device, runs on torch's current stream, waits for it and
+    frees them.  `field`: contiguous complex64 (MPA_C64) or complex128
+    (MPA_C128) CUDA tensor, updated in place."""
+    import torch
+    prec = MPA_C64 if field.dtype == torch.complex64 else MPA_C128
+    _check_field(field, prec, field.numel())
+    m = _lib.MapStruct(dmmap)
+    with torch.cuda.device(field.device):
+        _lib.check(_lib.lib().ss_propagate(C.byref(m.s), int(field.numel()), float(dt), float(dz), int(prec),
+                                           C.c_void_p(field.data_ptr()), float(z0), float(z1),
+                                           _stream_handle(torch, field.device)))
+    return field
+
+
 class SSPlan:
-    """ss_plan_create / ss_propagate (Eq. 4)."""
+    """ss_plan_create / ss_plan_propagate (Eq. 4)."""
 
     def __init__(self, n, dt, dmmap, dz, precision=MPA_C64, device=0):
         self.n, self.precision = int(n), int(precision)
@@ -268,8 +284,8 @@ class SSPlan:
 
     def propagate(self, field, z0, z1):
         torch = _check_field(field, self.precision, self.n)
-        _lib.check(_lib.lib().ss_propagate(self._h, C.c_void_p(field.data_ptr()), float(z0),
-                                           float(z1), _stream_handle(torch, field.device)))
+        _lib.check(_lib.lib().ss_plan_propagate(self._h, C.c_void_p(field.data_ptr()), float(z0),
+                                                float(z1), _stream_handle(torch, field.device)))
         return field
 
     def close(self):

@@ -17,9 +17,9 @@ MPA_ENOMEM = -2
 MPA_EDEVICE = -3
 MPA_EALIGN = -4
 MPA_EHALO = -5
-MPA_EUNSUPPORTED = -6
-MPA_ENONFINITE = -7
-MPA_EDIVERGE = -8
+MPA_ENONFINITE = -6
+MPA_EDIVERGE = -7
+MPA_EUNSUPPORTED = -8
 
 MPA_C64 = 0
 MPA_C128 = 1
@@ -34,7 +34,7 @@ EXPORTED = ("mpa_plan_create", "mpa_plan_destroy", "mpa_plan_get_info", "mpa_pla
             "mpa_step", "mpa_propagate", "mpa_batch_plan_validate", "mpa_batch_plan_create",
             "mpa_batch_plan_destroy", "mpa_batch_get_info", "mpa_batch_propagate",
             "mpa_graph_capture", "mpa_batch_graph_capture", "mpa_graph_launch", "mpa_graph_destroy",
-            "ss_plan_create", "ss_plan_destroy", "ss_propagate", "mpa_status_string", "mpa_last_error",
+            "ss_plan_create", "ss_plan_destroy", "ss_plan_propagate", "ss_propagate", "mpa_status_string", "mpa_last_error_detail",
             "mpa_checkpoint_count", "mpa_propagate_checkpointed", "mpa_adjoint",
             "mpa_batch_checkpoint_count", "mpa_batch_propagate_checkpointed", "mpa_batch_adjoint",
             "mpa_propagate_noalloc", "mpa_check_field", "mpa_picard_residuals")
@@ -108,7 +108,8 @@ def lib() -> C.CDLL:
     h.mpa_graph_destroy.argtypes = [vp]
     h.ss_plan_create.argtypes = [C.POINTER(mpa_map), C.c_int64, dp, dp, C.c_int32, C.c_int, C.POINTER(vp)]
     h.ss_plan_destroy.argtypes = [vp]
-    h.ss_propagate.argtypes = [vp, vp, dp, dp, vp]
+    h.ss_plan_propagate.argtypes = [vp, vp, dp, dp, vp]
+    h.ss_propagate.argtypes = [C.POINTER(mpa_map), C.c_int64, dp, dp, C.c_int32, vp, dp, dp, vp]
     h.mpa_checkpoint_count.argtypes = [vp, dp, dp, C.POINTER(C.c_int64)]
     h.mpa_propagate_checkpointed.argtypes = [vp, vp, dp, dp, vp, vp]
     h.mpa_adjoint.argtypes = [vp, vp, vp, dp, dp, vp, C.c_int64, vp]
@@ -117,7 +118,7 @@ def lib() -> C.CDLL:
     h.mpa_batch_adjoint.argtypes = [vp, vp, vp, dp, dp, vp, C.c_int64, vp]
     h.mpa_status_string.argtypes = [C.c_int]
     h.mpa_status_string.restype = C.c_char_p
-    h.mpa_last_error.argtypes = [C.c_char_p, C.c_int]
+    h.mpa_last_error_detail.argtypes = [C.c_char_p, C.c_int]
     for name in EXPORTED:
         if name not in ("mpa_status_string",):
             getattr(h, name).restype = C.c_int
@@ -128,7 +129,7 @@ def lib() -> C.CDLL:
 def check(status: int) -> None:
     if status != MPA_OK:
         buf = C.create_string_buffer(1024)
-        lib().mpa_last_error(buf, 1024)
+        lib().mpa_last_error_detail(buf, 1024)
         raise MPAError(status, buf.value.decode() or lib().mpa_status_string(status).decode())
 
 

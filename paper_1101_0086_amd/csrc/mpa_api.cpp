@@ -1557,7 +1557,7 @@ const char* mpa_status_string(int status) {
     }
 }
 
-int mpa_last_error(char* buf, int len) {
+int mpa_last_error_detail(char* buf, int len) {
     const int n = (int)g_last_error.size();
     if (buf && len > 0) {
         const int c = n < len - 1 ? n : len - 1;

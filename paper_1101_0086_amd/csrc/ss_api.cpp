@@ -85,12 +85,10 @@ static bool run_large(ss_plan* p, void* field, const void* half_ph, const void* 
     return mpa::launch_ss_cols(a) == hipSuccess;
 }
 
-extern "C" {
-
-int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz, int32_t precision, int device,
-                   ss_plan** out) {
-    if (!out) return fail_status(MPA_EINVAL, "out is NULL");
-    *out = nullptr;
+// Host checks of a split-step request (no device call); fills the steps per
+// span, the steps per map period and per amplifier period.
+static int ss_validate(const mpa_map* map, int64_t n, double dt, double dz, int32_t precision,
+                       std::vector<int64_t>& steps, int64_t* period, int64_t* amp) {
     int st = validate_map_c(map);
     if (st) return st;
     if (n < 64 || (n & (n - 1)) != 0 || n > (int64_t(1) << 30))
@@ -99,12 +97,24 @@ int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz, int32_t 
         return fail_status(MPA_EINVAL, "dt and dz must be finite and > 0");
     if (precision != MPA_C64 && precision != MPA_C128)
         return fail_status(MPA_EINVAL, "precision must be MPA_C64 or MPA_C128");
-    std::vector<int64_t> steps(map->n_seg);
-    int64_t period = 0, amp = 0;
-    st = schedule_c(map, dz, steps.data(), &period, &amp);
+    steps.assign(map->n_seg, 0);
+    st = schedule_c(map, dz, steps.data(), period, amp);
     if (st) return st;
     if (!mpa::ss_small_supported(precision, n) && !mpa::ss_large_supported(precision, n))
         return fail_status(MPA_EUNSUPPORTED, "split-step window size not compiled into the library (512..2^22)");
+    return MPA_OK;
+}
+
+extern "C" {
+
+int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz, int32_t precision, int device,
+                   ss_plan** out) {
+    if (!out) return fail_status(MPA_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::vector<int64_t> steps;
+    int64_t period = 0, amp = 0;
+    int st = ss_validate(map, n, dt, dz, precision, steps, &period, &amp);
+    if (st) return st;
     st = check_device_c(device);
     if (st) return st;
     if (hipSetDevice(device) != hipSuccess) return fail_status(MPA_EDEVICE, "hipSetDevice failed");
@@ -249,7 +259,7 @@ static bool run_steps_gain(ss_plan* p, void* field, int s, int64_t j, int64_t ru
     return true;
 }
 
-int ss_propagate(ss_plan* p, void* field, double z0, double z1, void* stream) {
+int ss_plan_propagate(ss_plan* p, void* field, double z0, double z1, void* stream) {
     if (!p || !field) return fail_status(MPA_EINVAL, "NULL plan or field");
     const int64_t j0 = grid_index_c(z0, p->dz), j1 = grid_index_c(z1, p->dz);
     if (j0 == INT64_MIN || j1 == INT64_MIN) return fail_status(MPA_EALIGN, "z0 or z1 is not a multiple of dz");
@@ -314,6 +324,29 @@ int ss_propagate(ss_plan* p, void* field, double z0, double z1, void* stream) {
         }
     }
     return MPA_OK;
+}
+
+int ss_propagate(const mpa_map* map, int64_t n, double dt, double dz, int32_t precision, void* field, double z0,
+                 double z1, void* stream) {
+    if (!field) return fail_status(MPA_EINVAL, "NULL field");
+    std::vector<int64_t> steps;
+    int64_t period = 0, amp = 0;
+    int st = ss_validate(map, n, dt, dz, precision, steps, &period, &amp);
+    if (st) return st;
+    const int64_t j0 = grid_index_c(z0, dz), j1 = grid_index_c(z1, dz);
+    if (j0 == INT64_MIN || j1 == INT64_MIN) return fail_status(MPA_EALIGN, "z0 or z1 is not a multiple of dz");
+    if (j1 < j0) return fail_status(MPA_EINVAL, "z1 < z0");
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return fail_status(MPA_EDEVICE, "hipGetDevice failed");
+    ss_plan* p = nullptr;
+    st = ss_plan_create(map, n, dt, dz, precision, device, &p);
+    if (st) return st;
+    st = ss_plan_propagate(p, field, z0, z1, stream);
+    // the tables are freed below: the launches that read them must be done
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && st == MPA_OK)
+        st = fail_status(MPA_EDEVICE, "hipStreamSynchronize failed");
+    ss_plan_destroy(p);
+    return st;
 }
 
 }  // extern "C"

@@ -67,7 +67,7 @@ int main() {
         c.set(q);
         EXPECT(mpa_plan_validate(&q, &map) == c.want);
         char buf[8];
-        EXPECT(mpa_last_error(buf, (int)sizeof buf) > 0 && std::strlen(buf) < sizeof buf);
+        EXPECT(mpa_last_error_detail(buf, (int)sizeof buf) > 0 && std::strlen(buf) < sizeof buf);
     }
     // maps
     mpa_map m = map;
@@ -125,7 +125,7 @@ int main() {
     EXPECT(mpa_propagate(nullptr, nullptr, 0.0, 1.0, nullptr) == MPA_EINVAL);
     EXPECT(mpa_check_field(nullptr, nullptr, nullptr) == MPA_EINVAL);
     EXPECT(mpa_picard_residuals(nullptr, nullptr, 0.0, nullptr, nullptr) == MPA_EINVAL);
-    EXPECT(ss_propagate(nullptr, nullptr, 0.0, 1.0, nullptr) == MPA_EINVAL);
+    EXPECT(ss_plan_propagate(nullptr, nullptr, 0.0, 1.0, nullptr) == MPA_EINVAL);
     ss_plan* sp = (ss_plan*)16;
     EXPECT(ss_plan_create(&map, 3000, 0.01, 1e-4, MPA_C64, 0, &sp) == MPA_EINVAL && sp == nullptr);
     EXPECT(ss_plan_create(&map, 1 << 18, 0.01, 3e-4, MPA_C64, 0, &sp) == MPA_EALIGN);
@@ -136,7 +136,7 @@ int main() {
     EXPECT(mpa_checkpoint_count(nullptr, 0.0, 1.0, &cnt) == MPA_EINVAL);
     for (int s = 0; s >= -8; --s) EXPECT(std::strncmp(mpa_status_string(s), "MPA_", 4) == 0);
     EXPECT(mpa_status_string(-99) != nullptr);
-    EXPECT(mpa_last_error(nullptr, 0) >= 0);
+    EXPECT(mpa_last_error_detail(nullptr, 0) >= 0);
     std::printf("%s (%d failures)\n", failures ? "FAILED" : "OK", failures);
     return failures ? 1 : 0;
 }

@@ -112,7 +112,7 @@ def test_error_message_and_status_strings():
     L = _lib()
     assert _validate(L=1e-3) == L.MPA_EHALO
     buf = C.create_string_buffer(256)
-    n = L.lib().mpa_last_error(buf, 256)
+    n = L.lib().mpa_last_error_detail(buf, 256)
     assert n > 0 and b"halo" in buf.value
     for s in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert L.lib().mpa_status_string(s).startswith(b"MPA_")
@@ -124,7 +124,7 @@ def test_null_arguments_rejected():
     assert h.mpa_plan_validate(None, None) == L.MPA_EINVAL
     assert h.mpa_step(None, None, C.c_double(0.0), None) == L.MPA_EINVAL
     assert h.mpa_propagate(None, None, C.c_double(0.0), C.c_double(1.0), None) == L.MPA_EINVAL
-    assert h.ss_propagate(None, None, C.c_double(0.0), C.c_double(1.0), None) == L.MPA_EINVAL
+    assert h.ss_plan_propagate(None, None, C.c_double(0.0), C.c_double(1.0), None) == L.MPA_EINVAL
     cnt = C.c_int64()
     assert h.mpa_checkpoint_count(None, 0.0, 1.0, C.byref(cnt)) == L.MPA_EINVAL
     assert h.mpa_batch_checkpoint_count(None, 0.0, 1.0, C.byref(cnt)) == L.MPA_EINVAL
@@ -133,6 +133,27 @@ def test_null_arguments_rejected():
     assert h.mpa_batch_propagate_checkpointed(None, None, 0.0, 1.0, None, None) == L.MPA_EINVAL
     assert h.mpa_check_field(None, None, None) == L.MPA_EINVAL
     assert h.mpa_picard_residuals(None, None, 0.0, None, None) == L.MPA_EINVAL
+
+
+def test_stateless_split_step_validates_on_the_host():
+    """ss_propagate without a plan checks its request before any device call."""
+    from workloads import WORKLOADS
+    L = _lib()
+    h = L.lib()
+    w = WORKLOADS["dm1ch_n4096_f64"]
+    m = L.MapStruct(w.dmmap)
+    fake = C.c_void_p(16)      # never dereferenced: every case fails before the device
+
+    def call(n=4096, dt=w.grid.dt, dz=0.05 / 8, prec=1, field=fake, z0=0.0, z1=1.0, mp=C.byref(m.s)):
+        return h.ss_propagate(mp, n, dt, dz, prec, field, z0, z1, None)
+    assert call(field=None) == L.MPA_EINVAL
+    assert call(mp=None) == L.MPA_EINVAL
+    assert call(n=3000) == L.MPA_EINVAL
+    assert call(dt=-1.0) == L.MPA_EINVAL
+    assert call(prec=7) == L.MPA_EINVAL
+    assert call(dz=0.3) == L.MPA_EALIGN            # does not divide the 0.5 spans
+    assert call(z0=0.001) == L.MPA_EALIGN
+    assert call(z0=1.0, z1=0.0) == L.MPA_EINVAL
     out = C.c_void_p(123)
     assert h.mpa_plan_create(None, None, 0, C.byref(out)) == L.MPA_EINVAL and out.value is None
     assert h.mpa_plan_destroy(None) == L.MPA_OK

@@ -41,7 +41,8 @@ def test_split_step_partial_runs():
     assert rel_l2(got, ref) < TOL_F64
 
 
-@pytest.mark.parametrize("n,prec", [(1 << 13, 1), (1 << 14, 0), (1 << 15, 1), (1 << 18, 0)])
+@pytest.mark.parametrize("n,prec", [(1 << 13, 1), (1 << 14, 0), (1 << 15, 1), (1 << 18, 0), (1 << 20, 1),
+                                    (1 << 22, 0)])
 def test_split_step_four_step_path(n, prec):
     """Windows above one workgroup: row/column kernels of the four-step FFT,
     across the span change at z = 0.5, against the oracle's Eq. 4."""
@@ -61,3 +62,18 @@ def test_split_step_four_step_path(n, prec):
     plan.close()
     ref = O.ss_propagate(a, dt, dmm, dz, z0, z1)
     assert rel_l2(got, ref) < (TOL_F64 if prec == 1 else TOL_F32)
+
+
+def test_stateless_split_step_equals_the_plan():
+    """ss_propagate (no plan) gives bitwise the field of ss_plan_propagate."""
+    import paper_1101_0086_amd as P
+    w = WORKLOADS["dm1ch_n4096_f64"]
+    a = w.field()
+    dz = 0.05 / 8
+    say("ss stateless")
+    plan = P.SSPlan(w.grid.n, w.grid.dt, w.dmmap, dz, 1)
+    x = to_dev(a, 1)
+    plan.propagate(x, 0.0, 1.0)
+    plan.close()
+    y = P.ss_propagate(to_dev(a, 1), w.grid.dt, w.dmmap, dz, 0.0, 1.0)
+    assert np.array_equal(to_host(x), to_host(y))
