@@ -23,8 +23,9 @@ Printed (one JSON line on stdout):
   cpu_baseline   the FP64 oracle on the host (blocked MPA, one thread, a
                  bounded sample), and the paper's own decomposition of a long
                  step over every host core
-  ...            the 8-channel 2^18-mode workload, batches, autotuner tables,
-                 gradients (extra keys)
+  ...            the single-channel FP64 2^12-mode workload, the 8-channel
+                 2^18-mode workload, batches, autotuner tables, gradients
+                 (extra keys)
 """
 from __future__ import annotations
 
@@ -124,14 +125,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip accuracy and split-step comparison")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the 2^18-mode workload, batches, autotuner tables and gradients")
+                    help="skip the 2^12- and 2^18-mode workloads, batches, autotuner tables and gradients")
     ap.add_argument("--grad-periods", type=int, default=20, help="map periods of the gradient measurement")
     ap.add_argument("--profile-pass", action="store_true",
                     help="for rocprofv3 --kernel-trace: 40 headline launches, 20 split-steps of each precision")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="for rocprofv3 --pmc: a 512 MiB copy (counter calibration), then 20 headline launches")
     ap.add_argument("--pmc-grad", action="store_true",
-                    help="for rocprofv3 --pmc: 20 reverse long steps of the 2^16-mode gradient workload")
+                    help="for rocprofv3: 20 reverse long steps of the 2^16-mode gradient workload, "
+                         "then 20 of a batch of 32 such fields")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this implementation runs on one GPU; --gpus must be 1 "
@@ -153,7 +155,18 @@ def main():
         pl.adjoint(ck, (2 * xg).contiguous(), 0.0, 20 * gs.L)
         torch.cuda.synchronize()
         pl.close()
-        print(json.dumps({"pmc_grad": True, "reverse_launches": 20}), flush=True)
+        # the same 20 reverse long steps for a batch of 32 such fields
+        import numpy as np
+        sig = np.random.default_rng(7).uniform(0.8, 1.2, 32).tolist()
+        bp = P.MPABatchPlan([g.grid.n] * 32, g.grid.dt, g.dmmap, gs.L, gs.M, gs.n_iter, gs.block, gs.halo,
+                            P.MPA_C64, gs.omega_band, sigma_scale=sig)
+        xb = torch.from_numpy(np.concatenate([g.field(seed=g.seed + i) for i in range(32)])).to(
+            device="cuda:0", dtype=torch.complex64)
+        ck = bp.propagate_checkpointed(xb, 0.0, 20 * gs.L)
+        bp.adjoint(ck, (2 * xb).contiguous(), 0.0, 20 * gs.L)
+        torch.cuda.synchronize()
+        bp.close()
+        print(json.dumps({"pmc_grad": True, "reverse_launches": 20, "batch_reverse_launches": 20}), flush=True)
         return
 
     w = WORKLOADS[HEADLINE]
@@ -245,6 +258,7 @@ def main():
     if not args.no_compare:
         out.update(compare(w, a0, torch, P, value))
     if not args.no_extra:
+        out["dm1ch_n4096_f64"] = c1_section(torch, P)
         out["wdm8_n262144"] = c2_section(torch, P)
         out["batched"] = batched(torch, P)
         out["autotune_wdm32"] = autotune_table(WORKLOADS[HEADLINE], torch, P, launches=20)
@@ -409,6 +423,57 @@ def c2_section(torch, P):
     return {"workload": w.name, "mpa": rows, "split_step_same_dz": ss,
             "reference": "FP64 split-step at dz = 3.9e-6; dz = 7.8e-6 differs from it by "
                          f"{err(r1):.1e} in band"}
+
+
+def c1_section(torch, P):
+    """The single-channel FP64 workload (2^12 modes, one window, L = 0.05,
+    M = 16, n_iter = 3) over its 10 map periods: MPA time and error against
+    an FP64 split-step at dz/64 (its distance to dz/128 reported), the FP64
+    split-step swept over dz, and its time at the MPA's error by
+    interpolation."""
+    import numpy as np
+    from workloads import WORKLOADS
+    w = WORKLOADS["dm1ch_n4096_f64"]
+    s = w.mpa
+    n, dt = w.grid.n, w.grid.dt
+    z1 = float(w.periods)
+    dz = s.L / s.M
+    a0 = w.field()
+
+    def run_ss(h):
+        pl = P.SSPlan(n, dt, w.dmmap, h, P.MPA_C128)
+        y = torch.from_numpy(a0).to(device="cuda:0", dtype=torch.complex128)
+        pl.propagate(y, 0.0, 2 * s.L)                 # warm-up
+        y = torch.from_numpy(a0).to(device="cuda:0", dtype=torch.complex128)
+        el, _ = _timed(torch, lambda: pl.propagate(y, 0.0, z1))
+        pl.close()
+        return y.cpu().numpy(), el
+
+    r128, _ = run_ss(dz / 128)
+    ref, _ = run_ss(dz / 64)
+
+    def err(a):
+        return float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
+
+    pl = _plan(P, w, prec=P.MPA_C128)
+    y = torch.from_numpy(a0).to(device="cuda:0", dtype=torch.complex128)
+    pl.propagate(y, 0.0, 2 * s.L)
+    y = torch.from_numpy(a0).to(device="cuda:0", dtype=torch.complex128)
+    el, _ = _timed(torch, lambda: pl.propagate(y, 0.0, z1))
+    pl.close()
+    e_mpa = err(y.cpu().numpy())
+    mpa = {"rel_l2": e_mpa, "seconds": el, "mode_steps_per_s": n * z1 / dz / el}
+    sweep = []
+    for k in (1, 2, 4, 8):
+        a, t = run_ss(dz / k)
+        sweep.append({"dz": dz / k, "rel_l2": err(a), "seconds": t, "mode_steps_per_s": n * z1 * k / dz / t})
+    t_ss = _interp_time([(r["rel_l2"], r["seconds"]) for r in sweep], e_mpa)
+    log(f"2^12 FP64: MPA {mpa['mode_steps_per_s']:.3e} mode-steps/s at {e_mpa:.3e}")
+    return {"workload": w.name, "precision": "FP64", "distance": z1, "L": s.L, "M": s.M, "n_iter": s.n_iter,
+            "mpa": mpa, "split_step_f64": sweep,
+            "split_step_seconds_at_mpa_error": t_ss,
+            "time_ratio_ss_over_mpa": (t_ss / el) if t_ss else None,
+            "reference": f"FP64 split-step at dz/64; the dz/128 run differs from it by {err(r128):.1e}"}
 
 
 # ---- batches, autotuner, gradients ---------------------------------------------------

@@ -21,7 +21,12 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
   limit); n -> infinity equals the sequential implicit trapezoid; SPM with
   loss; soliton; the analytic MPA/SS error ratio 2 of Eqs. 5 and 7.
 * ``mpa_blocked_long_step``: block = N reproduces the full window bitwise;
-  shift equivariance; sigma = 0 blocked error below the halo bound.
+  shift equivariance; sigma = 0 blocked error below the halo bound; with
+  windows shifted against their cores, a one-sided group delay that the
+  centred windows cannot hold is held by the shifted ones.
+* ``parallel.mpa_long_step_parallel`` (the paper's decomposition of a long
+  step over z-nodes and harmonic ranges, for the CPU baseline): equals
+  ``mpa_long_step`` to rounding.
 * ``ss_long_step`` / ``ss_propagate``: linear closed forms; exact SPM
   kick; second order; unitarity; time reversibility.
 * ``ss_long_step_gain`` (split-step with distributed gain): the exact linear
