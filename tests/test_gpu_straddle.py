@@ -63,7 +63,7 @@ def test_reverse_pass_refuses_boundary_crossing_plans():
     ck = plan.propagate_checkpointed(x, 0.0, 1.0)
     with pytest.raises(P.MPAError) as e:
         plan.adjoint(ck, torch.zeros_like(x), 0.0, 1.0)
-    assert e.value.status == -6
+    assert e.value.status == P._lib.MPA_EUNSUPPORTED
 
 
 def test_batch_steps_across_boundaries():
