@@ -234,6 +234,105 @@ __device__ __forceinline__ void block_fft_db(cx<T> (&v)[R], cx<T>*& buf0, cx<T>*
     }
 }
 
+// ---- variant with every twiddle loaded at the start -------------------------
+// For transforms outside the node loop (the FP64 carry transforms): the
+// twiddles of all passes are loaded when the call begins, so their latency is
+// paid once per transform instead of once per pass (COLD) and they do not
+// stay in registers after it (as they do without COLD).  Passes after the
+// first are radix 8 with one butterfly per thread, so each takes 7 twiddles.
+// The arithmetic is that of block_fft, bit for bit; DBUF selects the
+// exchange of block_fft_db (two buffers) or of block_fft (one).
+constexpr int first_radix(int B) { return ilog2(B) % 3 == 0 ? 8 : (1 << (ilog2(B) % 3)); }
+
+constexpr int n_passes(int B) {
+    int n = 0;
+    for (int p = 1; p < B; p *= (n == 0 ? first_radix(B) : 8), ++n) {
+    }
+    return n;
+}
+
+// span of pass s (s = 0: the first)
+constexpr int pass_span(int B, int s) { return s == 0 ? 1 : first_radix(B) * (1 << (3 * (s - 1))); }
+
+template <typename T, int B, int S, int NP>
+__device__ __forceinline__ void load_twiddles(cx<T> (&w)[NP - 1][7], const cx<T>* __restrict__ tw, int tid) {
+    if constexpr (S < NP) {
+        constexpr int p = pass_span(B, S);
+        constexpr int stride = B / (p * 8);
+        const int k = tid & (p - 1);
+#pragma unroll
+        for (int q = 1; q < 8; ++q) w[S - 1][q - 1] = tw[q * k * stride];
+        load_twiddles<T, B, S + 1, NP>(w, tw, tid);
+    }
+}
+
+template <typename T, int B, int R, int SIGN, int S, int NP, bool DBUF>
+__device__ __forceinline__ void passes_warm(cx<T> (&v)[R], cx<T>* buf0, cx<T>* buf1, const cx<T> (&w)[NP - 1][7],
+                                            int tid) {
+    constexpr int NT = B / R;
+    constexpr int p = pass_span(B, S);
+    constexpr int r = S == 0 ? first_radix(B) : 8;
+    constexpr int NB = R / r;
+    constexpr bool first = (S == 0), last = (S == NP - 1);
+    // exchange buffers: alternating (DBUF, pass S reads buf[(S - 1) % 2] and
+    // writes buf[S % 2]) or one
+    cx<T>* in = DBUF ? ((S % 2) ? buf0 : buf1) : buf0;
+    cx<T>* out = DBUF ? ((S % 2) ? buf1 : buf0) : buf0;
+    if constexpr (!first) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < R; ++m) v[m] = in[lds_slot(tid + NT * m)];
+        if constexpr (!DBUF) __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int i = tid + u * NT;
+        const int k = i & (p - 1);
+        cx<T> x[r];
+#pragma unroll
+        for (int q = 0; q < r; ++q) x[q] = v[u + q * NB];
+        if constexpr (!first) {
+#pragma unroll
+            for (int q = 1; q < r; ++q) {
+                cx<T> t = w[S - 1][q - 1];
+                if constexpr (SIGN < 0) t.im = -t.im;
+                x[q] = cmul(x[q], t);
+            }
+        }
+        dft<SIGN, r>(x);
+        if constexpr (!last) {
+            const int base = (i - k) * r + k;
+#pragma unroll
+            for (int q = 0; q < r; ++q) out[lds_slot(base + q * p)] = x[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < r; ++q) v[u + q * NB] = x[q];
+        }
+    }
+    if constexpr (!last) passes_warm<T, B, R, SIGN, S + 1, NP, DBUF>(v, buf0, buf1, w, tid);
+}
+
+// B-point transform as block_fft (DBUF = false: buf1 unused) or block_fft_db
+// (DBUF: buf0 and buf1 swapped on return when the exchange count is odd),
+// with the twiddles loaded at the start.
+template <typename T, int B, int R, int SIGN, bool DBUF>
+__device__ __forceinline__ void block_fft_warm(cx<T> (&v)[R], cx<T>*& buf0, cx<T>*& buf1,
+                                               const cx<T>* __restrict__ tw, int tid) {
+    static_assert((B & (B - 1)) == 0 && B >= 64 && R == 8, "power-of-two block, 8 points per thread");
+    constexpr int NP = n_passes(B);
+    static_assert(NP >= 2, "at least two passes");
+    int t = tid;
+    asm volatile("" : "+v"(t));      // the twiddle loads are made inside this call
+    cx<T> w[NP - 1][7];
+    load_twiddles<T, B, 1, NP>(w, tw, t);
+    passes_warm<T, B, R, SIGN, 0, NP, DBUF>(v, buf0, buf1, w, tid);
+    if constexpr (DBUF && (NP - 1) % 2 == 1) {
+        cx<T>* s = buf0;
+        buf0 = buf1;
+        buf1 = s;
+    }
+}
+
 // B-point transform of the workgroup's registers (see the file comment).
 // `tw` holds exp(+2 pi i j / B), j = 0..B-1.  Must be called by every
 // thread of the workgroup (it contains barriers).  COLD: the twiddle index

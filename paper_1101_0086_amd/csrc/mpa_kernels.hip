@@ -65,8 +65,8 @@ mpa_block_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long lon
                  const T* __restrict__ node_scale, const cx<T>* __restrict__ tw,
                  const cx<double>* __restrict__ tw64, const double* __restrict__ taper, int M, T sigma,
                  double out_scale) {
-    // one LDS exchange buffer, sized for FP64 and shared by both precisions
-    __shared__ cx<double> lds64[lds_elems<B>()];
+    // two FP64 exchange buffers (the node transforms use the first)
+    __shared__ cx<double> lds64[2 * lds_elems<B>()];
     const long long c0 = (long long)blockIdx.x * core;
     const int thread = threadIdx.x;
 #include "long_step_body.inc"
@@ -84,7 +84,7 @@ mpa_batch_kernel(const cx<T>* __restrict__ fin, cx<T>* __restrict__ fout,
                  const T* __restrict__ node_scale, const cx<T>* __restrict__ tw,
                  const cx<double>* __restrict__ tw64, const double* __restrict__ taper, int M,
                  double sigma_span, double out_scale) {
-    __shared__ cx<double> lds64[lds_elems<B>()];
+    __shared__ cx<double> lds64[2 * lds_elems<B>()];
     for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
         const int2 it = items[w];
         const cx<T>* __restrict__ in = fin + offset[it.x];
