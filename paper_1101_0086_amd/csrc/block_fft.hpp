@@ -234,14 +234,19 @@ __device__ __forceinline__ void block_fft_db(cx<T> (&v)[R], cx<T>*& buf0, cx<T>*
     }
 }
 
-// ---- variant with every twiddle loaded at the start -------------------------
-// For transforms outside the node loop (the FP64 carry transforms): the
-// twiddles of all passes are loaded when the call begins, so their latency is
-// paid once per transform instead of once per pass (COLD) and they do not
-// stay in registers after it (as they do without COLD).  Passes after the
-// first are radix 8 with one butterfly per thread, so each takes 7 twiddles.
-// The arithmetic is that of block_fft, bit for bit; DBUF selects the
-// exchange of block_fft_db (two buffers) or of block_fft (one).
+// ---- variant with the twiddles formed from one load per pass ------------------
+// For transforms outside the node loop (the FP64 carry transforms).  Passes
+// after the first are radix 8 with one butterfly per thread, which needs
+// w^k, w^{2k}, ..., w^{7k} (w = exp(2 pi i / (8 p))): each pass loads w^k
+// alone and forms the other six by complex products (w^2 = w w, w^3 = w^2 w,
+// w^4 = w^2 w^2, w^5 = w^4 w, w^6 = w^4 w^2, w^7 = w^4 w^3; at most four
+// roundings deep, a few units in the last place): seven table loads per
+// pass, gathered through the vector memory path, cost more than the six
+// products.  AHEAD: the twiddles of every pass are formed when the call
+// begins (their latency paid once); else at the start of each pass (fewer
+// registers).  Either way they do not stay in registers after the call, and
+// the arithmetic is the same.  DBUF selects the exchange of block_fft_db
+// (two buffers) or of block_fft (one).
 constexpr int first_radix(int B) { return ilog2(B) % 3 == 0 ? 8 : (1 << (ilog2(B) % 3)); }
 
 constexpr int n_passes(int B) {
@@ -254,21 +259,36 @@ constexpr int n_passes(int B) {
 // span of pass s (s = 0: the first)
 constexpr int pass_span(int B, int s) { return s == 0 ? 1 : first_radix(B) * (1 << (3 * (s - 1))); }
 
+// w^{q k}, q = 1..7, of pass S (S >= 1) for this thread
+template <typename T, int B, int S>
+__device__ __forceinline__ void pass_twiddles(cx<T> (&w)[7], const cx<T>* __restrict__ tw, int tid) {
+    constexpr int p = pass_span(B, S);
+    constexpr int stride = B / (p * 8);
+    const int k = tid & (p - 1);
+    const cx<T> w1 = tw[k * stride];
+    const cx<T> w2 = cmul(w1, w1);
+    const cx<T> w3 = cmul(w2, w1);
+    const cx<T> w4 = cmul(w2, w2);
+    w[0] = w1;
+    w[1] = w2;
+    w[2] = w3;
+    w[3] = w4;
+    w[4] = cmul(w4, w1);
+    w[5] = cmul(w4, w2);
+    w[6] = cmul(w4, w3);
+}
+
 template <typename T, int B, int S, int NP>
-__device__ __forceinline__ void load_twiddles(cx<T> (&w)[NP - 1][7], const cx<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void all_twiddles(cx<T> (&w)[NP - 1][7], const cx<T>* __restrict__ tw, int tid) {
     if constexpr (S < NP) {
-        constexpr int p = pass_span(B, S);
-        constexpr int stride = B / (p * 8);
-        const int k = tid & (p - 1);
-#pragma unroll
-        for (int q = 1; q < 8; ++q) w[S - 1][q - 1] = tw[q * k * stride];
-        load_twiddles<T, B, S + 1, NP>(w, tw, tid);
+        pass_twiddles<T, B, S>(w[S - 1], tw, tid);
+        all_twiddles<T, B, S + 1, NP>(w, tw, tid);
     }
 }
 
-template <typename T, int B, int R, int SIGN, int S, int NP, bool DBUF>
-__device__ __forceinline__ void passes_warm(cx<T> (&v)[R], cx<T>* buf0, cx<T>* buf1, const cx<T> (&w)[NP - 1][7],
-                                            int tid) {
+template <typename T, int B, int R, int SIGN, int S, int NP, bool DBUF, bool AHEAD>
+__device__ __forceinline__ void passes_warm(cx<T> (&v)[R], cx<T>* buf0, cx<T>* buf1, const cx<T> (&wall)[NP - 1][7],
+                                            const cx<T>* __restrict__ tw, int tid) {
     constexpr int NT = B / R;
     constexpr int p = pass_span(B, S);
     constexpr int r = S == 0 ? first_radix(B) : 8;
@@ -284,6 +304,17 @@ __device__ __forceinline__ void passes_warm(cx<T> (&v)[R], cx<T>* buf0, cx<T>* b
         for (int m = 0; m < R; ++m) v[m] = in[lds_slot(tid + NT * m)];
         if constexpr (!DBUF) __syncthreads();
     }
+    cx<T> wp[7];
+    if constexpr (!first) {
+        if constexpr (AHEAD) {
+#pragma unroll
+            for (int q = 0; q < 7; ++q) wp[q] = wall[S - 1][q];
+        } else {
+            int t = tid;
+            asm volatile("" : "+v"(t));      // formed here, not earlier
+            pass_twiddles<T, B, S>(wp, tw, t);
+        }
+    }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         const int i = tid + u * NT;
@@ -294,7 +325,7 @@ __device__ __forceinline__ void passes_warm(cx<T> (&v)[R], cx<T>* buf0, cx<T>* b
         if constexpr (!first) {
 #pragma unroll
             for (int q = 1; q < r; ++q) {
-                cx<T> t = w[S - 1][q - 1];
+                cx<T> t = wp[q - 1];
                 if constexpr (SIGN < 0) t.im = -t.im;
                 x[q] = cmul(x[q], t);
             }
@@ -309,23 +340,25 @@ __device__ __forceinline__ void passes_warm(cx<T> (&v)[R], cx<T>* buf0, cx<T>* b
             for (int q = 0; q < r; ++q) v[u + q * NB] = x[q];
         }
     }
-    if constexpr (!last) passes_warm<T, B, R, SIGN, S + 1, NP, DBUF>(v, buf0, buf1, w, tid);
+    if constexpr (!last) passes_warm<T, B, R, SIGN, S + 1, NP, DBUF, AHEAD>(v, buf0, buf1, wall, tw, tid);
 }
 
 // B-point transform as block_fft (DBUF = false: buf1 unused) or block_fft_db
 // (DBUF: buf0 and buf1 swapped on return when the exchange count is odd),
-// with the twiddles loaded at the start.
-template <typename T, int B, int R, int SIGN, bool DBUF>
+// with the twiddles formed as above.
+template <typename T, int B, int R, int SIGN, bool DBUF, bool AHEAD>
 __device__ __forceinline__ void block_fft_warm(cx<T> (&v)[R], cx<T>*& buf0, cx<T>*& buf1,
                                                const cx<T>* __restrict__ tw, int tid) {
     static_assert((B & (B - 1)) == 0 && B >= 64 && R == 8, "power-of-two block, 8 points per thread");
     constexpr int NP = n_passes(B);
     static_assert(NP >= 2, "at least two passes");
-    int t = tid;
-    asm volatile("" : "+v"(t));      // the twiddle loads are made inside this call
     cx<T> w[NP - 1][7];
-    load_twiddles<T, B, 1, NP>(w, tw, t);
-    passes_warm<T, B, R, SIGN, 0, NP, DBUF>(v, buf0, buf1, w, tid);
+    if constexpr (AHEAD) {
+        int t = tid;
+        asm volatile("" : "+v"(t));      // formed inside this call
+        all_twiddles<T, B, 1, NP>(w, tw, t);
+    }
+    passes_warm<T, B, R, SIGN, 0, NP, DBUF, AHEAD>(v, buf0, buf1, w, tw, tid);
     if constexpr (DBUF && (NP - 1) % 2 == 1) {
         cx<T>* s = buf0;
         buf0 = buf1;

@@ -68,7 +68,9 @@ np_init_kernel(const cx<T>* __restrict__ in, cx<double>* __restrict__ psi0_buf, 
         psi0[m] = a;
         cur[m] = narrow<T>(scale(a, norm2(a)));
     }
-    block_fft<double, B, R, +1>(psi0, lds64, tw64, tid);
+    cx<double>* e0 = lds64;
+    cx<double>* e1 = lds64;
+    block_fft_warm<double, B, R, +1, false, true>(psi0, e0, e1, tw64, tid);   // as the fused kernel
     block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
     const T d0 = sigma * node_scale[1];
     const size_t base = (size_t)blockIdx.x * B;
@@ -156,7 +158,9 @@ np_final_kernel(const cx<double>* __restrict__ psi0_buf, const cx<T>* __restrict
         // step 7: A(z0 + L) = e^{Gamma_M} F^-1[psi_M e^{i beta_M}] (times the roll-off and gain)
         v[m] = scale(cmul(psiM, phase_last[t]), out_scale);
     }
-    block_fft<double, B, R, -1>(v, lds64, tw64, tid);
+    cx<double>* e0 = lds64;
+    cx<double>* e1 = lds64;
+    block_fft_warm<double, B, R, -1, false, true>(v, e0, e1, tw64, tid);      // as the fused kernel
     const long long c0 = (long long)b * core;
     const long long rest = n - c0;
     const int clen = rest < core ? (int)rest : core;
