@@ -429,8 +429,8 @@ def c1_section(torch, P):
     """The single-channel FP64 workload (2^12 modes, one window, L = 0.05,
     M = 16, n_iter = 3) over its 10 map periods: MPA time and error against
     an FP64 split-step at dz/64 (its distance to dz/128 reported), the FP64
-    split-step swept over dz, and its time at the MPA's error by
-    interpolation."""
+    split-step swept over 4, 2, 1 and 1/2 times the MPA's dz, and its time at
+    the MPA's error by interpolation."""
     import numpy as np
     from workloads import WORKLOADS
     w = WORKLOADS["dm1ch_n4096_f64"]
@@ -464,7 +464,7 @@ def c1_section(torch, P):
     e_mpa = err(y.cpu().numpy())
     mpa = {"rel_l2": e_mpa, "seconds": el, "mode_steps_per_s": n * z1 / dz / el}
     sweep = []
-    for k in (1, 2, 4, 8):
+    for k in (0.25, 0.5, 1, 2):             # dz 4, 2, 1 and 1/2 times the MPA's
         a, t = run_ss(dz / k)
         sweep.append({"dz": dz / k, "rel_l2": err(a), "seconds": t, "mode_steps_per_s": n * z1 * k / dz / t})
     t_ss = _interp_time([(r["rel_l2"], r["seconds"]) for r in sweep], e_mpa)
