@@ -24,9 +24,25 @@ namespace mpa {
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
-// LDS slot of element j: one pad slot every 8 elements breaks the
-// power-of-two write strides of the early passes across banks.
-__device__ __forceinline__ int lds_slot(int j) { return j + (j >> 3); }
+// LDS slot of element j of a transform's exchange buffer: a permutation of
+// j inside aligned groups, so that the lanes the LDS serves together (16
+// lanes of 8-byte FP32 elements, 8 lanes of 16-byte FP64 elements, over 32
+// banks of 4 bytes) meet distinct banks both in the contiguous reads and in
+// the strided writes of the passes.  FP32: j ^ h(j >> 4), the low 3 bits of
+// h those of the group index (separating the stride-8 writes of the first
+// pass) and bit 3 of h its bit 2 (separating neighbouring 64-element runs
+// of the second pass); FP64: j ^ ((j >> 3) & 7).  (A pad slot every 8
+// elements, the simpler layout, leaves a 2-way conflict in most FP32
+// accesses of 16 lanes.)
+template <typename T>
+__device__ __forceinline__ int lds_slot(int j) {
+    if constexpr (sizeof(T) == 4) {
+        const int t = j >> 4;
+        return j ^ ((t & 7) | (((t >> 2) & 1) << 3));
+    } else {
+        return j ^ ((j >> 3) & 7);
+    }
+}
 
 template <int B>
 constexpr int lds_elems() { return B + B / 8; }
@@ -98,7 +114,7 @@ __device__ __forceinline__ void fft_pass(cx<T> (&v)[R], cx<T>* lds,
     if constexpr (FROM_LDS) {
         __syncthreads();        // the previous pass's writes are visible
 #pragma unroll
-        for (int m = 0; m < R; ++m) v[m] = lds[lds_slot(tid + NT * m)];
+        for (int m = 0; m < R; ++m) v[m] = lds[lds_slot<T>(tid + NT * m)];
         __syncthreads();        // every read done before this pass overwrites
     }
 #pragma unroll
@@ -122,7 +138,7 @@ __device__ __forceinline__ void fft_pass(cx<T> (&v)[R], cx<T>* lds,
         if constexpr (TO_LDS) {
             const int base = (i - k) * r + k;
 #pragma unroll
-            for (int q = 0; q < r; ++q) lds[lds_slot(base + q * p)] = x[q];
+            for (int q = 0; q < r; ++q) lds[lds_slot<T>(base + q * p)] = x[q];
         } else {
 #pragma unroll
             for (int q = 0; q < r; ++q) v[u + q * NB] = x[q];
@@ -168,7 +184,7 @@ __device__ __forceinline__ void fft_pass_db(cx<T> (&v)[R], const cx<T>* lds_in, 
     if constexpr (FROM_LDS) {
         __syncthreads();        // the previous pass's writes are visible
 #pragma unroll
-        for (int m = 0; m < R; ++m) v[m] = lds_in[lds_slot(tid + NT * m)];
+        for (int m = 0; m < R; ++m) v[m] = lds_in[lds_slot<T>(tid + NT * m)];
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
@@ -191,7 +207,7 @@ __device__ __forceinline__ void fft_pass_db(cx<T> (&v)[R], const cx<T>* lds_in, 
         if constexpr (TO_LDS) {
             const int base = (i - k) * r + k;
 #pragma unroll
-            for (int q = 0; q < r; ++q) lds_out[lds_slot(base + q * p)] = x[q];
+            for (int q = 0; q < r; ++q) lds_out[lds_slot<T>(base + q * p)] = x[q];
         } else {
 #pragma unroll
             for (int q = 0; q < r; ++q) v[u + q * NB] = x[q];
@@ -301,7 +317,7 @@ __device__ __forceinline__ void passes_warm(cx<T> (&v)[R], cx<T>* buf0, cx<T>* b
     if constexpr (!first) {
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < R; ++m) v[m] = in[lds_slot(tid + NT * m)];
+        for (int m = 0; m < R; ++m) v[m] = in[lds_slot<T>(tid + NT * m)];
         if constexpr (!DBUF) __syncthreads();
     }
     cx<T> wp[7];
@@ -334,7 +350,7 @@ __device__ __forceinline__ void passes_warm(cx<T> (&v)[R], cx<T>* buf0, cx<T>* b
         if constexpr (!last) {
             const int base = (i - k) * r + k;
 #pragma unroll
-            for (int q = 0; q < r; ++q) out[lds_slot(base + q * p)] = x[q];
+            for (int q = 0; q < r; ++q) out[lds_slot<T>(base + q * p)] = x[q];
         } else {
 #pragma unroll
             for (int q = 0; q < r; ++q) v[u + q * NB] = x[q];

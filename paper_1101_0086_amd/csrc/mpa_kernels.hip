@@ -58,8 +58,11 @@ struct StepTables {
 };
 
 // One field: one workgroup per block.
+// Both kernels are held to 256 registers per lane (two waves per SIMD): at
+// B <= 2048 a workgroup has at most one wave per SIMD, and the compiler would
+// otherwise take up to 512 and keep one workgroup per CU.
 template <typename T, int B, int NIT>
-__global__ void __launch_bounds__(B / PTS)
+__global__ void __launch_bounds__(B / PTS) __attribute__((amdgpu_waves_per_eu(2)))
 mpa_block_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long long n, int core,
                  int lead, const cx<T>* __restrict__ phase, const cx<double>* __restrict__ phase_last,
                  const T* __restrict__ node_scale, const cx<T>* __restrict__ tw,
@@ -76,7 +79,7 @@ mpa_block_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, long lon
 // workgroups walks the static list of (instance, block) work items; every
 // workgroup leaves the loop once the list is exhausted.
 template <typename T, int B, int NIT>
-__global__ void __launch_bounds__(B / PTS)
+__global__ void __launch_bounds__(B / PTS) __attribute__((amdgpu_waves_per_eu(2)))
 mpa_batch_kernel(const cx<T>* __restrict__ fin, cx<T>* __restrict__ fout,
                  const int2* __restrict__ items, int n_items, const long long* __restrict__ offset,
                  const long long* __restrict__ len, const double* __restrict__ sigma_scale, int core,
