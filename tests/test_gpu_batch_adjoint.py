@@ -84,6 +84,42 @@ def test_batch_adjoint_equals_single_plans(prec, store_steps, gain):
     assert err < 1e-12, (err, pg, ref_p)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_reverse_kernel_forms_agree(prec):
+    """The reverse kernel runs with its node transforms' twiddles in registers
+    when a launch has no more work items than CUs, and loads them in each pass
+    otherwise: the arithmetic is the same.  A batch of 40 fields of 11 blocks
+    (440 items, more than the CUs of any current device: per-pass form) gives
+    bitwise the field gradients of the per-field plans (11 items each:
+    register form)."""
+    import paper_1101_0086_amd as P
+    ns = [16384] * 40
+    scales = [1.0] * 40
+    block = 2048
+    fields, g_out, halo, L = _case(ns, 23, block)
+    dmm = dm_map(beta3=0.1)
+    z0, z1 = 0.0, 2 * L
+    say("reverse kernel forms", prec)
+    bp = P.MPABatchPlan(ns, DT, dmm, L, 2, 2, block, halo, prec, BAND, sigma_scale=scales)
+    assert bp.info()["work_items"] == 440
+    x = to_dev(np.concatenate(fields), prec)
+    ck = bp.propagate_checkpointed(x, z0, z1)
+    g = to_dev(np.concatenate(g_out), prec)
+    pg = bp.adjoint(ck, g, z0, z1).cpu().numpy()
+    got_g = [to_host(v) for v in bp.split(g)]
+    bp.close()
+    ref_p = np.zeros((3, 2))
+    for i in (0, 17, 39):
+        p = P.MPAPlan(ns[i], DT, dmm, L, 2, 2, block, halo, prec, BAND)
+        y = to_dev(fields[i], prec)
+        c1 = p.propagate_checkpointed(y, z0, z1)
+        h = to_dev(g_out[i], prec)
+        p.adjoint(c1, h, z0, z1)
+        p.close()
+        assert np.array_equal(to_host(h), got_g[i]), i
+    assert np.all(np.isfinite(pg))
+
+
 def test_batch_adjoint_fp64_matches_oracle():
     import paper_1101_0086_amd as P
     ns = [4096, 2048, 8192]
