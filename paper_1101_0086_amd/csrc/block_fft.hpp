@@ -28,17 +28,18 @@ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 // j inside aligned groups, so that the lanes the LDS serves together (16
 // lanes of 8-byte FP32 elements, 8 lanes of 16-byte FP64 elements, over 32
 // banks of 4 bytes) meet distinct banks both in the contiguous reads and in
-// the strided writes of the passes.  FP32: j ^ h(j >> 4), the low 3 bits of
-// h those of the group index (separating the stride-8 writes of the first
-// pass) and bit 3 of h its bit 2 (separating neighbouring 64-element runs
-// of the second pass); FP64: j ^ ((j >> 3) & 7).  (A pad slot every 8
-// elements, the simpler layout, leaves a 2-way conflict in most FP32
-// accesses of 16 lanes.)
+// the strided writes of the passes, for B = 512 .. 4096.  FP32:
+// j ^ h(t), t = j >> 4, with h's bits (t0, t0 ^ t1, t1 ^ t2, t2): its low
+// bits separate the stride-8, -4 and -2 writes of a radix-8, -4 or -2 first
+// pass, its high bits the 64-, 32- and 16-element runs of the pass after it.
+// FP64: j ^ ((j >> 3) & 7).  (A pad slot every 8 elements, the simpler
+// layout, leaves a 2-way conflict in most FP32 accesses of 16 lanes.)
 template <typename T>
 __device__ __forceinline__ int lds_slot(int j) {
     if constexpr (sizeof(T) == 4) {
         const int t = j >> 4;
-        return j ^ ((t & 7) | (((t >> 2) & 1) << 3));
+        const int h = (t & 1) | ((t ^ (t << 1)) & 6) | ((t << 1) & 8);
+        return j ^ h;
     } else {
         return j ^ ((j >> 3) & 7);
     }
