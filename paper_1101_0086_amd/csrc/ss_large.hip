@@ -61,8 +61,12 @@ template <typename ST>
 __device__ __forceinline__ cx<ST> store_n(cx<double> x) { return {ST(x.re), ST(x.im)}; }
 
 // TR rows of N2 points per workgroup; thread layout tid = r NT2 + t.
+// Rows of 4096 points and columns of 1024 (the 2^22-mode shape) are held to
+// 128 registers per lane (four waves per SIMD: two workgroups per CU instead
+// of one, a few registers spilled): 81.7 against 87.5 us per split-step at
+// 2^22 modes; the smaller shapes ran slower so (14.7 against 13.9 us at 2^18).
 template <typename ST, int N2, int TR>
-__global__ void __launch_bounds__(TR * N2 / SL_PTS)
+__global__ void __launch_bounds__(TR * N2 / SL_PTS) __attribute__((amdgpu_waves_per_eu(N2 >= 4096 ? 4 : 1)))
 ss_rows_kernel(cx<ST>* __restrict__ y, int n1, const cx<double>* __restrict__ tw2,
                const cx<double>* __restrict__ twl, const cx<double>* __restrict__ twh, int split,
                const cx<double>* __restrict__ phase, double scl) {
@@ -95,7 +99,7 @@ ss_rows_kernel(cx<ST>* __restrict__ y, int n1, const cx<double>* __restrict__ tw
 // TC columns of N1 points per workgroup; thread layout tid = t TC + c so that
 // consecutive lanes read consecutive columns of one row.
 template <typename ST, int N1, int TC, int MODE>
-__global__ void __launch_bounds__(TC * N1 / SL_PTS)
+__global__ void __launch_bounds__(TC * N1 / SL_PTS) __attribute__((amdgpu_waves_per_eu(N1 >= 1024 ? 4 : 1)))
 ss_cols_kernel(cx<ST>* __restrict__ y, int n2, const cx<double>* __restrict__ tw1,
                const cx<double>* __restrict__ twl, const cx<double>* __restrict__ twh, int split, double sdz) {
     constexpr int R = SL_PTS, NT = N1 / R;
