@@ -427,10 +427,13 @@ def c2_section(torch, P):
 
 def c1_section(torch, P):
     """The single-channel FP64 workload (2^12 modes, one window, L = 0.05,
-    M = 16, n_iter = 3) over its 10 map periods: MPA time and error against
-    an FP64 split-step at dz/64 (its distance to dz/128 reported), the FP64
-    split-step swept over 4, 2, 1 and 1/2 times the MPA's dz, and its time at
-    the MPA's error by interpolation."""
+    M = 16, n_iter = 3) over its 10 map periods: MPA time and error, in the
+    fused (wavefront) schedule and in the paper's node-parallel schedule (the
+    sixteen nodes of a sweep in workgroups of their own: one window leaves
+    the fused kernel a single workgroup), against an FP64 split-step at dz/64
+    (its distance to dz/128 reported), the FP64 split-step swept over 4, 2, 1
+    and 1/2 times the MPA's dz, and its time at the MPA's error by
+    interpolation."""
     import numpy as np
     from workloads import WORKLOADS
     w = WORKLOADS["dm1ch_n4096_f64"]
@@ -455,24 +458,27 @@ def c1_section(torch, P):
     def err(a):
         return float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
 
-    pl = _plan(P, w, prec=P.MPA_C128)
-    y = torch.from_numpy(a0).to(device="cuda:0", dtype=torch.complex128)
-    pl.propagate(y, 0.0, 2 * s.L)
-    y = torch.from_numpy(a0).to(device="cuda:0", dtype=torch.complex128)
-    el, _ = _timed(torch, lambda: pl.propagate(y, 0.0, z1))
-    pl.close()
-    e_mpa = err(y.cpu().numpy())
-    mpa = {"rel_l2": e_mpa, "seconds": el, "mode_steps_per_s": n * z1 / dz / el}
+    mpa = {}
+    for name, sched in (("wavefront", P.MPA_WAVEFRONT), ("node_parallel", P.MPA_NODE_PARALLEL)):
+        pl = P.MPAPlan(n, w.grid.dt, w.dmmap, s.L, s.M, s.n_iter, 0, 0, P.MPA_C128, s.omega_band, schedule=sched)
+        y = torch.from_numpy(a0).to(device="cuda:0", dtype=torch.complex128)
+        pl.propagate(y, 0.0, 2 * s.L)
+        y = torch.from_numpy(a0).to(device="cuda:0", dtype=torch.complex128)
+        el, _ = _timed(torch, lambda: pl.propagate(y, 0.0, z1))
+        pl.close()
+        mpa[name] = {"rel_l2": err(y.cpu().numpy()), "seconds": el, "mode_steps_per_s": n * z1 / dz / el}
     sweep = []
     for k in (0.25, 0.5, 1, 2):             # dz 4, 2, 1 and 1/2 times the MPA's
         a, t = run_ss(dz / k)
         sweep.append({"dz": dz / k, "rel_l2": err(a), "seconds": t, "mode_steps_per_s": n * z1 * k / dz / t})
-    t_ss = _interp_time([(r["rel_l2"], r["seconds"]) for r in sweep], e_mpa)
-    log(f"2^12 FP64: MPA {mpa['mode_steps_per_s']:.3e} mode-steps/s at {e_mpa:.3e}")
+    for name, r in mpa.items():
+        t_ss = _interp_time([(q["rel_l2"], q["seconds"]) for q in sweep], r["rel_l2"])
+        r["split_step_seconds_at_mpa_error"] = t_ss
+        r["time_ratio_ss_over_mpa"] = (t_ss / r["seconds"]) if t_ss else None
+        log(f"2^12 FP64 MPA ({name}): {r['mode_steps_per_s']:.3e} mode-steps/s at {r['rel_l2']:.3e}, "
+            f"split-step / MPA time at that error {r['time_ratio_ss_over_mpa']}")
     return {"workload": w.name, "precision": "FP64", "distance": z1, "L": s.L, "M": s.M, "n_iter": s.n_iter,
             "mpa": mpa, "split_step_f64": sweep,
-            "split_step_seconds_at_mpa_error": t_ss,
-            "time_ratio_ss_over_mpa": (t_ss / el) if t_ss else None,
             "reference": f"FP64 split-step at dz/64; the dz/128 run differs from it by {err(r128):.1e}"}
 
 
