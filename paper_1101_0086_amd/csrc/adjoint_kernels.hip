@@ -58,13 +58,19 @@ __device__ __forceinline__ long long wrap(long long g, long long n) {
     return g;
 }
 
-// node-precision transform: double-buffered when DB (see block_fft_db);
-// COLD: twiddles loaded inside each pass (see block_fft)
-template <typename T, int B, int SG, bool DB, bool COLD>
+// node-precision transform, double-buffered when DB (as block_fft_db), its
+// twiddles read from the LDS table `twl` in each pass (block_fft_warm,
+// TW_TABLE: the values of the B-point table, the arithmetic of block_fft)
+template <typename T, int B, int SG, bool DB>
 __device__ __forceinline__ void node_fft(cx<T> (&v)[PTS], cx<T>*& db0, cx<T>*& db1, cx<T>* lds,
-                                         const cx<T>* __restrict__ tw, int tid) {
-    if constexpr (DB) block_fft_db<T, B, PTS, SG, COLD>(v, db0, db1, tw, tid);
-    else block_fft<T, B, PTS, SG, COLD>(v, lds, tw, tid);
+                                         const cx<T>* __restrict__ tw, const cx<T>* twl, int tid) {
+    if constexpr (DB) {
+        block_fft_warm<T, B, PTS, SG, true, TW_TABLE>(v, db0, db1, tw, tid, twl);
+    } else {
+        cx<T>* l0 = lds;
+        cx<T>* l1 = lds;
+        block_fft_warm<T, B, PTS, SG, false, TW_TABLE>(v, l0, l1, tw, tid, twl);
+    }
 }
 
 }  // namespace
@@ -76,14 +82,15 @@ __device__ __forceinline__ void node_fft(cx<T> (&v)[PTS], cx<T>*& db0, cx<T>*& d
 // reuses its own node store for every item it takes.  The sigma derivative
 // is taken with respect to the sigma the item runs with (the span's sigma
 // times the instance's scale).
-// COLD: the node transforms load their twiddles inside each pass.  Kept in
-// registers (COLD = false) they stay live across the whole kernel: 353
-// registers per lane at B = 2048, n_iter = 2 (one workgroup per CU) and 102
-// spilled at B = 4096, against 233 with no spills when loaded per pass (two
-// workgroups per CU at B = 2048), at the price of the loads' latency in each
-// pass.  The launcher takes COLD when more work items than CUs wait.
-template <typename T, int B, int NIT, bool COLD>
-__global__ void __launch_bounds__(B / PTS)
+// The node transforms read their twiddles from a table in LDS, filled once
+// per workgroup, in each pass.  Kept in registers they stayed live across
+// the whole kernel (353 registers per lane at B = 2048, n_iter = 2: one
+// workgroup per CU; 102 spilled at B = 4096), and gathered from the global
+// table in each pass they cost 30 % of a batched reverse long step; with the
+// table the kernel is held to 256 registers (two workgroups per CU at
+// B = 2048, a few registers spilled).
+template <typename T, int B, int NIT>
+__global__ void __launch_bounds__(B / PTS) __attribute__((amdgpu_waves_per_eu(2)))
 mpa_adjoint_block_kernel(const cx<T>* __restrict__ fin, const cx<double>* __restrict__ gin,
                          cx<double>* __restrict__ g_blk, double* __restrict__ partial,
                          cx<T>* __restrict__ node_store, cx<double>* __restrict__ last_store,
@@ -95,6 +102,8 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ fin, const cx<double>* __rest
                          const double* __restrict__ taper, const cx<double>* __restrict__ mask_grad, int M,
                          double sigma_span, double out_scale, double w1, double dz) {
     __shared__ cx<double> lds64[lds_elems<B>()];
+    __shared__ cx<T> twl[tl_elems(B)];
+    fill_twiddle_table<T, B>(twl, tw, threadIdx.x, B / PTS);   // barrier: each item's first
     cx<T>* __restrict__ store = node_store + (size_t)blockIdx.x * NIT * M * 3 * B;
     cx<double>* __restrict__ last = last_store + (size_t)blockIdx.x * B;
     for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
@@ -211,16 +220,16 @@ __global__ void zero_kernel(double* __restrict__ p, long long count) {
 template <typename T, int B>
 hipError_t adjoint_nit(const AdjointStepArgs& a);
 template <typename T, int B>
-int adjoint_occupancy(int n_iter, bool cold);
+int adjoint_occupancy(int n_iter);
 
 #if !defined(MPA_SPLIT) || defined(MPA_PART_T)
-template <typename T, int B, int NIT, bool COLD>
+template <typename T, int B, int NIT>
 static hipError_t adjoint_typed(const AdjointStepArgs& a) {
     const BatchItems* bt = a.batch;
     const int n_items = bt ? bt->n_items : a.n_blocks;
     const int grid = bt ? a.grid : a.n_blocks;
     if (grid < 1 || grid > n_items) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((mpa_adjoint_block_kernel<T, B, NIT, COLD>), dim3(grid), dim3(B / PTS), 0, a.stream,
+    hipLaunchKernelGGL((mpa_adjoint_block_kernel<T, B, NIT>), dim3(grid), dim3(B / PTS), 0, a.stream,
                        static_cast<const cx<T>*>(a.in), static_cast<const cx<double>*>(a.g_out),
                        static_cast<cx<double>*>(a.g_blk), a.partial, static_cast<cx<T>*>(a.node_store),
                        static_cast<cx<double>*>(a.last_store), bt ? static_cast<const int2*>(bt->items) : nullptr,
@@ -234,40 +243,30 @@ static hipError_t adjoint_typed(const AdjointStepArgs& a) {
     return hipGetLastError();
 }
 
-template <typename T, int B, bool COLD>
-static hipError_t adjoint_cold(const AdjointStepArgs& a) {
-    switch (a.n_iter) {
-        case 1: return adjoint_typed<T, B, 1, COLD>(a);
-        case 2: return adjoint_typed<T, B, 2, COLD>(a);
-        case 3: return adjoint_typed<T, B, 3, COLD>(a);
-        case 4: return adjoint_typed<T, B, 4, COLD>(a);
-        case 5: return adjoint_typed<T, B, 5, COLD>(a);
-        default: return hipErrorInvalidValue;
-    }
-}
-
 template <typename T, int B>
 hipError_t adjoint_nit(const AdjointStepArgs& a) {
-    return a.cold ? adjoint_cold<T, B, true>(a) : adjoint_cold<T, B, false>(a);
-}
-
-template <typename T, int B, bool COLD>
-static const void* adjoint_kernel_of(int n_iter) {
-    switch (n_iter) {
-        case 1: return reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, B, 1, COLD>);
-        case 2: return reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, B, 2, COLD>);
-        case 3: return reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, B, 3, COLD>);
-        case 4: return reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, B, 4, COLD>);
-        case 5: return reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, B, 5, COLD>);
-        default: return nullptr;
+    switch (a.n_iter) {
+        case 1: return adjoint_typed<T, B, 1>(a);
+        case 2: return adjoint_typed<T, B, 2>(a);
+        case 3: return adjoint_typed<T, B, 3>(a);
+        case 4: return adjoint_typed<T, B, 4>(a);
+        case 5: return adjoint_typed<T, B, 5>(a);
+        default: return hipErrorInvalidValue;
     }
 }
 
 // workgroups of the reverse kernel resident on one CU at once (0: unknown)
 template <typename T, int B>
-int adjoint_occupancy(int n_iter, bool cold) {
-    const void* f = cold ? adjoint_kernel_of<T, B, true>(n_iter) : adjoint_kernel_of<T, B, false>(n_iter);
-    if (!f) return 0;
+int adjoint_occupancy(int n_iter) {
+    const void* f = nullptr;
+    switch (n_iter) {
+        case 1: f = reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, B, 1>); break;
+        case 2: f = reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, B, 2>); break;
+        case 3: f = reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, B, 3>); break;
+        case 4: f = reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, B, 4>); break;
+        case 5: f = reinterpret_cast<const void*>(&mpa_adjoint_block_kernel<T, B, 5>); break;
+        default: return 0;
+    }
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, B / PTS, 0) != hipSuccess) n = 0;
     return n;
@@ -276,7 +275,7 @@ int adjoint_occupancy(int n_iter, bool cold) {
 
 #if defined(MPA_PART_T)
 template hipError_t adjoint_nit<MPA_PART_T, MPA_PART_B>(const AdjointStepArgs&);
-template int adjoint_occupancy<MPA_PART_T, MPA_PART_B>(int, bool);
+template int adjoint_occupancy<MPA_PART_T, MPA_PART_B>(int);
 #else
 template <typename T>
 static hipError_t adjoint_b(const AdjointStepArgs& a) {
@@ -290,19 +289,19 @@ static hipError_t adjoint_b(const AdjointStepArgs& a) {
 }
 
 template <typename T>
-static int per_cu_b(int block, int n_iter, bool cold) {
+static int per_cu_b(int block, int n_iter) {
     switch (block) {
-        case 512: return adjoint_occupancy<T, 512>(n_iter, cold);
-        case 1024: return adjoint_occupancy<T, 1024>(n_iter, cold);
-        case 2048: return adjoint_occupancy<T, 2048>(n_iter, cold);
-        case 4096: return adjoint_occupancy<T, 4096>(n_iter, cold);
+        case 512: return adjoint_occupancy<T, 512>(n_iter);
+        case 1024: return adjoint_occupancy<T, 1024>(n_iter);
+        case 2048: return adjoint_occupancy<T, 2048>(n_iter);
+        case 4096: return adjoint_occupancy<T, 4096>(n_iter);
         default: return 0;
     }
 }
 
-int adjoint_workgroups_per_cu(int precision, int block, int n_iter, bool cold) {
+int adjoint_workgroups_per_cu(int precision, int block, int n_iter) {
     if (!block_step_supported(precision, block, n_iter)) return 0;
-    return precision == 0 ? per_cu_b<float>(block, n_iter, cold) : per_cu_b<double>(block, n_iter, cold);
+    return precision == 0 ? per_cu_b<float>(block, n_iter) : per_cu_b<double>(block, n_iter);
 }
 
 hipError_t launch_adjoint_step(const AdjointStepArgs& a) {

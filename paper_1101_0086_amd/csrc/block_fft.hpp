@@ -259,11 +259,16 @@ __device__ __forceinline__ void block_fft_db(cx<T> (&v)[R], cx<T>*& buf0, cx<T>*
 // w^4 = w^2 w^2, w^5 = w^4 w, w^6 = w^4 w^2, w^7 = w^4 w^3; at most four
 // roundings deep, a few units in the last place): seven table loads per
 // pass, gathered through the vector memory path, cost more than the six
-// products.  AHEAD: the twiddles of every pass are formed when the call
-// begins (their latency paid once); else at the start of each pass (fewer
-// registers).  Either way they do not stay in registers after the call, and
-// the arithmetic is the same.  DBUF selects the exchange of block_fft_db
-// (two buffers) or of block_fft (one).
+// products.  TW_AHEAD: the twiddles of every pass are formed when the call
+// begins (their latency paid once); TW_PASS: at the start of each pass
+// (fewer registers); either way they do not stay in registers after the
+// call, and the arithmetic is the same.  TW_TABLE: read from a table in LDS
+// (fill_twiddle_table), the B-point table's own values, as block_fft uses
+// them, for transforms inside a loop whose registers cannot hold them.
+// DBUF selects the exchange of block_fft_db (two buffers) or of block_fft
+// (one).
+enum TwiddleSource { TW_AHEAD = 0, TW_PASS = 1, TW_TABLE = 2 };
+
 constexpr int first_radix(int B) { return ilog2(B) % 3 == 0 ? 8 : (1 << (ilog2(B) % 3)); }
 
 constexpr int n_passes(int B) {
@@ -295,6 +300,33 @@ __device__ __forceinline__ void pass_twiddles(cx<T> (&w)[7], const cx<T>* __rest
     w[6] = cmul(w4, w3);
 }
 
+// LDS twiddle table of the radix-8 passes: pass s >= 1 (span p) holds
+// w^{q k} = tw[q k B / (8 p)] for q = 1..7, k < p at tl_offset(B, s) +
+// (q - 1) p + k, so that the lanes of a pass, whose k are consecutive, read
+// consecutive entries.
+constexpr int tl_offset(int B, int s) {
+    int o = 0;
+    for (int t = 1; t < s; ++t) o += 7 * pass_span(B, t);
+    return o;
+}
+
+constexpr int tl_elems(int B) { return tl_offset(B, n_passes(B)); }
+
+// Fills the table from the B-point table `tw`, `nthreads` threads striding
+// over it; the caller puts a barrier between this and the first transform.
+template <typename T, int B>
+__device__ __forceinline__ void fill_twiddle_table(cx<T>* tl, const cx<T>* __restrict__ tw, int tid, int nthreads) {
+    constexpr int NP = n_passes(B);
+    for (int e = tid; e < tl_elems(B); e += nthreads) {
+        int s = 1;
+        while (s + 1 < NP && e >= tl_offset(B, s + 1)) ++s;
+        const int p = pass_span(B, s);
+        const int r = e - tl_offset(B, s);
+        const int q = r / p + 1, k = r - (q - 1) * p;
+        tl[e] = tw[q * k * (B / (8 * p))];
+    }
+}
+
 template <typename T, int B, int S, int NP>
 __device__ __forceinline__ void all_twiddles(cx<T> (&w)[NP - 1][7], const cx<T>* __restrict__ tw, int tid) {
     if constexpr (S < NP) {
@@ -303,9 +335,9 @@ __device__ __forceinline__ void all_twiddles(cx<T> (&w)[NP - 1][7], const cx<T>*
     }
 }
 
-template <typename T, int B, int R, int SIGN, int S, int NP, bool DBUF, bool AHEAD>
+template <typename T, int B, int R, int SIGN, int S, int NP, bool DBUF, int TWS>
 __device__ __forceinline__ void passes_warm(cx<T> (&v)[R], cx<T>* buf0, cx<T>* buf1, const cx<T> (&wall)[NP - 1][7],
-                                            const cx<T>* __restrict__ tw, int tid) {
+                                            const cx<T>* __restrict__ tw, const cx<T>* tl, int tid) {
     constexpr int NT = B / R;
     constexpr int p = pass_span(B, S);
     constexpr int r = S == 0 ? first_radix(B) : 8;
@@ -323,13 +355,18 @@ __device__ __forceinline__ void passes_warm(cx<T> (&v)[R], cx<T>* buf0, cx<T>* b
     }
     cx<T> wp[7];
     if constexpr (!first) {
-        if constexpr (AHEAD) {
+        if constexpr (TWS == TW_AHEAD) {
 #pragma unroll
             for (int q = 0; q < 7; ++q) wp[q] = wall[S - 1][q];
-        } else {
+        } else if constexpr (TWS == TW_PASS) {
             int t = tid;
             asm volatile("" : "+v"(t));      // formed here, not earlier
             pass_twiddles<T, B, S>(wp, tw, t);
+        } else {
+            int k = tid & (p - 1);
+            asm volatile("" : "+v"(k));      // read here, not hoisted out of the caller's loops
+#pragma unroll
+            for (int q = 0; q < 7; ++q) wp[q] = tl[tl_offset(B, S) + q * p + k];
         }
     }
 #pragma unroll
@@ -357,25 +394,25 @@ __device__ __forceinline__ void passes_warm(cx<T> (&v)[R], cx<T>* buf0, cx<T>* b
             for (int q = 0; q < r; ++q) v[u + q * NB] = x[q];
         }
     }
-    if constexpr (!last) passes_warm<T, B, R, SIGN, S + 1, NP, DBUF, AHEAD>(v, buf0, buf1, wall, tw, tid);
+    if constexpr (!last) passes_warm<T, B, R, SIGN, S + 1, NP, DBUF, TWS>(v, buf0, buf1, wall, tw, tl, tid);
 }
 
 // B-point transform as block_fft (DBUF = false: buf1 unused) or block_fft_db
 // (DBUF: buf0 and buf1 swapped on return when the exchange count is odd),
-// with the twiddles formed as above.
-template <typename T, int B, int R, int SIGN, bool DBUF, bool AHEAD>
+// with the twiddles from the source TWS (above; `tl` for TW_TABLE).
+template <typename T, int B, int R, int SIGN, bool DBUF, int TWS>
 __device__ __forceinline__ void block_fft_warm(cx<T> (&v)[R], cx<T>*& buf0, cx<T>*& buf1,
-                                               const cx<T>* __restrict__ tw, int tid) {
+                                               const cx<T>* __restrict__ tw, int tid, const cx<T>* tl = nullptr) {
     static_assert((B & (B - 1)) == 0 && B >= 64 && R == 8, "power-of-two block, 8 points per thread");
     constexpr int NP = n_passes(B);
     static_assert(NP >= 2, "at least two passes");
     cx<T> w[NP - 1][7];
-    if constexpr (AHEAD) {
+    if constexpr (TWS == TW_AHEAD) {
         int t = tid;
         asm volatile("" : "+v"(t));      // formed inside this call
         all_twiddles<T, B, 1, NP>(w, tw, t);
     }
-    passes_warm<T, B, R, SIGN, 0, NP, DBUF, AHEAD>(v, buf0, buf1, w, tw, tid);
+    passes_warm<T, B, R, SIGN, 0, NP, DBUF, TWS>(v, buf0, buf1, w, tw, tl, tid);
     if constexpr (DBUF && (NP - 1) % 2 == 1) {
         cx<T>* s = buf0;
         buf0 = buf1;

@@ -82,14 +82,12 @@ struct AdjointStepArgs {
     int32_t precision;
     const BatchItems* batch; // concatenated fields (work list), or nullptr: one field of n blocks
     int32_t grid;            // batch: workgroups walking the list (1..n_items)
-    bool cold;               // the kernel whose node transforms load twiddles per pass
     hipStream_t stream;
 };
 
 hipError_t launch_adjoint_step(const AdjointStepArgs& a);
-// Workgroups of the reverse kernel (cold: the per-pass-twiddle form)
-// resident on one CU at once (0: unknown).
-int adjoint_workgroups_per_cu(int precision, int block, int n_iter, bool cold);
+// Workgroups of the reverse kernel resident on one CU at once (0: unknown).
+int adjoint_workgroups_per_cu(int precision, int block, int n_iter);
 
 // g_in[i] = sum of g_blk over the windows containing sample i (per field of a
 // batch); adds the work items' parameter derivatives to

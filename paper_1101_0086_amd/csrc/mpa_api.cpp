@@ -841,24 +841,10 @@ struct AdjTarget {
     int32_t n_items, grid;              // work items per long step, reverse-kernel workgroups
     void* work;                         // count samples (forward march)
     AdjWork* w;
-    bool cold;                          // reverse kernel with per-pass twiddle loads
 };
 
-// The reverse kernel's form: twiddles loaded in each pass when more work
-// items than CUs wait (its registers then allow two or more workgroups per
-// CU at B <= 2048 where the other form holds one), and always at B = 4096
-// (the other form spills); kept in registers otherwise (one item per CU:
-// occupancy gains nothing and the per-pass loads add latency).
-static bool adjoint_cold(int device, int block, int n_items) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
-        cus = 256;
-    return block >= 4096 || n_items > cus;
-}
-
 static AdjTarget single_target(mpa_plan* p) {
-    return {p,         nullptr, nullptr, 0, p->prm.n, p->n_blocks, p->n_blocks, p->work, &p->adj,
-            adjoint_cold(p->device, p->block, p->n_blocks)};
+    return {p, nullptr, nullptr, 0, p->prm.n, p->n_blocks, p->n_blocks, p->work, &p->adj};
 }
 
 // Grow-only device buffer of `count` fields.
@@ -978,7 +964,6 @@ static int adjoint_long_step(const AdjTarget& t, const void* in, const void* g_o
     a.precision = p->prm.precision;
     a.batch = t.batch;
     a.grid = t.grid;
-    a.cold = t.cold;
     a.stream = stream;
     hipError_t e = mpa::launch_adjoint_step(a);
     if (e != hipSuccess) return fail(MPA_EDEVICE, "adjoint step launch failed: %s", hipGetErrorString(e));
@@ -1330,8 +1315,7 @@ static int adjoint_grid(mpa_batch_plan* b) {
     (void)hipSetDevice(p->device);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus <= 0)
         cus = 256;
-    const int per_cu = mpa::adjoint_workgroups_per_cu(p->prm.precision, p->block, p->prm.n_iter,
-                                                      adjoint_cold(p->device, p->block, n));
+    const int per_cu = mpa::adjoint_workgroups_per_cu(p->prm.precision, p->block, p->prm.n_iter);
     const int slots = cus * (per_cu > 0 ? per_cu : 1);
     const int rounds = (n + slots - 1) / slots;
     b->adj_grid = (n + rounds - 1) / rounds;
@@ -1340,7 +1324,7 @@ static int adjoint_grid(mpa_batch_plan* b) {
 
 static AdjTarget batch_target(mpa_batch_plan* b) {
     return {b->base,         &b->items, b->d_item_base, (int32_t)b->len.size(), b->total, b->items.n_items,
-            adjoint_grid(b), b->work,   &b->adj, adjoint_cold(b->base->device, b->base->block, b->items.n_items)};
+            adjoint_grid(b), b->work,   &b->adj};
 }
 
 int mpa_batch_checkpoint_count(const mpa_batch_plan* b, double z0, double z1, int64_t* count) {

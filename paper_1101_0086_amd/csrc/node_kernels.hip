@@ -70,7 +70,7 @@ np_init_kernel(const cx<T>* __restrict__ in, cx<double>* __restrict__ psi0_buf, 
     }
     cx<double>* e0 = lds64;
     cx<double>* e1 = lds64;
-    block_fft_warm<double, B, R, +1, false, true>(psi0, e0, e1, tw64, tid);   // as the fused kernel
+    block_fft_warm<double, B, R, +1, false, TW_AHEAD>(psi0, e0, e1, tw64, tid);   // as the fused kernel
     block_fft<T, B, R, +1>(cur, ldsT, tw, tid);
     const T d0 = sigma * node_scale[1];
     const size_t base = (size_t)blockIdx.x * B;
@@ -160,7 +160,7 @@ np_final_kernel(const cx<double>* __restrict__ psi0_buf, const cx<T>* __restrict
     }
     cx<double>* e0 = lds64;
     cx<double>* e1 = lds64;
-    block_fft_warm<double, B, R, -1, false, true>(v, e0, e1, tw64, tid);      // as the fused kernel
+    block_fft_warm<double, B, R, -1, false, TW_AHEAD>(v, e0, e1, tw64, tid);      // as the fused kernel
     const long long c0 = (long long)b * core;
     const long long rest = n - c0;
     const int clen = rest < core ? (int)rest : core;

@@ -81,10 +81,10 @@ ss_rows_kernel(cx<ST>* __restrict__ y, int n1, const cx<double>* __restrict__ tw
     for (int m = 0; m < R; ++m) v[m] = load_w(row[t + NT * m]);
     cx<double>* b0 = lds + r * lds_elems<N2>();
     cx<double>* b1 = b0;
-    block_fft_warm<double, N2, R, +1, false, true>(v, b0, b1, tw2, t);
+    block_fft_warm<double, N2, R, +1, false, TW_AHEAD>(v, b0, b1, tw2, t);
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = scale(cmul(v[m], prow[t + NT * m]), scl);
-    block_fft_warm<double, N2, R, -1, false, true>(v, b0, b1, tw2, t);
+    block_fft_warm<double, N2, R, -1, false, TW_AHEAD>(v, b0, b1, tw2, t);
     // w_N^{n2 k1} for n2 = t + NT m: w_N^{t k1} (w_N^{NT k1})^m, two table
     // lookups per thread instead of one per point
     cx<double> w = big_twiddle(twl, twh, split, t * k1);
@@ -115,14 +115,14 @@ ss_cols_kernel(cx<ST>* __restrict__ y, int n2, const cx<double>* __restrict__ tw
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = load_w(y[(size_t)(t + NT * m) * n2 + col]);
     if constexpr (MODE != SS_COL_FIRST) {
-        block_fft_warm<double, N1, R, -1, false, true>(v, my, my1, tw1, t);   // x[N2 n1 + n2], n1 = t + NT m
+        block_fft_warm<double, N1, R, -1, false, TW_AHEAD>(v, my, my1, tw1, t);   // x[N2 n1 + n2], n1 = t + NT m
     }
     if constexpr (MODE == SS_COL_MID) {
 #pragma unroll
         for (int m = 0; m < R; ++m) v[m] = kick_sl(v[m], sdz);
     }
     if constexpr (MODE != SS_COL_LAST) {
-        block_fft_warm<double, N1, R, +1, false, true>(v, my, my1, tw1, t);   // Y[k1][n2], k1 = t + NT m
+        block_fft_warm<double, N1, R, +1, false, TW_AHEAD>(v, my, my1, tw1, t);   // Y[k1][n2], k1 = t + NT m
         // w_N^{col k1} for k1 = t + NT m, as in the row kernel
         cx<double> w = big_twiddle(twl, twh, split, col * t);
         const cx<double> step = big_twiddle(twl, twh, split, col * NT);

@@ -85,13 +85,11 @@ def test_batch_adjoint_equals_single_plans(prec, store_steps, gain):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_reverse_kernel_forms_agree(prec):
-    """The reverse kernel runs with its node transforms' twiddles in registers
-    when a launch has no more work items than CUs, and loads them in each pass
-    otherwise: the arithmetic is the same.  A batch of 40 fields of 11 blocks
-    (440 items, more than the CUs of any current device: per-pass form) gives
-    bitwise the field gradients of the per-field plans (11 items each:
-    register form)."""
+def test_large_batch_adjoint_equals_single_plans(prec):
+    """A batch of 40 fields of 11 blocks (440 work items, more than the CUs:
+    the reverse launch deals several items to each workgroup, which reuses
+    its LDS twiddle table and node store) gives bitwise the field gradients
+    of per-field plans (11 items each, one per workgroup)."""
     import paper_1101_0086_amd as P
     ns = [16384] * 40
     scales = [1.0] * 40
@@ -99,7 +97,7 @@ def test_reverse_kernel_forms_agree(prec):
     fields, g_out, halo, L = _case(ns, 23, block)
     dmm = dm_map(beta3=0.1)
     z0, z1 = 0.0, 2 * L
-    say("reverse kernel forms", prec)
+    say("large batch adjoint", prec)
     bp = P.MPABatchPlan(ns, DT, dmm, L, 2, 2, block, halo, prec, BAND, sigma_scale=scales)
     assert bp.info()["work_items"] == 440
     x = to_dev(np.concatenate(fields), prec)
