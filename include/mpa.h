@@ -142,7 +142,8 @@ typedef struct {
     int32_t M;             /* quadrature intervals per long step (>= 1)          */
     int32_t n_iter;        /* Picard sweeps per long step (1..5)                 */
     int32_t block;         /* B: power of two <= N; 0 (or N with halo 0) for one
-                              full periodic window                              */
+                              full periodic window (N <= 2^22; above 4096
+                              modes by four-step transforms, node order)       */
     int32_t halo;          /* samples of overlap per side (0 for a full window)  */
     int32_t precision;     /* mpa_precision                                      */
     double omega_band;     /* highest |omega| carrying signal, for the halo

@@ -371,8 +371,8 @@ static int validate_params(const mpa_params* p, const mpa_map* map, Schedule* sc
     const int B = full ? (int)p->n : p->block;
     if (full && p->n > 4096) {
         // the four-step full-window path
-        if (p->n > (int64_t(1) << 20))
-            return fail(MPA_EUNSUPPORTED, "full windows above 2^20 modes are not supported (use time blocks)");
+        if (p->n > (int64_t(1) << 22))
+            return fail(MPA_EUNSUPPORTED, "full windows above 2^22 modes are not supported (use time blocks)");
         if (p->schedule != MPA_WAVEFRONT)
             return fail(MPA_EUNSUPPORTED, "full windows above 4096 modes run in node order only");
         return MPA_OK;
@@ -549,12 +549,14 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
     p->ns_host = ns;
     p->window = full && params->n > 4096;
     if (p->window) {
-        // four-step shape N = n1 n2 (n2 >= n1), spectral-order tables, twiddles and state
+        // four-step shape N = n1 n2 (n1 = min(2^floor(lg/2), 1024) column points,
+        // n2 <= 4096 row points), spectral-order tables, twiddles and state
         const int64_t N = params->n;
         int lg = 0;
         while ((int64_t(1) << lg) < N) ++lg;
-        p->n1 = 1 << (lg / 2);
-        p->n2 = (int)(N >> (lg / 2));
+        const int l1 = lg / 2 < 10 ? lg / 2 : 10;
+        p->n1 = 1 << l1;
+        p->n2 = (int)(N >> l1);
         p->split = lg / 2;
         auto phasors = [](int64_t count, double mult, double denom) {
             std::vector<double> v(2 * (size_t)count);

@@ -1,5 +1,5 @@
 // Full-window MPA long step for windows larger than one workgroup's
-// transform (8192 <= N <= 2^20): no time blocks, so no taper, halo or
+// transform (8192 <= N <= 2^22): no time blocks, so no taper, halo or
 // roll-off; every transform of Eqs. 2 and 6 is an N-point transform done as
 // a four-step FFT over N = N1 N2 (row-major matrix x[n1][n2], n = N2 n1 + n2):
 //   forward   column pass  Y[k1][n2] = w_N^{n2 k1} sum_{n1} x[n1][n2] w_N1^{n1 k1}
@@ -253,6 +253,8 @@ static hipError_t rows(const WindowStepArgs& w, const WinRowArgs& a) {
         case 256: return rows_n2<T, MODE, 256>(w, a);
         case 512: return rows_n2<T, MODE, 512>(w, a);
         case 1024: return rows_n2<T, MODE, 1024>(w, a);
+        case 2048: return rows_n2<T, MODE, 2048>(w, a);
+        case 4096: return rows_n2<T, MODE, 4096>(w, a);
         default: return hipErrorInvalidValue;
     }
 }

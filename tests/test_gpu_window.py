@@ -1,5 +1,5 @@
 """Full-window MPA for windows larger than one workgroup's transform
-(four-step transforms, 8192 <= N <= 2^20) through the C ABI: against the
+(four-step transforms, 8192 <= N <= 2^22) through the C ABI: against the
 FP64 oracle's full-window MPA (no blocks) at sizes the oracle runs in
 seconds, across a span change and an amplifier, both precisions; and the
 blocking error of the time-blocked plan measured against it at 2^16 modes."""
@@ -31,6 +31,27 @@ def test_window_against_oracle(n, prec):
     plan.propagate(x, z0, z1)
     ref = O.mpa_propagate(a, dt, dmm, L, M, nit, z0, z1)
     assert rel_l2(to_host(x), ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_window_at_2_22_modes(prec):
+    """The 1024 x 4096 shape (2^22 modes, rows of 4096 points): one long step
+    against the oracle's full-window long step."""
+    import paper_1101_0086_amd as P
+    from workloads.wdm import _fast_wdm_field
+    n, dt = 1 << 22, 10.0 / 4096
+    a = _fast_wdm_field(Grid(n, dt), n // 4096, 8, "qpsk", np.random.default_rng(53))
+    dmm = dm_map(beta3=0.1)
+    L, M, nit = 1e-4, 2, 2
+    z0, z1 = 0.2, 0.2 + L
+    say("window 2^22", prec)
+    plan = P.MPAPlan(n, dt, dmm, L, M, nit, 0, 0, prec)
+    x = to_dev(a, prec)
+    plan.propagate(x, z0, z1)
+    got = to_host(x)
+    plan.close()
+    ref = O.mpa_propagate(a, dt, dmm, L, M, nit, z0, z1)
+    assert rel_l2(got, ref) < TOL[prec]
 
 
 def test_blocking_error_at_2_16_modes():
@@ -65,7 +86,7 @@ def test_window_refusals():
     import paper_1101_0086_amd as P
     dmm = dm_map()
     with pytest.raises(P.MPAError) as e:
-        P.MPAPlan(1 << 21, 0.01, dmm, 0.05, 2, 2, 0, 0, 0)
+        P.MPAPlan(1 << 23, 0.01, dmm, 0.05, 2, 2, 0, 0, 0)
     assert e.value.status == P._lib.MPA_EUNSUPPORTED
     with pytest.raises(P.MPAError):
         P.MPAPlan(1 << 14, 0.01, dmm, 0.05, 2, 2, 0, 0, 0, schedule=P.MPA_NODE_PARALLEL)
