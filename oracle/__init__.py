@@ -34,11 +34,13 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
   the uniform-loss split-step when the distributed gain is zero.
 * ``mpa_propagate``: marching and resume identity; lumped gain restores the
   span loss exactly.
-* ``mpa_long_step_vjp`` / ``mpa_blocked_long_step_vjp`` /
-  ``mpa_propagate_vjp`` (module ``adjoint``): gradients of a real loss with
-  respect to the input field, sigma, beta2 and beta3 (per span), pinned by
-  central finite differences of the forward functions above, across a
-  span change, an amplifier and the dispersion-dependent roll-off.
+* ``mpa_long_step_vjp`` / ``mpa_long_step_vjp_nodes`` /
+  ``mpa_blocked_long_step_vjp`` / ``mpa_propagate_vjp`` (module
+  ``adjoint``): gradients of a real loss with respect to the input field,
+  sigma, beta2 and beta3 (per span), pinned by central finite differences
+  of the forward functions above, across a span change, an amplifier, the
+  dispersion-dependent roll-off and long steps that cross span boundaries
+  (``step_weights``: also pinned against ``step_coefficients``).
 * the FP32 rounding pattern of the GPU path has no oracle: FP32 results
   are compared with this FP64 oracle ("parity unpinned" for the FP32
   rounding pattern itself).
@@ -50,8 +52,8 @@ from .nlse import (DMMapSpec, paper_fft, paper_ifft, omega_grid, beta_phase,
                    ss_long_step_gain,
                    ss_propagate, reference_propagate, if_trapezoid_long_step,
                    span_of_long_step, rel_l2)
-from .adjoint import (mpa_long_step_vjp, mpa_blocked_long_step_vjp, mpa_propagate_vjp,
-                      block_mask_grad)
+from .adjoint import (mpa_long_step_vjp, mpa_long_step_vjp_nodes, mpa_blocked_long_step_vjp,
+                      mpa_propagate_vjp, block_mask_grad, step_weights)
 
 __all__ = ["DMMapSpec", "paper_fft", "paper_ifft", "omega_grid", "beta_phase",
            "linear_step", "mpa_long_step", "mpa_blocked_long_step",
@@ -60,4 +62,4 @@ __all__ = ["DMMapSpec", "paper_fft", "paper_ifft", "omega_grid", "beta_phase",
            "ss_long_step_gain",
            "ss_propagate", "reference_propagate", "if_trapezoid_long_step",
            "span_of_long_step", "rel_l2", "mpa_long_step_vjp", "mpa_blocked_long_step_vjp",
-           "mpa_propagate_vjp", "block_mask_grad"]
+           "mpa_long_step_vjp_nodes", "mpa_propagate_vjp", "block_mask_grad", "step_weights"]
