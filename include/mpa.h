@@ -137,8 +137,9 @@ typedef struct {
                               exact integral of the piecewise-constant beta2,
                               beta3 and sigma sampled at the nodes (the mean of
                               both spans on a node that lies on a boundary);
-                              such plans have no reverse pass and cannot be
-                              combined with distributed gain (MPA_EUNSUPPORTED) */
+                              such plans cannot be combined with distributed
+                              gain (MPA_EUNSUPPORTED); their reverse pass runs
+                              each such step once per span it overlaps      */
     int32_t M;             /* quadrature intervals per long step (>= 1)          */
     int32_t n_iter;        /* Picard sweeps per long step (1..5)                 */
     int32_t block;         /* B: power of two <= N; 0 (or N with halo 0) for one
@@ -277,7 +278,9 @@ int mpa_propagate_checkpointed(mpa_plan* plan, void* field, double z0, double z1
  * `param_grad`: device buffer of 3 x n_seg doubles, overwritten with
  * dl/dsigma, dl/dbeta2 and dl/dbeta3 of every span of the map (in that order,
  * n_seg entries each; the derivative of the block roll-off with respect to
- * beta2 and beta3 is included).  `store_steps`: the most long-step inputs
+ * beta2 and beta3 is included; a long step across span boundaries adds to
+ * each span it overlaps, through the integrals of beta2 and beta3 to its
+ * nodes and the node sigma, and is reversed once per such span).  `store_steps`: the most long-step inputs
  * kept at once (0: the automatic rule above; under it, when there are
  * several segments and two segments' inputs fit in MPA_ADJOINT_STORE_BYTES,
  * the inputs of the next segment are recomputed on a second stream of the

@@ -79,9 +79,13 @@ __device__ __forceinline__ void node_fft(cx<T> (&v)[PTS], cx<T>*& db0, cx<T>*& d
 // block w of the field.  Many fields of different lengths concatenated (as in
 // the forward batch kernel): item w is block items[w].y of instance
 // items[w].x, a fixed grid of workgroups walks the list, and each workgroup
-// reuses its own node store for every item it takes.  The sigma derivative
-// is taken with respect to the sigma the item runs with (the span's sigma
-// times the instance's scale).
+// reuses its own node store for every item it takes.  The parameters enter
+// through the table nw: per node j, sigma_j and the derivatives of sigma_j
+// and of int_{z0}^{z_j} beta2 (beta3 likewise) with respect to the sigma,
+// beta2 and beta3 of one span (for a step inside that span: sigma, 1 and
+// z_j - z0; a step across span boundaries is run once per span it overlaps,
+// each run adding that span's derivatives).  The sigma derivative is taken
+// with respect to the sigma the item runs with (times the instance's scale).
 // The node transforms read their twiddles from a table in LDS, filled once
 // per workgroup, in each pass.  Kept in registers they stayed live across
 // the whole kernel (353 registers per lane at B = 2048, n_iter = 2: one
@@ -100,7 +104,7 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ fin, const cx<double>* __rest
                          const cx<double>* __restrict__ phase_last, const T* __restrict__ node_scale,
                          const cx<T>* __restrict__ tw, const cx<double>* __restrict__ tw64,
                          const double* __restrict__ taper, const cx<double>* __restrict__ mask_grad, int M,
-                         double sigma_span, double out_scale, double w1, double dz) {
+                         const double* __restrict__ nw, double out_scale, double w1) {
     __shared__ cx<double> lds64[lds_elems<B>()];
     __shared__ cx<T> twl[tl_elems(B)];
     fill_twiddle_table<T, B>(twl, tw, threadIdx.x, B / PTS);   // barrier: each item's first
@@ -120,7 +124,6 @@ mpa_adjoint_block_kernel(const cx<T>* __restrict__ fin, const cx<double>* __rest
         const cx<T>* __restrict__ in = fin + base;
         const cx<double>* __restrict__ g_out = gin + base;
         const long long c0 = (long long)blk * core;
-        const T sigma = T(sigma_span * sc);
         cx<double>* __restrict__ g_item = g_blk + (size_t)w * B;
         double* __restrict__ part = partial + (size_t)w * 3;
         int thread = threadIdx.x;
@@ -239,7 +242,8 @@ static hipError_t adjoint_typed(const AdjointStepArgs& a) {
                        static_cast<const cx<T>*>(a.phase), static_cast<const cx<double>*>(a.phase_last),
                        static_cast<const T*>(a.node_scale), static_cast<const cx<T>*>(a.twiddle),
                        static_cast<const cx<double>*>(a.twiddle64), static_cast<const double*>(a.taper),
-                       static_cast<const cx<double>*>(a.mask_grad), a.M, a.sigma, a.out_scale, a.w1, a.dz);
+                       static_cast<const cx<double>*>(a.mask_grad), a.M, static_cast<const double*>(a.node_w),
+                       a.out_scale, a.w1);
     return hipGetLastError();
 }
 

@@ -74,11 +74,12 @@ struct AdjointStepArgs {
     const void* twiddle;
     const void* twiddle64;
     const void* taper;
-    const void* mask_grad;   // 2 x B FP64 complex: e^{i beta_M} d(roll-off)/d beta2, .../d beta3; or nullptr
+    const void* mask_grad;   // 2 x B FP64 complex: e^{i beta_M} d(roll-off)/d beta2, .../d beta3 of the span
+                             // whose derivatives are taken; or nullptr
+    const void* node_w;      // 3 (M+1) FP64: per node sigma_j, d sigma_j / d sigma_s, d int_{z0}^{z_j} beta2 / d beta2_s
     int32_t M, n_iter;
-    double sigma, out_scale;
+    double out_scale;
     double w1;               // 2 pi / (B dt): block frequency spacing
-    double dz;               // L / M
     int32_t precision;
     const BatchItems* batch; // concatenated fields (work list), or nullptr: one field of n blocks
     int32_t grid;            // batch: workgroups walking the list (1..n_items)
@@ -95,7 +96,7 @@ int adjoint_workgroups_per_cu(int precision, int block, int n_iter);
 struct AdjointGatherArgs {
     const void* g_blk;
     void* g_in;
-    int64_t count;           // samples (all fields of a batch)
+    int64_t count;           // samples (all fields of a batch); 0: the parameter derivatives only
     int32_t block, core;
     int32_t lead;            // samples of each window before its core: halo + window shift
     int32_t n_blocks;        // single field

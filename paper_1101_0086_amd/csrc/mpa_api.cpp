@@ -76,6 +76,12 @@ int validate_map(const mpa_map* map) {
 struct Straddle {
     int64_t step;                      // step index within the period
     std::vector<double> b2, b3, sig;   // per node j = 0..M (filled at plan creation)
+    // the derivatives of b2 (b3) and sig with respect to beta2 (beta3) and sigma of
+    // each span the step depends on: len[q][j], the length of [z0, z_j] inside span
+    // spans[q], and w[q][j], that span's weight in sig[j] (the reverse pass)
+    std::vector<int> spans;
+    std::vector<std::vector<double>> len, w;
+    int adj_row = 0;                   // first row of its spans in the reverse-pass tables
 };
 
 struct Schedule {
@@ -160,12 +166,13 @@ void fill_straddle(const mpa_map* map, double h, int M, Straddle* st) {
     st->b2.assign(M + 1, 0.0);
     st->b3.assign(M + 1, 0.0);
     st->sig.assign(M + 1, 0.0);
+    std::vector<std::vector<double>> len(map->n_seg, std::vector<double>(M + 1, 0.0)), w = len;
     for (int j = 0; j <= M; ++j) {
         const double zj = z0 + j * dz;
         for (int i = 0; i < map->n_seg; ++i) {
-            const double len = std::fmin(std::fmax(zj, bnd[i]), bnd[i + 1]) - std::fmin(std::fmax(z0, bnd[i]), bnd[i + 1]);
-            st->b2[j] += map->beta2[i] * len;
-            st->b3[j] += map->beta3[i] * len;
+            len[i][j] = std::fmin(std::fmax(zj, bnd[i]), bnd[i + 1]) - std::fmin(std::fmax(z0, bnd[i]), bnd[i + 1]);
+            st->b2[j] += map->beta2[i] * len[i][j];
+            st->b3[j] += map->beta3[i] * len[i][j];
         }
         int on = -1;
         for (int k = 0; k <= map->n_seg; ++k)
@@ -173,11 +180,25 @@ void fill_straddle(const mpa_map* map, double h, int M, Straddle* st) {
         if (on >= 0) {
             const int left = (on - 1 + map->n_seg) % map->n_seg, right = on % map->n_seg;
             st->sig[j] = 0.5 * (map->sigma[left] + map->sigma[right]);
+            w[left][j] += 0.5;
+            w[right][j] += 0.5;
         } else {
             int i = 0;
             while (i + 1 < map->n_seg && zj >= bnd[i + 1]) ++i;
             st->sig[j] = map->sigma[i];
+            w[i][j] = 1.0;
         }
+    }
+    st->spans.clear();
+    st->len.clear();
+    st->w.clear();
+    for (int i = 0; i < map->n_seg; ++i) {
+        bool used = false;
+        for (int j = 0; j <= M; ++j) used = used || len[i][j] != 0.0 || w[i][j] != 0.0;
+        if (!used) continue;
+        st->spans.push_back(i);
+        st->len.push_back(len[i]);
+        st->w.push_back(w[i]);
     }
 }
 
@@ -269,7 +290,8 @@ struct mpa_plan {
     void* w_work64 = nullptr;
     // reverse pass: workspace of the plan's own field, roll-off derivative tables
     AdjWork adj;
-    void* adj_mask = nullptr;           // n_seg x 2 x B FP64 complex (blocked plans)
+    void* adj_mask = nullptr;           // rows x 2 x B FP64 complex (blocked plans; rows: see adjoint_setup)
+    void* adj_nodew = nullptr;          // rows x (M + 1) x 3 FP64: node sigma and derivative weights
     // diagnostics: reduction partials and result (3 STATS_PARTS + 3 doubles), and a
     // second field for the Picard residuals (allocated by their first call)
     void* diag = nullptr;
@@ -281,7 +303,7 @@ static void plan_free(mpa_plan* p) {
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
     for (void* q : {p->phase, p->phase_last, p->node_scale, p->twiddle, p->twiddle64, p->taper, p->work,
-                    p->adj_mask, p->nodes.psi0, p->nodes.half_u0, p->nodes.u[0], p->nodes.u[1],
+                    p->adj_mask, p->adj_nodew, p->nodes.psi0, p->nodes.half_u0, p->nodes.u[0], p->nodes.u[1],
                     p->w_psi0, p->w_sums, p->w_cur, p->w_work, p->w_work64, p->diag, p->diag_field})
         if (q) (void)hipFree(q);
     for (void* q : p->w_tw)
@@ -884,41 +906,81 @@ static int adjoint_setup(const AdjTarget& t) {
             return fail(MPA_ENOMEM, "adjoint: workspace allocation failed");
         }
     }
+    // rows of the reverse-pass tables: one per span, then one per span that each
+    // boundary-crossing step depends on (such a step is reversed once per span)
+    int rows = S;
+    for (auto& st : p->sched.straddles) {
+        st.adj_row = rows;
+        rows += (int)st.spans.size();
+    }
+    const double dz = p->prm.L / M;
+    if (!p->adj_nodew) {
+        // per node j: sigma_j, d sigma_j / d sigma_s, d int_{z0}^{z_j} beta2 / d beta2_s (= beta3's)
+        std::vector<double> nw((size_t)rows * 3 * (M + 1));
+        for (int s = 0; s < S; ++s)
+            for (int j = 0; j <= M; ++j) {
+                double* e = nw.data() + ((size_t)s * (M + 1) + j) * 3;
+                e[0] = p->sigma[s];
+                e[1] = 1.0;
+                e[2] = j * dz;
+            }
+        for (const auto& st : p->sched.straddles)
+            for (size_t q = 0; q < st.spans.size(); ++q)
+                for (int j = 0; j <= M; ++j) {
+                    double* e = nw.data() + (((size_t)st.adj_row + q) * (M + 1) + j) * 3;
+                    e[0] = st.sig[j];
+                    e[1] = st.w[q][j];
+                    e[2] = st.len[q][j];
+                }
+        void* d = nullptr;
+        if (hipMalloc(&d, nw.size() * 8) != hipSuccess) return fail(MPA_ENOMEM, "adjoint: table allocation failed");
+        if (hipMemcpy(d, nw.data(), nw.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(d);
+            return fail(MPA_EDEVICE, "adjoint: node weight table upload failed");
+        }
+        p->adj_nodew = d;
+    }
     if (p->halo > 0 && !p->adj_mask) {
         // e^{i beta_M(omega)} times the derivatives of the block roll-off with respect to
         // beta2 and beta3: the roll-off is d((g - 0.35) / 0.15) d((q - 0.8) / 0.1) with
         // g = |v| / (halo dt), v = (beta2 omega + beta3 omega^2 / 2) L - shift dt, q = |omega| dt / pi,
         // d(x) = (1 + cos pi x) / 2 on (0, 1), so d' = -(pi / 2) sin(pi x) there;
         // dg/dbeta2 = sign(v) omega L / (halo dt), dg/dbeta3 = sign(v) omega^2 L / (2 halo dt).
+        // A boundary-crossing step's roll-off follows its mean coefficients (the integrals
+        // over the step divided by L), whose derivative with respect to span s's
+        // coefficient is len_M / L (len_M: the length of the step inside span s).
         const double pi = 3.14159265358979323846;
         const double bdt = B * p->prm.dt;
         const double w1 = 2.0 * pi / bdt;
         const double hd = p->prm.L / (p->halo * p->prm.dt);
-        std::vector<double> tab((size_t)S * 4 * B);
+        std::vector<double> tab((size_t)rows * 4 * B);
         auto drop = [&](double x) { return x <= 0 ? 1.0 : (x >= 1 ? 0.0 : 0.5 * (1.0 + std::cos(pi * x))); };
         auto slope = [&](double x) { return (x > 0 && x < 1) ? -0.5 * pi * std::sin(pi * x) : 0.0; };
-        for (int s = 0; s < S; ++s) {
-            const double c2 = pi * p->beta2[s] * p->prm.L / (bdt * bdt);
-            const double c3 = (2.0 * pi * pi / 3.0) * p->beta3[s] * p->prm.L / (bdt * bdt * bdt);
+        auto fill = [&](int r, double bet2, double bet3, double share) {
+            const double c2 = pi * bet2 * p->prm.L / (bdt * bdt);
+            const double c3 = (2.0 * pi * pi / 3.0) * bet3 * p->prm.L / (bdt * bdt * bdt);
             for (int k = 0; k < B; ++k) {
                 const double kp = k < B / 2 ? k : k - B;
                 const double om = w1 * kp;
-                const double v = (p->beta2[s] * om + 0.5 * p->beta3[s] * om * om) * p->prm.L -
-                                 p->shift * p->prm.dt;
+                const double v = (bet2 * om + 0.5 * bet3 * om * om) * p->prm.L - p->shift * p->prm.dt;
                 const double sg = (v > 0) - (v < 0);
                 const double x1 = (std::fabs(v) / (p->halo * p->prm.dt) - 0.35) / 0.15;
-                const double dm_dg = slope(x1) / 0.15 * drop((2.0 * std::fabs(kp) / B - 0.8) / 0.1);
+                const double dm_dg = slope(x1) / 0.15 * drop((2.0 * std::fabs(kp) / B - 0.8) / 0.1) * share;
                 const double dm2 = dm_dg * sg * om * hd, dm3 = dm_dg * sg * 0.5 * om * om * hd;
                 const double turns = c2 * kp * kp + c3 * kp * kp * kp;
                 const double f = turns - std::nearbyint(turns);
                 const double c = std::cos(2.0 * pi * f), sn = std::sin(2.0 * pi * f);
-                double* row = tab.data() + (size_t)s * 4 * B;
+                double* row = tab.data() + (size_t)r * 4 * B;
                 row[2 * k] = dm2 * c;
                 row[2 * k + 1] = dm2 * sn;
                 row[2 * B + 2 * k] = dm3 * c;
                 row[2 * B + 2 * k + 1] = dm3 * sn;
             }
-        }
+        };
+        for (int s = 0; s < S; ++s) fill(s, p->beta2[s], p->beta3[s], 1.0);
+        for (const auto& st : p->sched.straddles)
+            for (size_t q = 0; q < st.spans.size(); ++q)
+                fill(st.adj_row + (int)q, st.b2[M] / p->prm.L, st.b3[M] / p->prm.L, st.len[q][M] / p->prm.L);
         void* d = nullptr;
         if (hipMalloc(&d, tab.size() * 8) != hipSuccess) return fail(MPA_ENOMEM, "adjoint: table allocation failed");
         if (hipMemcpy(d, tab.data(), tab.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
@@ -931,13 +993,20 @@ static int adjoint_setup(const AdjTarget& t) {
 }
 
 // Reverse pass of long step m: g_in (FP64) from g_out (FP64), adding the
-// step's parameter derivatives to param_grad.
+// step's parameter derivatives to param_grad.  A step across span boundaries
+// is reversed once per span it depends on, each run adding that span's
+// derivatives (the field gradient, the same in every run, is gathered after
+// the last).
 static int adjoint_long_step(const AdjTarget& t, const void* in, const void* g_out, void* g_in, int64_t m,
                              double* param_grad, hipStream_t stream) {
     mpa_plan* p = t.p;
     const int s = p->sched.span_of(m);
-    const int M = p->prm.M;
+    const int M = p->prm.M, S = (int)p->beta2.size();
     const double gain = p->sched.amp_after(m) ? p->lumped : 1.0;
+    // a boundary-crossing step's own node-scale row carries sigma_j; the reverse kernel
+    // takes sigma_j from the node weights and the row without it, which every span
+    // shares when there is no distributed gain (such steps exclude it)
+    const int ns_row = s < S ? gain_row(p, m, s) : 0;
     mpa::AdjointStepArgs a;
     a.in = in;
     a.g_out = g_out;
@@ -952,41 +1021,45 @@ static int adjoint_long_step(const AdjTarget& t, const void* in, const void* g_o
     a.n_blocks = p->n_blocks;
     a.phase = (const char*)p->phase + (size_t)s * (M + 1) * p->block * p->elem;
     a.phase_last = (const char*)p->phase_last + (size_t)s * p->block * 16;
-    a.node_scale = (const char*)p->node_scale + (size_t)gain_row(p, m, s) * 2 * (M + 1) * (p->elem / 2);
+    a.node_scale = (const char*)p->node_scale + (size_t)ns_row * 2 * (M + 1) * (p->elem / 2);
     a.twiddle = p->twiddle;
     a.twiddle64 = p->twiddle64;
     a.taper = p->taper;
-    a.mask_grad = p->adj_mask ? (const char*)p->adj_mask + (size_t)s * 2 * p->block * 16 : nullptr;
     a.M = M;
     a.n_iter = p->prm.n_iter;
-    a.sigma = s < (int)p->sigma.size() ? p->sigma[s] : 1.0;   // boundary-crossing steps: sigma in the table
-    a.out_scale = p->row_out[gain_row(p, m, s)] / p->block * gain;
+    a.out_scale = p->row_out[ns_row] / p->block * gain;
     a.w1 = 2.0 * 3.14159265358979323846 / (p->block * p->prm.dt);
-    a.dz = p->prm.L / M;
     a.precision = p->prm.precision;
     a.batch = t.batch;
     a.grid = t.grid;
     a.stream = stream;
-    hipError_t e = mpa::launch_adjoint_step(a);
-    if (e != hipSuccess) return fail(MPA_EDEVICE, "adjoint step launch failed: %s", hipGetErrorString(e));
     mpa::AdjointGatherArgs g;
     g.g_blk = t.w->gblk;
     g.g_in = g_in;
-    g.count = t.count;
     g.block = p->block;
     g.core = p->core;
     g.lead = p->halo + p->shift;
     g.n_blocks = p->n_blocks;
     g.partial = (const double*)t.w->partial;
     g.param_grad = param_grad;
-    g.n_seg = (int)p->beta2.size();
-    g.span = s;
+    g.n_seg = S;
     g.batch = t.batch;
     g.item_base = t.item_base;
     g.n_inst = t.n_inst;
     g.stream = stream;
-    e = mpa::launch_adjoint_gather(g);
-    if (e != hipSuccess) return fail(MPA_EDEVICE, "adjoint gather launch failed: %s", hipGetErrorString(e));
+    const Straddle* st = s < S ? nullptr : &p->sched.straddles[(size_t)(s - S)];
+    const int runs = st ? (int)st->spans.size() : 1;
+    for (int q = 0; q < runs; ++q) {
+        const int row = st ? st->adj_row + q : s;
+        a.node_w = (const char*)p->adj_nodew + (size_t)row * 3 * (M + 1) * sizeof(double);
+        a.mask_grad = p->adj_mask ? (const char*)p->adj_mask + (size_t)row * 2 * p->block * 16 : nullptr;
+        hipError_t e = mpa::launch_adjoint_step(a);
+        if (e != hipSuccess) return fail(MPA_EDEVICE, "adjoint step launch failed: %s", hipGetErrorString(e));
+        g.count = q == runs - 1 ? t.count : 0;       // 0: the parameter derivatives only
+        g.span = st ? st->spans[(size_t)q] : s;
+        e = mpa::launch_adjoint_gather(g);
+        if (e != hipSuccess) return fail(MPA_EDEVICE, "adjoint gather launch failed: %s", hipGetErrorString(e));
+    }
     return MPA_OK;
 }
 
@@ -1043,8 +1116,6 @@ static int forward_checkpointed(const AdjTarget& t, void* field, double z0, doub
 static int reverse(const AdjTarget& t, const void* checkpoints, void* grad, double z0, double z1,
                    double* param_grad, int64_t store_steps, hipStream_t s) {
     mpa_plan* p = t.p;
-    if (!p->sched.straddles.empty())
-        return fail(MPA_EUNSUPPORTED, "the reverse pass needs long steps that stay within one span");
     if (p->window) return fail(MPA_EUNSUPPORTED, "the reverse pass needs B <= 4096 (time blocks above that)");
     if (store_steps < 0) return fail(MPA_EINVAL, "store_steps must be >= 0");
     int64_t m0, m1;

@@ -1,7 +1,9 @@
 """Long steps that cross span boundaries (L divides the map period, not the
 spans) through the C ABI against the FP64 oracle: full window with a node on
-the boundary, blocked with the boundary between nodes, both schedules, the
-reverse pass refusing such plans, and a batch whose long steps cross them."""
+the boundary, blocked with the boundary between nodes, both schedules, a
+step over three spans, and a batch whose long steps cross them; the reverse
+pass of such plans (field gradient and per-span parameter derivatives)
+against the oracle's gradient, single fields and a batch."""
 import math
 
 import numpy as np
@@ -54,16 +56,115 @@ def test_blocked_steps_across_boundaries(prec, schedule):
     assert rel_l2(to_host(x), ref) < TOL[prec]
 
 
-def test_reverse_pass_refuses_boundary_crossing_plans():
-    import torch
+def _straddle_blocked_case(n=1 << 13, B=1024, seed=33):
+    dt = 10.0 / 1024
+    a = wdm_field(Grid(n, dt), 64, 4, "ook", np.random.default_rng(seed))
+    band = 65.0
+    halo = B // 8
+    rate = O.halo_rate(band, 20.0, 0.1)
+    k = math.ceil(1.0 / (0.25 * halo * dt / rate))
+    k += 1 - k % 2                                   # odd: L divides the period, not the spans
+    return a, dt, band, halo, k
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_reverse_full_window_across_a_boundary_on_a_node(prec):
+    """L = 1/7, M = 6, sigma 1 and 2: the step [3/7, 4/7] crosses z = 0.5 with
+    node 3 on it; field gradient and per-span derivatives against the oracle."""
+    from tests.test_gpu_adjoint import _compare, _gpu_grad, _oracle, _target
     import paper_1101_0086_amd as P
     w = WORKLOADS["dm1ch_n4096_f64"]
-    plan = P.MPAPlan(w.grid.n, w.grid.dt, w.dmmap, 1.0 / 7.0, 6, 2, 0, 0, 1)
-    x = to_dev(w.field(), 1)
-    ck = plan.propagate_checkpointed(x, 0.0, 1.0)
-    with pytest.raises(P.MPAError) as e:
-        plan.adjoint(ck, torch.zeros_like(x), 0.0, 1.0)
-    assert e.value.status == P._lib.MPA_EUNSUPPORTED
+    dmm = w.dmmap.__class__(**{**w.dmmap.__dict__, "sigma": (1.0, 2.0)})
+    a = w.field()
+    L, M, nit = 1.0 / 7.0, 6, 2
+    z0, z1 = 2.0 / 7.0, 5.0 / 7.0
+    target = _target(a, w.grid.dt, np.random.default_rng(61), 0.8, 0.05, 10.0)
+    _, g_out, ref_g, ref_p = _oracle(a, w.grid.dt, dmm, L, M, nit, z0, z1, target)
+    say("straddle reverse full window", prec)
+    plan = P.MPAPlan(w.grid.n, w.grid.dt, dmm, L, M, nit, 0, 0, prec)
+    _, got_g, got_p = _gpu_grad(plan, a, g_out, z0, z1, prec)
+    plan.close()
+    _compare(prec, got_g, got_p, ref_g, ref_p)
+
+
+@pytest.mark.parametrize("prec,shifted", [(1, False), (0, False), (1, True)])
+def test_reverse_blocked_across_boundaries(prec, shifted):
+    """Blocked plans whose boundary at 0.5 falls between two nodes of a step
+    (and the map-period boundary at 1.0 on a step edge), with and without a
+    window shift (the roll-off follows the step's mean coefficients)."""
+    from tests.gpu_util import centred_shift
+    from tests.test_gpu_adjoint import _compare, _gpu_grad, _oracle, _target
+    import paper_1101_0086_amd as P
+    a, dt, band, halo, k = _straddle_blocked_case()
+    L = 1.0 / k
+    base = dm_map(beta3=0.1)
+    dmm = base.__class__(**{**base.__dict__, "sigma": (1.0, 2.0)})
+    sh = centred_shift(band, dmm, L, dt, halo) if shifted else 0
+    target = _target(a, dt, np.random.default_rng(62), 0.9, 0.02, band)
+    m0 = k // 2 - 2
+    z0, z1 = m0 * L, (m0 + 5) * L
+    _, g_out, ref_g, ref_p = _oracle(a, dt, dmm, L, 3, 2, z0, z1, target, 1024, halo, sh)
+    say("straddle reverse blocked", prec, sh)
+    plan = P.MPAPlan(a.size, dt, dmm, L, 3, 2, 1024, halo, prec, band, shift=sh)
+    _, got_g, got_p = _gpu_grad(plan, a, g_out, z0, z1, prec)
+    plan.close()
+    _compare(prec, got_g, got_p, ref_g, ref_p)
+
+
+def test_step_over_three_spans_forward_and_reverse():
+    """A middle span (0.05) shorter than the long step (1/7): the step
+    [3/7, 4/7] overlaps three spans; forward and reverse, FP64."""
+    from tests.test_gpu_adjoint import _compare, _gpu_grad, _oracle, _target
+    import paper_1101_0086_amd as P
+    w = WORKLOADS["dm1ch_n4096_f64"]
+    dmm = dm_map(beta3=0.1, beta2=(20.0, -7.0, -19.8), seg=(0.5, 0.05, 0.45))
+    dmm = dmm.__class__(**{**dmm.__dict__, "sigma": (1.0, 3.0, 2.0)})
+    a = w.field()
+    L, M, nit = 1.0 / 7.0, 3, 2
+    z0, z1 = 2.0 / 7.0, 5.0 / 7.0
+    target = _target(a, w.grid.dt, np.random.default_rng(63), 0.8, 0.05, 10.0)
+    out, g_out, ref_g, ref_p = _oracle(a, w.grid.dt, dmm, L, M, nit, z0, z1, target)
+    say("three spans in one step")
+    plan = P.MPAPlan(w.grid.n, w.grid.dt, dmm, L, M, nit, 0, 0, 1)
+    x = to_dev(a, 1)
+    plan.propagate(x, z0, z1)
+    assert rel_l2(to_host(x), out) < TOL_F64
+    _, got_g, got_p = _gpu_grad(plan, a, g_out, z0, z1, 1)
+    plan.close()
+    _compare(1, got_g, got_p, ref_g, ref_p)
+
+
+def test_batch_reverse_across_boundaries():
+    """Batch (two instances, sigma scales 1 and 1.5) over steps that cross
+    the span change: field gradients and the summed per-span derivatives
+    against the oracle run with each instance's sigma, FP64."""
+    import paper_1101_0086_amd as P
+    a0, dt, band, halo, k = _straddle_blocked_case()
+    ns, scales = [8192, 4096], [1.0, 1.5]
+    fields = [a0, wdm_field(Grid(4096, dt), 32, 4, "ook", np.random.default_rng(41))]
+    L = 1.0 / k
+    base = dm_map(beta3=0.1)
+    dmm = base.__class__(**{**base.__dict__, "sigma": (1.0, 2.0)})
+    m0 = k // 2 - 2
+    z0, z1 = m0 * L, (m0 + 5) * L
+    rng = np.random.default_rng(64)
+    g_out = [0.1 * (rng.normal(size=n) + 1j * rng.normal(size=n)) for n in ns]
+    say("straddle reverse batch")
+    bp = P.MPABatchPlan(ns, dt, dmm, L, 3, 2, 1024, halo, P.MPA_C128, band, sigma_scale=scales)
+    x = to_dev(np.concatenate(fields), 1)
+    ck = bp.propagate_checkpointed(x, z0, z1)
+    g = to_dev(np.concatenate(g_out), 1)
+    pg = bp.adjoint(ck, g, z0, z1).cpu().numpy()
+    got_g = [to_host(v) for v in bp.split(g)]
+    bp.close()
+    ref_p = np.zeros((3, 2))
+    for a, go, sc, gg in zip(fields, g_out, scales, got_g):
+        di = dmm.__class__(**{**dmm.__dict__, "sigma": tuple(sc * s for s in dmm.sigma)})
+        ga, gs, g2, g3 = O.mpa_propagate_vjp(a, dt, di, L, 3, 2, z0, z1, go, 1024, halo)
+        assert rel_l2(gg, ga) < 1e-10
+        ref_p += np.stack([sc * gs, g2, g3])
+    err = np.linalg.norm(pg - ref_p) / np.linalg.norm(ref_p)
+    assert err < 1e-9, (err, pg, ref_p)
 
 
 def test_batch_steps_across_boundaries():
