@@ -142,9 +142,12 @@ typedef struct {
                               each such step once per span it overlaps      */
     int32_t M;             /* quadrature intervals per long step (>= 1)          */
     int32_t n_iter;        /* Picard sweeps per long step (1..5)                 */
-    int32_t block;         /* B: power of two <= N; 0 (or N with halo 0) for one
-                              full periodic window (N <= 2^22; above 4096
-                              modes by four-step transforms, node order)       */
+    int32_t block;         /* B: power of two <= N, 512..2^22; 0 (or N with
+                              halo 0) for one full periodic window (N <= 2^22).
+                              Windows above 4096 modes (full, or time blocks)
+                              run by four-step transforms in node order, with
+                              no batches, reverse pass or allocation-free
+                              march (MPA_EUNSUPPORTED)                        */
     int32_t halo;          /* samples of overlap per side (0 for a full window)  */
     int32_t precision;     /* mpa_precision                                      */
     double omega_band;     /* highest |omega| carrying signal, for the halo

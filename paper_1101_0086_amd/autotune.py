@@ -16,6 +16,9 @@ cores by the middle of the band's group-delay range over L (with beta3 != 0
 the group delay is one-signed over much of a wide band, and the shift
 centres the core's domain of dependence in its window); the tuner times a
 few launches of each on the GPU and keeps the cheapest per unit distance.
+Blocks of 512..4096 run in the fused long-step kernel; blocks of
+8192..32768 run by four-step transforms in node order (every window's state
+in HBM), which allows long steps up to 8 times longer at the same overlap.
 """
 from __future__ import annotations
 
@@ -24,7 +27,7 @@ import math
 import time
 from typing import List, Optional
 
-BLOCKS = (512, 1024, 2048, 4096)
+BLOCKS = (512, 1024, 2048, 4096, 8192, 16384, 32768)
 HALO_FRACTIONS = ((1, 8), (1, 4), (3, 8))   # halo B/8, B/4, 3B/8: overlap 2H/B of 25, 50, 75 %
 HALO_RULE = 0.25          # the library's check: rate * L <= 0.25 * halo * dt
 

@@ -114,26 +114,32 @@ hipError_t launch_convert(const void* src, int src_precision, void* dst, int dst
                           hipStream_t stream);
 hipError_t launch_zero(double* p, int64_t count, hipStream_t stream);
 
-// Full-window long step for 8192 <= N <= 2^20 (four-step transforms, see
+// Long step on windows of 8192 <= N <= 2^22 points (one full window, or the
+// time blocks of a blocked plan) by four-step transforms (see
 // window_kernels.hip).  Spectra in row-pass order: position k1 N2 + k2 holds
 // frequency k1 + N1 k2.
 struct WindowStepArgs {
     const void* in;                 // field at z0 (plan precision)
     void* out;                      // field at z0 + L (must not alias `in`)
-    int64_t n;
+    int64_t n;                      // points per window (the field's, for a full window)
+    int32_t windows;                // windows side by side (1: a full window)
+    bool blocked;                   // time blocks: gather with halos and taper, stitch the cores
+    int64_t n_field;                // blocked: samples of the field
+    int32_t core, lead;             // blocked: core length, samples before the core (halo + shift)
+    const double* taper;            // blocked: n FP64 reals
     int32_t n1, n2, split;          // N = n1 n2; w_N^j = twh[j >> split] twl[j mod 2^split]
     const void* phase;              // (M+1) x N node phasors e^{i beta_j}, spectral order (node precision)
-    const void* phase_last;         // N FP64 node-M phasors, spectral order
+    const void* phase_last;         // N FP64 node-M phasors (times the roll-off when blocked), spectral order
     const double* node_scale_host;  // host: c_j = e^{Gamma_j} / N, e_j = dz e^{-Gamma_j}, j = 0..M
     const void* tw1; const void* tw1_64;   // N1 twiddles exp(+2 pi i j / N1), node precision / FP64
     const void* tw2; const void* tw2_64;   // N2 twiddles
     const void* twl; const void* twh;      // w_N split tables, node precision
     const void* twl_64; const void* twh_64;
-    void* psi0;                     // N FP64 complex
-    void* sums;                     // n_iter x N FP64 complex
-    void* cur;                      // N complex (node precision)
-    void* work;                     // N complex (node precision)
-    void* work64;                   // N FP64 complex
+    void* psi0;                     // windows x N FP64 complex
+    void* sums;                     // n_iter x windows x N FP64 complex
+    void* cur;                      // windows x N complex (node precision)
+    void* work;                     // windows x N complex (node precision)
+    void* work64;                   // windows x N FP64 complex
     int32_t M, n_iter;
     double sigma, out_scale;
     int32_t precision;
@@ -141,8 +147,10 @@ struct WindowStepArgs {
 };
 
 hipError_t launch_window_step(const WindowStepArgs& w);
+// Phase table in the row-pass order of the four-step transform (see
+// launch_phase_table for coef and the optional roll-off `mask`, with B = n1 n2).
 hipError_t launch_phase_table_t(void* table, int precision, int n1, int n2, int rows, const double* coef,
-                                hipStream_t stream);
+                                const double* mask, hipStream_t stream);
 
 // FP64 phase table: rows r = 0..rows-1, column k = 0..B-1,
 // turns = c2[r] k'^2 + c3[r] k'^3 (k' the signed harmonic index),

@@ -390,18 +390,19 @@ static int validate_params(const mpa_params* p, const mpa_map* map, Schedule* sc
         }
     }
     if (shift_out) *shift_out = shift;
-    const int B = full ? (int)p->n : p->block;
-    if (full && p->n > 4096) {
-        // the four-step full-window path
-        if (p->n > (int64_t(1) << 22))
-            return fail(MPA_EUNSUPPORTED, "full windows above 2^22 modes are not supported (use time blocks)");
+    const int64_t B = full ? p->n : p->block;
+    if (B > 4096) {
+        // the four-step path: one full window, or time blocks above 4096 modes
+        if (B > (int64_t(1) << 22))
+            return fail(MPA_EUNSUPPORTED, full ? "full windows above 2^22 modes are not supported (use time blocks)"
+                                               : "blocks above 2^22 modes are not supported");
         if (p->schedule != MPA_WAVEFRONT)
-            return fail(MPA_EUNSUPPORTED, "full windows above 4096 modes run in node order only");
+            return fail(MPA_EUNSUPPORTED, "windows above 4096 modes run in node order only");
         return MPA_OK;
     }
-    if (!mpa::block_step_supported(p->precision, B, p->n_iter))
-        return fail(MPA_EUNSUPPORTED, "block size %d with n_iter %d is not compiled (512..4096)", B,
-                    p->n_iter);
+    if (!mpa::block_step_supported(p->precision, (int)B, p->n_iter))
+        return fail(MPA_EUNSUPPORTED, "block size %d with n_iter %d is not compiled (512..4096, or above 4096 "
+                                      "by four-step transforms)", (int)B, p->n_iter);
     return MPA_OK;
 }
 
@@ -569,11 +570,13 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
         return fail(MPA_EDEVICE, "plan table construction failed");
     }
     p->ns_host = ns;
-    p->window = full && params->n > 4096;
+    p->window = B > 4096;
     if (p->window) {
-        // four-step shape N = n1 n2 (n1 = min(2^floor(lg/2), 1024) column points,
-        // n2 <= 4096 row points), spectral-order tables, twiddles and state
-        const int64_t N = params->n;
+        // four-step shape of a window of N = B points, N = n1 n2 (n1 = min(2^floor(lg/2), 1024)
+        // column points, n2 <= 4096 row points), spectral-order tables, twiddles, and the
+        // state of every window (one full window, or the n_blocks time blocks side by side)
+        const int64_t N = B;
+        const size_t NW = (size_t)p->n_blocks;
         int lg = 0;
         while ((int64_t(1) << lg) < N) ++lg;
         const int l1 = lg / 2 < 10 ? lg / 2 : 10;
@@ -601,22 +604,23 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
                   hipMemcpy(p->w_tw[i64], v.data(), v.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMalloc(&p->w_tw[ip], v.size() * rsz) == hipSuccess && upload_real(p->w_tw[ip], v);
         }
-        wok = wok && hipMalloc(&p->w_psi0, (size_t)N * 16) == hipSuccess &&
-              hipMalloc(&p->w_sums, (size_t)params->n_iter * N * 16) == hipSuccess &&
-              hipMalloc(&p->w_cur, (size_t)N * p->elem) == hipSuccess &&
-              hipMalloc(&p->w_work, (size_t)N * p->elem) == hipSuccess &&
-              hipMalloc(&p->w_work64, (size_t)N * 16) == hipSuccess;
-        // phase tables again, in the row-pass order of the four-step transform
+        wok = wok && hipMalloc(&p->w_psi0, NW * N * 16) == hipSuccess &&
+              hipMalloc(&p->w_sums, (size_t)params->n_iter * NW * N * 16) == hipSuccess &&
+              hipMalloc(&p->w_cur, NW * N * p->elem) == hipSuccess &&
+              hipMalloc(&p->w_work, NW * N * p->elem) == hipSuccess &&
+              hipMalloc(&p->w_work64, NW * N * 16) == hipSuccess;
+        // phase tables again, in the row-pass order of the four-step transform (node M:
+        // times the block roll-off when blocked)
         wok = wok && mpa::launch_phase_table_t(p->phase, params->precision, p->n1, p->n2, rows,
-                                               (const double*)dcoef.p, 0) == hipSuccess &&
-              mpa::launch_phase_table_t(p->phase_last, MPA_C128, p->n1, p->n2, TT, (const double*)dlast.p, 0) ==
-                  hipSuccess &&
+                                               (const double*)dcoef.p, nullptr, 0) == hipSuccess &&
+              mpa::launch_phase_table_t(p->phase_last, MPA_C128, p->n1, p->n2, TT, (const double*)dlast.p,
+                                        p->halo > 0 ? (const double*)dmask.p : nullptr, 0) == hipSuccess &&
               hipDeviceSynchronize() == hipSuccess;
         if (!wok) {
             plan_free(p);
-            return fail(MPA_ENOMEM, "full-window state or table construction failed");
+            return fail(MPA_ENOMEM, "window state or table construction failed");
         }
-        p->node_bytes = (int64_t)((size_t)N * (16 * (2 + params->n_iter) + 2 * p->elem));
+        p->node_bytes = (int64_t)(NW * N * (16 * (2 + params->n_iter) + 2 * p->elem));
     }
     if (params->schedule == MPA_NODE_PARALLEL) {
         const size_t nb = (size_t)p->n_blocks;
@@ -696,7 +700,13 @@ static int launch_long_step(mpa_plan* p, const void* in, void* out, int64_t m, h
         mpa::WindowStepArgs w;
         w.in = in;
         w.out = out;
-        w.n = p->prm.n;
+        w.n = p->block;
+        w.windows = p->n_blocks;
+        w.blocked = p->block < p->prm.n;
+        w.n_field = p->prm.n;
+        w.core = p->core;
+        w.lead = p->halo + p->shift;
+        w.taper = static_cast<const double*>(p->taper);
         w.n1 = p->n1;
         w.n2 = p->n2;
         w.split = p->split;
@@ -1116,7 +1126,7 @@ static int forward_checkpointed(const AdjTarget& t, void* field, double z0, doub
 static int reverse(const AdjTarget& t, const void* checkpoints, void* grad, double z0, double z1,
                    double* param_grad, int64_t store_steps, hipStream_t s) {
     mpa_plan* p = t.p;
-    if (p->window) return fail(MPA_EUNSUPPORTED, "the reverse pass needs B <= 4096 (time blocks above that)");
+    if (p->window) return fail(MPA_EUNSUPPORTED, "the reverse pass needs windows of at most 4096 modes (time blocks)");
     if (store_steps < 0) return fail(MPA_EINVAL, "store_steps must be >= 0");
     int64_t m0, m1;
     int st = grid_range(p, z0, z1, &m0, &m1);
@@ -1280,6 +1290,7 @@ int mpa_batch_plan_validate(const mpa_params* params, const mpa_map* map, const 
         return fail(MPA_EINVAL, "a batch needs time blocks (block > 0, halo > 0)");
     if (params->schedule != MPA_WAVEFRONT)
         return fail(MPA_EUNSUPPORTED, "batches run the wavefront schedule only");
+    if (params->block > 4096) return fail(MPA_EUNSUPPORTED, "batches take blocks of at most 4096 modes");
     int64_t nmax = 0;
     for (int i = 0; i < desc->count; ++i) {
         const int64_t n = desc->n[i];
@@ -1527,8 +1538,8 @@ int mpa_propagate_noalloc(const mpa_params* params, const mpa_map* map, void* fi
     int st = validate_params(params, map, &sched, &shift);
     if (st) return st;
     const bool full = (params->block == 0 || (params->block == params->n && params->halo == 0));
-    if (params->schedule != MPA_WAVEFRONT || (full && params->n > 4096))
-        return fail(MPA_EUNSUPPORTED, "the allocation-free march runs the fused kernel only (blocks, or one "
+    if (params->schedule != MPA_WAVEFRONT || (full ? params->n : params->block) > 4096)
+        return fail(MPA_EUNSUPPORTED, "the allocation-free march runs the fused kernel only (blocks or one "
                                       "window of at most 4096 modes)");
     if (map->raman_g0 > 0 || !sched.straddles.empty())
         return fail(MPA_EUNSUPPORTED, "the allocation-free march takes neither distributed gain nor long steps "

@@ -183,7 +183,7 @@ int ss_plan_create(const mpa_map* map, int64_t n, double dt, double dz, int32_t 
         int lg = 0;
         while ((int64_t(1) << lg) < n) ++lg;
         p->split = lg / 2;
-        if (ok) ok = mpa::launch_phase_table_t(p->tables, MPA_C128, p->n1, p->n2, rows, (const double*)dcoef, 0) ==
+        if (ok) ok = mpa::launch_phase_table_t(p->tables, MPA_C128, p->n1, p->n2, rows, (const double*)dcoef, nullptr, 0) ==
                      hipSuccess;
         if (ok) ok = upload(&p->tw1, phasors(p->n1, 1.0, p->n1)) && upload(&p->tw2, phasors(p->n2, 1.0, p->n2)) &&
                      upload(&p->twl, phasors(int64_t(1) << p->split, 1.0, (double)n)) &&

@@ -232,9 +232,14 @@ hipError_t launch_ss_cols(const SSLargeArgs& a) {
     return a.precision == 0 ? cols_p<float>(a) : cols_p<double>(a);
 }
 
+// 1 for x <= 0, 0 for x >= 1, (1 + cos(pi x)) / 2 in between (the roll-off's edge).
+__device__ __forceinline__ double rc_drop_t(double x) {
+    return x <= 0.0 ? 1.0 : (x >= 1.0 ? 0.0 : 0.5 * (1.0 + cospi(x)));
+}
+
 template <typename T>
 __global__ void phase_table_t_kernel(cx<T>* __restrict__ out, int n1, int n2, int rows,
-                                     const double* __restrict__ coef) {
+                                     const double* __restrict__ coef, const double* __restrict__ mask) {
     const long long N = (long long)n1 * n2;
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)rows * N) return;
@@ -249,20 +254,28 @@ __global__ void phase_table_t_kernel(cx<T>* __restrict__ out, int n1, int n2, in
     const double f = turns - rint(turns);
     double s, c;
     sincospi(2.0 * f, &s, &c);
+    if (mask) {
+        // the block roll-off of launch_phase_table, for blocks of N points
+        const double g = fabs(fma(mask[rows + r], k2d, mask[r] * kp) - mask[2 * rows + r]);
+        const double nyq = 2.0 * fabs(kp) / double(N);
+        const double m = rc_drop_t((g - 0.35) / 0.15) * rc_drop_t((nyq - 0.8) / 0.1);
+        s *= m;
+        c *= m;
+    }
     out[idx] = cx<T>{T(c), T(s)};
 }
 
 hipError_t launch_phase_table_t(void* table, int precision, int n1, int n2, int rows, const double* coef,
-                                hipStream_t stream) {
+                                const double* mask, hipStream_t stream) {
     const long long total = (long long)rows * n1 * n2;
     const int tpb = 256;
     const unsigned grid = (unsigned)((total + tpb - 1) / tpb);
     if (precision == 0)
         hipLaunchKernelGGL(phase_table_t_kernel<float>, dim3(grid), dim3(tpb), 0, stream,
-                           static_cast<cx<float>*>(table), n1, n2, rows, coef);
+                           static_cast<cx<float>*>(table), n1, n2, rows, coef, mask);
     else
         hipLaunchKernelGGL(phase_table_t_kernel<double>, dim3(grid), dim3(tpb), 0, stream,
-                           static_cast<cx<double>*>(table), n1, n2, rows, coef);
+                           static_cast<cx<double>*>(table), n1, n2, rows, coef, mask);
     return hipGetLastError();
 }
 

@@ -1,7 +1,11 @@
-// Full-window MPA long step for windows larger than one workgroup's
-// transform (8192 <= N <= 2^22): no time blocks, so no taper, halo or
-// roll-off; every transform of Eqs. 2 and 6 is an N-point transform done as
-// a four-step FFT over N = N1 N2 (row-major matrix x[n1][n2], n = N2 n1 + n2):
+// MPA long step on windows larger than one workgroup's transform
+// (8192 <= N <= 2^22 points per window): either one full periodic window (no
+// taper, halo or roll-off), or the time blocks of a blocked plan with
+// B > 4096, every window gathered with its halos and tapered, run side by side
+// (grid dimension y = window), its spectrum rolled off at reconstruction and
+// its core stitched back.  Every transform of Eqs. 2 and 6 is an N-point
+// transform done as a four-step FFT over N = N1 N2 (row-major matrix
+// x[n1][n2], n = N2 n1 + n2):
 //   forward   column pass  Y[k1][n2] = w_N^{n2 k1} sum_{n1} x[n1][n2] w_N1^{n1 k1}
 //             row pass     X[k1][k2] = sum_{n2} Y[k1][n2] w_N2^{n2 k2}
 //   inverse   row pass     Y[k1][n2] = w_N^{-n2 k1} sum_{k2} X[k1][k2] w_N2^{-n2 k2}
@@ -21,8 +25,11 @@
 //            rows: forward row pass, U = i sigma dz e^{-Gamma_l} e^{-i beta_l} .,
 //            psi^(s+1)_l = psi_0 + S^(s) + U / 2, S^(s) += U
 //   final    rows(-) and columns(-) in FP64 of psi_M e^{i beta_M + Gamma_M}.
-// This path exists to measure the blocking error of the time-blocked plans
-// at full size; it makes 3 n_iter M + 6 passes over the window per long step.
+// Blocked plans add a gather (taper, FP64) before init and a stitch of the
+// cores after final.  This path measures the blocking error of the
+// time-blocked plans at full size and gives the autotuner blocks above 4096;
+// it makes 3 n_iter M + 6 passes over the windows per long step.
+#include <algorithm>
 #include <type_traits>
 
 #include "block_fft.hpp"
@@ -68,6 +75,9 @@ win_cols_kernel(const cx<TIN>* __restrict__ src, cx<TOUT>* __restrict__ dst, int
     __shared__ cx<TK> lds[TC * lds_elems<N1>()];
     const int c = threadIdx.x % TC, t = threadIdx.x / TC;
     const int col = blockIdx.x * TC + c;
+    const size_t woff = (size_t)blockIdx.y * N1 * n2;      // window of a blocked plan
+    src += woff;
+    dst += woff;
     cx<TK>* my = lds + c * lds_elems<N1>();
     cx<TK> v[R];
 #pragma unroll
@@ -125,21 +135,22 @@ __global__ void __launch_bounds__(TR * N2 / WP)
 win_rows_kernel(WinRowArgs a, const cx<T>* __restrict__ tw2, const cx<double>* __restrict__ tw2_64,
                 const cx<T>* __restrict__ twl, const cx<T>* __restrict__ twh,
                 const cx<double>* __restrict__ twl64, const cx<double>* __restrict__ twh64, int split,
-                long long N) {
+                long long N, long long Ntot) {
     using TP = typename std::conditional<MODE == WR_PSI0 || MODE == WR_FINAL, double, T>::type;
     constexpr int R = WP, NT = N2 / R;
     __shared__ cx<TP> lds[TR * lds_elems<N2>()];
     const int r = threadIdx.x / NT, t = threadIdx.x - r * NT;
     const long long k1 = (long long)blockIdx.x * TR + r;
     const size_t base = (size_t)k1 * N2;
+    const size_t woff = (size_t)blockIdx.y * N;            // window of a blocked plan (tables: no offset)
     cx<TP>* my = lds + r * lds_elems<N2>();
     const cx<TP>* __restrict__ tw = nullptr;
     if constexpr (sizeof(TP) == 8) tw = reinterpret_cast<const cx<TP>*>(tw2_64);
     else tw = reinterpret_cast<const cx<TP>*>(tw2);
-    cx<double>* psi0 = reinterpret_cast<cx<double>*>(a.psi0);
+    cx<double>* psi0 = reinterpret_cast<cx<double>*>(a.psi0) + woff;
     cx<TP> v[R];
     if constexpr (MODE == WR_PSI0 || MODE == WR_U0 || MODE == WR_NODE_OUT) {
-        const cx<TP>* src = static_cast<const cx<TP>*>(a.src);
+        const cx<TP>* src = static_cast<const cx<TP>*>(a.src) + woff;
 #pragma unroll
         for (int m = 0; m < R; ++m) v[m] = src[base + t + NT * m];
         block_fft<TP, N2, R, +1>(v, my, tw, t);
@@ -148,15 +159,15 @@ win_rows_kernel(WinRowArgs a, const cx<T>* __restrict__ tw2, const cx<double>* _
 #pragma unroll
         for (int m = 0; m < R; ++m) psi0[base + t + NT * m] = widen(v[m]);
     } else if constexpr (MODE == WR_U0) {
-        cx<double>* S = reinterpret_cast<cx<double>*>(a.S);
+        cx<double>* S = reinterpret_cast<cx<double>*>(a.S) + woff;
 #pragma unroll
         for (int m = 0; m < R; ++m) {
             const cx<double> u0 = widen(rot<+1>(scale(v[m], T(a.half_d0))));
-            for (int s = 0; s < a.n_iter; ++s) S[(size_t)s * N + base + t + NT * m] = u0;
+            for (int s = 0; s < a.n_iter; ++s) S[(size_t)s * Ntot + base + t + NT * m] = u0;
         }
     } else if constexpr (MODE == WR_NODE_OUT) {
-        cx<double>* S = reinterpret_cast<cx<double>*>(a.S) + (size_t)a.s * N;
-        cx<T>* cur = static_cast<cx<T>*>(a.cur);
+        cx<double>* S = reinterpret_cast<cx<double>*>(a.S) + (size_t)a.s * Ntot + woff;
+        cx<T>* cur = static_cast<cx<T>*>(a.cur) + woff;
         const cx<T>* ph = static_cast<const cx<T>*>(a.ph);
         const T dl = T(a.dl);
         const bool need_next = (a.s < a.n_iter - 1) || a.last_node;
@@ -179,14 +190,14 @@ win_rows_kernel(WinRowArgs a, const cx<T>* __restrict__ tw2, const cx<double>* _
         for (int m = 0; m < R; ++m) {
             const size_t i = base + t + NT * m;
             if constexpr (MODE == WR_NODE_IN) {
-                const cx<T> x = a.first ? narrow<T>(psi0[i]) : static_cast<const cx<T>*>(a.cur)[i];
+                const cx<T> x = a.first ? narrow<T>(psi0[i]) : static_cast<const cx<T>*>(a.cur)[woff + i];
                 v[m] = cmul(x, static_cast<const cx<T>*>(a.ph)[i]);
             } else {
                 v[m] = scale(cmul(psi0[i], static_cast<const cx<double>*>(a.ph_last)[i]), a.out_scale);
             }
         }
         block_fft<TP, N2, R, -1>(v, my, tw, t);
-        cx<TP>* dst = static_cast<cx<TP>*>(a.dst);
+        cx<TP>* dst = static_cast<cx<TP>*>(a.dst) + woff;
 #pragma unroll
         for (int m = 0; m < R; ++m) {
             const int n2 = t + NT * m;
@@ -195,6 +206,35 @@ win_rows_kernel(WinRowArgs a, const cx<T>* __restrict__ tw2, const cx<double>* _
             else w = wN(twl, twh, split, (long long)n2 * k1);
             dst[base + n2] = cmulc(v[m], w);
         }
+    }
+}
+
+// Blocked plans: window w of B samples starts at w C - lead (mod n) and is
+// multiplied by the taper, in FP64 (out[w][t]).
+template <typename T>
+__global__ void win_gather_kernel(const cx<T>* __restrict__ in, cx<double>* __restrict__ out, long long n, int B,
+                                  int core, int lead, const double* __restrict__ taper, long long total) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const long long w = i / B;
+        const int t = (int)(i - w * B);
+        long long j = (w * core - lead + t) % n;
+        if (j < 0) j += n;
+        const cx<T> x = in[j];
+        out[i] = scale(cx<double>{double(x.re), double(x.im)}, taper[t]);
+    }
+}
+
+// Sample i of the field is sample lead + (i - w C) of window w = i / C (the
+// cores partition the field; the last one may be shorter).
+template <typename T>
+__global__ void win_stitch_kernel(const cx<double>* __restrict__ win, cx<T>* __restrict__ out, long long n, int B,
+                                  int core, int lead) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const long long w = i / core;
+        const cx<double> x = win[w * B + lead + (i - w * core)];
+        out[i] = cx<T>{T(x.re), T(x.im)};
     }
 }
 
@@ -211,7 +251,7 @@ static hipError_t cols_n1(const WindowStepArgs& w, const void* src, void* dst, c
                           const void* twh, double cnode) {
     constexpr int TC = col_tile<N1>();
     if (w.n2 % TC) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((win_cols_kernel<TIN, TK, TOUT, N1, TC, MODE>), dim3(w.n2 / TC), dim3(TC * N1 / WP), 0,
+    hipLaunchKernelGGL((win_cols_kernel<TIN, TK, TOUT, N1, TC, MODE>), dim3(w.n2 / TC, w.windows), dim3(TC * N1 / WP), 0,
                        w.stream, static_cast<const cx<TIN>*>(src), static_cast<cx<TOUT>*>(dst), w.n2,
                        static_cast<const cx<TK>*>(tw1), static_cast<const cx<TK>*>(twl),
                        static_cast<const cx<TK>*>(twh), w.split, TK(cnode));
@@ -238,11 +278,11 @@ template <typename T, int MODE, int N2>
 static hipError_t rows_n2(const WindowStepArgs& w, const WinRowArgs& a) {
     constexpr int TR = row_tile<N2>();
     if (w.n1 % TR) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((win_rows_kernel<T, N2, TR, MODE>), dim3(w.n1 / TR), dim3(TR * N2 / WP), 0, w.stream, a,
+    hipLaunchKernelGGL((win_rows_kernel<T, N2, TR, MODE>), dim3(w.n1 / TR, w.windows), dim3(TR * N2 / WP), 0, w.stream, a,
                        static_cast<const cx<T>*>(w.tw2), static_cast<const cx<double>*>(w.tw2_64),
                        static_cast<const cx<T>*>(w.twl), static_cast<const cx<T>*>(w.twh),
                        static_cast<const cx<double>*>(w.twl_64), static_cast<const cx<double>*>(w.twh_64), w.split,
-                       (long long)w.n);
+                       (long long)w.n, (long long)w.n * w.windows);
     return hipGetLastError();
 }
 
@@ -270,10 +310,23 @@ static hipError_t window_step_t(const WindowStepArgs& w) {
     a.n_iter = w.n_iter;
     const double* ns = w.node_scale_host;           // c_j, e_j as built (FP64), rounded to T below
     // init: psi_0 = F[A] (FP64), U_0 / 2 into every S^(s)
-    if ((e = cols<T, double, double, WC_FWD>(w, w.in, w.work64))) return e;
+    if (w.blocked) {
+        // the tapered windows in FP64; the cube's column pass reads them before the
+        // forward column pass overwrites them in place
+        const long long total = (long long)w.n * w.windows;
+        const unsigned grid = (unsigned)std::min<long long>((total + 255) / 256, 8192);
+        hipLaunchKernelGGL(win_gather_kernel<T>, dim3(grid), dim3(256), 0, w.stream, static_cast<const cx<T>*>(w.in),
+                           static_cast<cx<double>*>(w.work64), (long long)w.n_field, (int)w.n, w.core, w.lead,
+                           w.taper, total);
+        if ((e = hipGetLastError())) return e;
+        if ((e = cols<double, T, T, WC_FWD_CUBE>(w, w.work64, w.work))) return e;
+        if ((e = cols<double, double, double, WC_FWD>(w, w.work64, w.work64))) return e;
+    } else {
+        if ((e = cols<T, double, double, WC_FWD>(w, w.in, w.work64))) return e;
+    }
     a.src = w.work64;
     if ((e = rows<T, WR_PSI0>(w, a))) return e;
-    if ((e = cols<T, T, T, WC_FWD_CUBE>(w, w.in, w.work))) return e;
+    if (!w.blocked && (e = cols<T, T, T, WC_FWD_CUBE>(w, w.in, w.work))) return e;
     a.src = w.work;
     a.half_d0 = double(T(T(w.sigma) * T(ns[1])) * T(0.5));
     if ((e = rows<T, WR_U0>(w, a))) return e;
@@ -296,7 +349,13 @@ static hipError_t window_step_t(const WindowStepArgs& w) {
     a.out_scale = w.out_scale;
     a.dst = w.work64;
     if ((e = rows<T, WR_FINAL>(w, a))) return e;
-    return cols<double, double, T, WC_INV>(w, w.work64, w.out);
+    if (!w.blocked) return cols<double, double, T, WC_INV>(w, w.work64, w.out);
+    if ((e = cols<double, double, double, WC_INV>(w, w.work64, w.work64))) return e;
+    const unsigned grid = (unsigned)std::min<long long>((w.n_field + 255) / 256, 8192);
+    hipLaunchKernelGGL(win_stitch_kernel<T>, dim3(grid), dim3(256), 0, w.stream,
+                       static_cast<const cx<double>*>(w.work64), static_cast<cx<T>*>(w.out), (long long)w.n_field,
+                       (int)w.n, w.core, w.lead);
+    return hipGetLastError();
 }
 
 hipError_t launch_window_step(const WindowStepArgs& w) {

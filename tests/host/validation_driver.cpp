@@ -57,7 +57,9 @@ int main() {
         {[](mpa_params& q) { q.shift = -257; }, MPA_EINVAL},
         {[](mpa_params& q) { q.L = 3e-4; }, MPA_EALIGN},
         {[](mpa_params& q) { q.L = 1e-3; }, MPA_EHALO},
-        {[](mpa_params& q) { q.block = 1 << 14; q.halo = 2048; }, MPA_EUNSUPPORTED},
+        {[](mpa_params& q) { q.block = 1 << 14; q.halo = 2048; }, MPA_OK},
+        {[](mpa_params& q) { q.block = 1 << 14; q.halo = 2048; q.schedule = MPA_NODE_PARALLEL; }, MPA_EUNSUPPORTED},
+        {[](mpa_params& q) { q.n = 1 << 24; q.block = 1 << 23; q.halo = 2048; }, MPA_EUNSUPPORTED},
         {[](mpa_params& q) { q.block = 0; q.halo = 0; q.n = 1 << 23; q.L = 0.05; }, MPA_EUNSUPPORTED},
         {[](mpa_params& q) { q.block = 0; q.halo = 0; q.n = 4096; q.L = 0.05; q.shift = 3; }, MPA_EINVAL},
     };

@@ -61,7 +61,10 @@ def test_validation_status_codes():
     assert _validate(L=3e-4) == L.MPA_EALIGN            # does not divide the 0.5 spans
     assert _validate(L=1e-3) == L.MPA_EHALO             # group delay over L too large for H
     assert _validate(halo=64) == L.MPA_EHALO
-    assert _validate(block=1 << 14, halo=2048) == L.MPA_EUNSUPPORTED
+    # blocks above 4096: four-step transforms in node order, up to 2^22
+    assert _validate(block=1 << 14, halo=2048) == L.MPA_OK
+    assert _validate(block=1 << 14, halo=2048, schedule=L.MPA_NODE_PARALLEL) == L.MPA_EUNSUPPORTED
+    assert _validate(n=1 << 24, block=1 << 23, halo=2048) == L.MPA_EUNSUPPORTED
     assert _validate(dmmap=dm_map(beta3=0.1, z_amp=1.0 / 3.0)) == L.MPA_EALIGN
     # distributed gain: needs a positive profile rate and amplifiers
     from workloads.wdm import DMMap

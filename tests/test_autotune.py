@@ -14,7 +14,10 @@ def test_candidates_are_valid_and_maximal():
     cands = candidates(w.grid.n, w.grid.dt, w.dmmap, dz, w.mpa.omega_band, shifted=False)
     # halos of 64 and 128 samples cannot take even one dz inside the halo rule
     assert [(c.block, c.halo) for c in cands] == [(1024, 256), (1024, 384), (2048, 256), (2048, 512), (2048, 768),
-                                                  (4096, 512), (4096, 1024), (4096, 1536)]
+                                                  (4096, 512), (4096, 1024), (4096, 1536),
+                                                  (8192, 1024), (8192, 2048), (8192, 3072),
+                                                  (16384, 2048), (16384, 4096), (16384, 6144),
+                                                  (32768, 4096), (32768, 8192), (32768, 12288)]
     rate = max(abs(b2) * w.mpa.omega_band + 0.5 * abs(b3) * w.mpa.omega_band ** 2
                for b2, b3 in zip(w.dmmap.beta2, w.dmmap.beta3))
     m = L.MapStruct(w.dmmap)

@@ -188,14 +188,19 @@ def test_resume_step_and_determinism():
     # shifted windows at the same dz
     ("wdm32_n4194304_f32", dict(block=4096, halo=512, L=1.5625e-5, M=2, shift=96), 0),
     ("wdm32_n4194304_f32", dict(block=2048, halo=256, L=7.8125e-6, M=1, shift=48), 0),
+    # blocks above 4096 (four-step transforms, node order), the autotuner's shapes at the same dz
+    ("wdm32_n4194304_f32", dict(block=8192, halo=2048, L=6.25e-5, M=8, shift=384), 0),
+    ("wdm32_n4194304_f32", dict(block=16384, halo=4096, L=1.25e-4, M=16, shift=769), 0),
+    ("wdm32_n4194304_f32", dict(block=32768, halo=8192, L=2.5e-4, M=32, shift=1538), 0),
+    ("wdm32_n4194304_f32", dict(block=16384, halo=2048, L=6.25e-5, M=8, shift=384), 1),
 ])
 def test_full_size_sampled_blocks(name, over, prec):
     """The benchmark's 2^18-mode 8-channel workload and the 2^22-mode
     32-channel QPSK workload (the largest configuration) in their launch
     configurations (4096-blocks, 512-halo) and in the wider-overlap
-    configurations the autotuner picks at the same dz: one long step on the
-    GPU, three blocks (first, middle, ragged last) recomputed by the oracle
-    one at a time, roll-off included."""
+    configurations and blocks of 8192..32768 the autotuner tries at the same
+    dz: one long step on the GPU, three blocks (first, middle, ragged last)
+    recomputed by the oracle one at a time, roll-off included."""
     import dataclasses
     w = WORKLOADS[name]
     if over:

@@ -1,15 +1,17 @@
-"""Full-window MPA for windows larger than one workgroup's transform
-(four-step transforms, 8192 <= N <= 2^22) through the C ABI: against the
+"""MPA on windows larger than one workgroup's transform (four-step
+transforms, 8192 <= N <= 2^22) through the C ABI: the full window against the
 FP64 oracle's full-window MPA (no blocks) at sizes the oracle runs in
-seconds, across a span change and an amplifier, both precisions; and the
-blocking error of the time-blocked plan measured against it at 2^16 modes."""
+seconds, across a span change and an amplifier, both precisions; time blocks
+of 8192..32768 against the oracle's blocked MPA (taper, roll-off, shifted
+windows, ragged last core); and the blocking error of the time-blocked plan
+measured against the full window at 2^16 modes."""
 import math
 
 import numpy as np
 import pytest
 
 import oracle as O
-from tests.gpu_util import TOL_F32, TOL_F64, rel_l2, say, to_dev, to_host
+from tests.gpu_util import TOL_F32, TOL_F64, centred_shift, rel_l2, say, to_dev, to_host
 from workloads import Grid, dm_map, wdm_field
 
 pytestmark = pytest.mark.gpu
@@ -52,6 +54,75 @@ def test_window_at_2_22_modes(prec):
     plan.close()
     ref = O.mpa_propagate(a, dt, dmm, L, M, nit, z0, z1)
     assert rel_l2(got, ref) < TOL[prec]
+
+
+def _large_block_case(n, H, seed):
+    """WDM field (4 OOK channels, 128 samples per bit) and the longest L = 0.5/k
+    within the halo rule for the 65-wide band."""
+    dt = 10.0 / 1024
+    a = wdm_field(Grid(n, dt), n // 128, 4, "ook", np.random.default_rng(seed))
+    band = 65.0
+    rate = O.halo_rate(band, 20.0, 0.1)
+    k = math.ceil(0.5 / (0.25 * H * dt / rate))
+    while (0.5 / k) * rate > 0.25 * H * dt:
+        k += 1
+    return a, dt, band, 0.5 / k
+
+
+@pytest.mark.parametrize("n,B,H,prec,shifted", [
+    (1 << 15, 8192, 1024, 1, False),
+    (1 << 15, 8192, 1024, 0, False),
+    (1 << 16, 16384, 3072, 0, True),
+    (1 << 17, 32768, 4096, 1, True),
+])
+def test_blocks_above_4096_against_oracle(n, B, H, prec, shifted):
+    """Blocked plans with B > 4096 (gather with halos and taper, roll-off,
+    stitched cores; ragged last core) across the span change and, for the
+    FP64 8192-blocks, an amplifier."""
+    import paper_1101_0086_amd as P
+    a, dt, band, L = _large_block_case(n, H, 72)
+    dmm = dm_map(beta3=0.1)
+    sh = centred_shift(band, dmm, L, dt, H) if shifted else 0
+    M, nit = 4, 2
+    ranges = [(0.5 - 2 * L, 0.5 + 2 * L)]
+    if B == 8192 and prec == 1:
+        ranges.append((1.0 - 2 * L, 1.0 + L))
+    plan = P.MPAPlan(n, dt, dmm, L, M, nit, B, H, prec, band, shift=sh)
+    assert plan.info()["n_blocks"] == -(-n // (B - 2 * H))
+    assert n % (B - 2 * H) != 0                       # the last core is ragged
+    for z0, z1 in ranges:
+        say("large blocks", n, B, H, prec, sh, z0, z1)
+        x = to_dev(a, prec)
+        plan.propagate(x, z0, z1)
+        ref = O.mpa_propagate(a, dt, dmm, L, M, nit, z0, z1, B, H, sh)
+        assert rel_l2(to_host(x), ref) < TOL[prec], (z0, z1)
+    plan.close()
+
+
+def test_large_blocks_refusals():
+    """Blocks above 4096 run in node order only, with no reverse pass and no
+    batches; blocks above 2^22 are refused (L = 0.005 and a band of 10 keep
+    the halo rule)."""
+    import torch
+    import paper_1101_0086_amd as P
+    dmm = dm_map()
+    L, band = 0.005, 10.0
+    with pytest.raises(P.MPAError) as e:
+        P.MPAPlan(1 << 16, 0.01, dmm, L, 2, 2, 8192, 1024, 0, band, schedule=P.MPA_NODE_PARALLEL)
+    assert e.value.status == P._lib.MPA_EUNSUPPORTED
+    with pytest.raises(P.MPAError) as e:
+        P.MPABatchPlan([1 << 15, 1 << 14], 0.01, dmm, L, 2, 2, 8192, 1024, P.MPA_C64, band)
+    assert e.value.status == P._lib.MPA_EUNSUPPORTED
+    with pytest.raises(P.MPAError) as e:
+        P.MPAPlan(1 << 24, 0.01, dmm, L, 2, 2, 1 << 23, 1024, 0, band)
+    assert e.value.status == P._lib.MPA_EUNSUPPORTED
+    plan = P.MPAPlan(1 << 15, 0.01, dmm, L, 2, 2, 8192, 1024, 1, band)
+    x = torch.zeros(1 << 15, dtype=torch.complex128, device="cuda:0")
+    ck = plan.propagate_checkpointed(x, 0.0, 0.1)
+    with pytest.raises(P.MPAError) as e:
+        plan.adjoint(ck, x.clone(), 0.0, 0.1)
+    assert e.value.status == P._lib.MPA_EUNSUPPORTED
+    plan.close()
 
 
 def test_blocking_error_at_2_16_modes():
