@@ -510,7 +510,8 @@ def batched(torch, P, count=256, steps=200):
     sigma uniform in [0.5, 2], 4096-blocks with 512-halos, L = 5e-5, M = 1,
     2 sweeps: one launch per long step for all instances, eager and as a
     replayed HIP graph of `steps` long steps; and the autotuner's candidates
-    for the shortest instance at the same dz."""
+    for the shortest instance at the same dz (blocks of at most 4096, the
+    batch kernel's)."""
     import numpy as np
     from workloads import dm_map
     from workloads.wdm import batched_instances
@@ -536,7 +537,7 @@ def batched(torch, P, count=256, steps=200):
     from paper_1101_0086_amd.autotune import candidates
     dz = L / M
     tuned = []
-    for c in candidates(min(ns), dt, dm_map(beta3=0.1), dz, band):
+    for c in candidates(min(ns), dt, dm_map(beta3=0.1), dz, band, blocks=(512, 1024, 2048, 4096)):
         cp = P.MPABatchPlan(ns, dt, dm_map(beta3=0.1), c.L, c.M, nit, c.block, c.halo, P.MPA_C64, band,
                             sigma_scale=sig, shift=c.shift)
         y = x.clone()
