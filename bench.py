@@ -604,6 +604,7 @@ def gradient(torch, P, periods=20):
     t_ck, ck = _timed(torch, lambda: plan.propagate_checkpointed(x, 0.0, z1))
     g = (2 * (x - target)).contiguous()
     t_adj, pg = _timed(torch, lambda: plan.adjoint(ck, g, 0.0, z1))
+    kept = _kept_inputs(torch, plan, x0, z1, steps, lambda y: (2 * (y - target)).contiguous())
     nb = plan.info()["n_blocks"]
     plan.close()
     fl = adjoint_flops_per_block(s.block, s.M, s.n_iter) * nb
@@ -614,10 +615,35 @@ def gradient(torch, P, periods=20):
          "gradient_mode_steps_per_s": w.grid.n * s.M * steps / (t_ck + t_adj),
          "reverse_us_per_long_step": t_adj / steps * 1e6,
          "adjoint_flops_per_launch": fl,
-         "adjoint_tflops_wall": fl * steps / t_adj / 1e12}
+         "adjoint_tflops_wall": fl * steps / t_adj / 1e12,
+         "kept_inputs": dict(kept, gradient_over_forward=(kept["checkpointed_forward_s"] + kept["reverse_s"]) / t_fwd)}
     log(f"gradient ({periods} periods): forward {t_fwd:.2f} s, checkpointed {t_ck:.2f} s, reverse {t_adj:.2f} s "
-        f"({r['gradient_over_forward']:.2f}x forward)")
+        f"({r['gradient_over_forward']:.2f}x forward; step inputs kept: "
+        f"{r['kept_inputs']['gradient_over_forward']:.2f}x)")
     return r
+
+
+# HBM budget for the step inputs kept by the checkpointed forward (the
+# gradient runs keep 40 GiB and 62.5 GiB of the MI355X's 288 GB)
+KEEP_BYTES = 96 << 30
+
+
+def _kept_inputs(torch, plan, x0, z1, steps, grad_of):
+    """The same checkpointed forward and reverse pass with every step input
+    kept by the forward (plan.keep_inputs): one untimed run sizes the
+    workspace, then both are timed."""
+    plan.keep_inputs(KEEP_BYTES)
+    x = x0.clone()
+    ck = plan.propagate_checkpointed(x, 0.0, z1)
+    plan.adjoint(ck, grad_of(x), 0.0, z1)
+    del ck
+    x = x0.clone()
+    t_ck, ck = _timed(torch, lambda: plan.propagate_checkpointed(x, 0.0, z1))
+    g = grad_of(x)
+    t_adj, _ = _timed(torch, lambda: plan.adjoint(ck, g, 0.0, z1))
+    plan.keep_inputs(0)
+    del ck
+    return {"checkpointed_forward_s": t_ck, "reverse_s": t_adj, "kept_bytes": int(x0.numel() * x0.element_size() * steps)}
 
 
 def batched_gradient(torch, P, count=32, periods=1):
@@ -648,6 +674,8 @@ def batched_gradient(torch, P, count=32, periods=1):
     t_ck, ck = _timed(torch, lambda: bp.propagate_checkpointed(x, 0.0, z1))
     g = (2 * x).contiguous()
     t_adj, _ = _timed(torch, lambda: bp.adjoint(ck, g, 0.0, z1))
+    del ck
+    kept = _kept_inputs(torch, bp, x0, z1, steps, lambda y: (2 * y).contiguous())
     bp.close()
     ms = info["total_samples"] * s.M * steps
     r = {"workload": f"{count} x {w.name}", "total_modes": info["total_samples"],
@@ -656,8 +684,11 @@ def batched_gradient(torch, P, count=32, periods=1):
          "gradient_over_forward": (t_ck + t_adj) / t_fwd,
          "forward_mode_steps_per_s": ms / t_fwd,
          "gradient_mode_steps_per_s": ms / (t_ck + t_adj),
-         "reverse_us_per_long_step": t_adj / steps * 1e6}
-    log(f"batched gradient ({count} instances): gradient {r['gradient_over_forward']:.2f}x forward")
+         "reverse_us_per_long_step": t_adj / steps * 1e6,
+         "kept_inputs": dict(kept, gradient_over_forward=(kept["checkpointed_forward_s"] + kept["reverse_s"]) / t_fwd,
+                             gradient_mode_steps_per_s=ms / (kept["checkpointed_forward_s"] + kept["reverse_s"]))}
+    log(f"batched gradient ({count} instances): gradient {r['gradient_over_forward']:.2f}x forward "
+        f"(step inputs kept: {r['kept_inputs']['gradient_over_forward']:.2f}x)")
     return r
 
 

@@ -295,6 +295,21 @@ int mpa_propagate_checkpointed(mpa_plan* plan, void* field, double z0, double z1
 int mpa_adjoint(mpa_plan* plan, const void* checkpoints, void* grad, double z0, double z1,
                 double* param_grad, int64_t store_steps, void* stream);
 
+/* Checkpointing trades recomputation for memory (the reverse pass needs the
+ * input of every long step, Eq. 6 per step); with HBM to spare the forward
+ * can keep them all.  After this call, mpa_propagate_checkpointed also keeps
+ * the input of every long step of [z0, z1] in the plan's reverse-pass
+ * workspace whenever they fit in max_bytes (steps x N complex samples of the
+ * plan precision; 0, the default, keeps none).  A following mpa_adjoint over
+ * the same z0, z1 and checkpoints with store_steps = 0 then reverses from
+ * them without recomputing any long step; the results are bitwise those of
+ * the recomputing pass.  The inputs stay valid until the next
+ * mpa_propagate_checkpointed, a reverse pass that recomputes (store_steps >
+ * 0, or another range or checkpoint buffer), or the next call of this
+ * function; the workspace is held until the plan is destroyed.
+ * MPA_EINVAL for a NULL plan or max_bytes < 0.                              */
+int mpa_adjoint_keep_inputs(mpa_plan* plan, int64_t max_bytes);
+
 /* ---- batches of independent fields (one launch per long step for all) ----
  *
  * Instances share dt, L, M, n_iter, block, halo, precision and the map (so
@@ -342,6 +357,8 @@ int mpa_batch_propagate_checkpointed(mpa_batch_plan* plan, void* fields, double 
                                      void* checkpoints, void* stream);
 int mpa_batch_adjoint(mpa_batch_plan* plan, const void* checkpoints, void* grads, double z0,
                       double z1, double* param_grad, int64_t store_steps, void* stream);
+/* mpa_adjoint_keep_inputs for a batch plan (max_bytes counts all fields).  */
+int mpa_batch_adjoint_keep_inputs(mpa_batch_plan* plan, int64_t max_bytes);
 
 /* ---- captured launch sequences (HIP graphs) ------------------------------
  *

@@ -118,6 +118,12 @@ class MPAPlan:
             C.c_void_p(ckpt.data_ptr() if k else 0), _stream_handle(torch, field.device)))
         return ckpt
 
+    def keep_inputs(self, max_bytes):
+        """mpa_adjoint_keep_inputs: propagate_checkpointed keeps every long
+        step's input when they fit in `max_bytes` (0: none), and adjoint over
+        the same range and checkpoints reverses from them."""
+        _lib.check(_lib.lib().mpa_adjoint_keep_inputs(self._h, int(max_bytes)))
+
     def adjoint(self, checkpoints, grad, z0, z1, store_steps=0):
         """mpa_adjoint: turns G(A(z1)) in `grad` into G(A(z0)) in place and
         returns dl/d(sigma, beta2, beta3) per span as a (3, n_seg) FP64 tensor
@@ -224,6 +230,10 @@ class MPABatchPlan:
             self._h, C.c_void_p(fields.data_ptr()), float(z0), float(z1),
             C.c_void_p(ckpt.data_ptr() if k else 0), _stream_handle(torch, fields.device)))
         return ckpt
+
+    def keep_inputs(self, max_bytes):
+        """mpa_batch_adjoint_keep_inputs (see MPAPlan.keep_inputs)."""
+        _lib.check(_lib.lib().mpa_batch_adjoint_keep_inputs(self._h, int(max_bytes)))
 
     def adjoint(self, checkpoints, grads, z0, z1, store_steps=0):
         """mpa_batch_adjoint: turns G(A(z1)) of every instance (concatenated in

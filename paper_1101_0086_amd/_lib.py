@@ -35,8 +35,9 @@ EXPORTED = ("mpa_plan_create", "mpa_plan_destroy", "mpa_plan_get_info", "mpa_pla
             "mpa_batch_plan_destroy", "mpa_batch_get_info", "mpa_batch_propagate",
             "mpa_graph_capture", "mpa_batch_graph_capture", "mpa_graph_launch", "mpa_graph_destroy",
             "ss_plan_create", "ss_plan_destroy", "ss_plan_propagate", "ss_propagate", "mpa_status_string", "mpa_last_error_detail",
-            "mpa_checkpoint_count", "mpa_propagate_checkpointed", "mpa_adjoint",
+            "mpa_checkpoint_count", "mpa_propagate_checkpointed", "mpa_adjoint", "mpa_adjoint_keep_inputs",
             "mpa_batch_checkpoint_count", "mpa_batch_propagate_checkpointed", "mpa_batch_adjoint",
+            "mpa_batch_adjoint_keep_inputs",
             "mpa_propagate_noalloc", "mpa_check_field", "mpa_picard_residuals")
 
 
@@ -116,6 +117,8 @@ def lib() -> C.CDLL:
     h.mpa_batch_checkpoint_count.argtypes = [vp, dp, dp, C.POINTER(C.c_int64)]
     h.mpa_batch_propagate_checkpointed.argtypes = [vp, vp, dp, dp, vp, vp]
     h.mpa_batch_adjoint.argtypes = [vp, vp, vp, dp, dp, vp, C.c_int64, vp]
+    h.mpa_adjoint_keep_inputs.argtypes = [vp, C.c_int64]
+    h.mpa_batch_adjoint_keep_inputs.argtypes = [vp, C.c_int64]
     h.mpa_status_string.argtypes = [C.c_int]
     h.mpa_status_string.restype = C.c_char_p
     h.mpa_last_error_detail.argtypes = [C.c_char_p, C.c_int]

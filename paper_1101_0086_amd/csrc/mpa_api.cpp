@@ -234,6 +234,13 @@ struct AdjWork {
     int64_t inputs_cap = 0;
     void* subs = nullptr;       // subs_cap fields: inner checkpoints of a long map period
     int64_t subs_cap = 0;
+    // inputs kept by the checkpointed forward (mpa_adjoint_keep_inputs): when every
+    // step input of its range fits in keep_bytes, `inputs` holds them, valid for a
+    // reverse pass over the same range and checkpoints until `inputs` is reused
+    int64_t keep_bytes = 0;
+    bool kept = false;
+    const void* kept_ck = nullptr;
+    int64_t kept_m0 = 0, kept_m1 = 0;
     hipStream_t aux = nullptr;  // recompute of the next segment's inputs (default priority)
     hipEvent_t fork = nullptr;  // caller's stream -> aux
     hipEvent_t join = nullptr;  // aux -> caller's stream
@@ -244,6 +251,7 @@ struct AdjWork {
                 *q = nullptr;
             }
         inputs_cap = subs_cap = 0;
+        kept = false;
         if (fork) (void)hipEventDestroy(fork);
         if (join) (void)hipEventDestroy(join);
         if (aux) (void)hipStreamDestroy(aux);
@@ -1111,6 +1119,35 @@ static int forward_checkpointed(const AdjTarget& t, void* field, double z0, doub
     const std::vector<int64_t> seg = segment_starts(p, m0, m1);
     if (!seg.empty() && !checkpoints) return fail(MPA_EINVAL, "NULL checkpoints");
     if (hipSetDevice(p->device) != hipSuccess) return fail(MPA_EDEVICE, "hipSetDevice failed");
+    AdjWork* w = t.w;
+    w->kept = false;
+    const int64_t steps = m1 - m0;
+    const int64_t field_bytes = t.count * (int64_t)p->elem;
+    if (steps > 0 && w->keep_bytes > 0 && steps <= w->keep_bytes / field_bytes) {
+        // keep every step input: slot i holds the input of step m0 + i, the last step
+        // writes the field; checkpoint k is copied from the slot of its step
+        st = reserve_fields(t, &w->inputs, &w->inputs_cap, steps);
+        if (st) return st;
+        if (mpa::launch_copy_field(field, w->inputs, t.count, p->prm.precision, s) != hipSuccess)
+            return fail(MPA_EDEVICE, "input copy failed");
+        size_t k = 0;
+        for (int64_t i = 0; i < steps; ++i) {
+            const void* in = field_at(t, w->inputs, i);
+            if (k < seg.size() && seg[k] == m0 + i) {
+                if (mpa::launch_copy_field(in, field_at(t, checkpoints, (int64_t)k), t.count, p->prm.precision, s) !=
+                    hipSuccess)
+                    return fail(MPA_EDEVICE, "checkpoint copy failed");
+                ++k;
+            }
+            st = launch_long_step(p, in, i + 1 < steps ? field_at(t, w->inputs, i + 1) : field, m0 + i, s, t.batch);
+            if (st) return st;
+        }
+        w->kept = true;
+        w->kept_ck = checkpoints;
+        w->kept_m0 = m0;
+        w->kept_m1 = m1;
+        return MPA_OK;
+    }
     for (size_t k = 0; k < seg.size(); ++k) {
         const int64_t a = seg[k], b = (k + 1 < seg.size()) ? seg[k + 1] : m1;
         if (mpa::launch_copy_field(field, field_at(t, checkpoints, (int64_t)k), t.count, p->prm.precision, s) !=
@@ -1140,6 +1177,23 @@ static int reverse(const AdjTarget& t, const void* checkpoints, void* grad, doub
     if (seg.empty()) return MPA_OK;
     st = adjoint_setup(t);
     if (st) return st;
+    AdjWork* w = t.w;
+    if (store_steps == 0 && w->kept && w->kept_ck == checkpoints && w->kept_m0 == m0 && w->kept_m1 == m1) {
+        // the checkpointed forward kept every step input: no recompute
+        void* ga = w->ga;
+        void* gb = w->gb;
+        if (mpa::launch_convert(grad, p->prm.precision, ga, MPA_C128, t.count, s) != hipSuccess)
+            return fail(MPA_EDEVICE, "gradient conversion failed");
+        for (int64_t i = m1 - m0 - 1; i >= 0; --i) {
+            st = adjoint_long_step(t, field_at(t, w->inputs, i), ga, gb, m0 + i, param_grad, s);
+            if (st) return st;
+            std::swap(ga, gb);
+        }
+        if (mpa::launch_convert(ga, MPA_C128, grad, p->prm.precision, t.count, s) != hipSuccess)
+            return fail(MPA_EDEVICE, "gradient conversion failed");
+        return MPA_OK;
+    }
+    w->kept = false;                                  // `inputs` is reused below
 
     // the longest segment decides how many step inputs are kept at once
     int64_t longest = 0;
@@ -1153,7 +1207,6 @@ static int reverse(const AdjTarget& t, const void* checkpoints, void* grad, doub
     int64_t Q = store_steps;
     if (Q == 0) Q = longest * field_bytes <= MPA_ADJOINT_STORE_BYTES ? longest : (int64_t)std::ceil(std::sqrt((double)longest));
     Q = std::max<int64_t>(1, std::min(Q, longest));
-    AdjWork* w = t.w;
     st = reserve_fields(t, &w->inputs, &w->inputs_cap, overlap ? 2 * Q : std::max<int64_t>(Q, 2));
     if (st) return st;
     const int64_t n_sub = (longest + Q - 1) / Q;
@@ -1243,6 +1296,14 @@ int mpa_propagate_checkpointed(mpa_plan* p, void* field, double z0, double z1, v
                                void* stream) {
     if (!p || !field) return fail(MPA_EINVAL, "NULL plan or field");
     return forward_checkpointed(single_target(p), field, z0, z1, checkpoints, (hipStream_t)stream);
+}
+
+int mpa_adjoint_keep_inputs(mpa_plan* p, int64_t max_bytes) {
+    if (!p) return fail(MPA_EINVAL, "NULL plan");
+    if (max_bytes < 0) return fail(MPA_EINVAL, "max_bytes must be >= 0");
+    p->adj.keep_bytes = max_bytes;
+    p->adj.kept = false;
+    return MPA_OK;
 }
 
 int mpa_adjoint(mpa_plan* p, const void* checkpoints, void* grad, double z0, double z1, double* param_grad,
@@ -1420,6 +1481,14 @@ int mpa_batch_propagate_checkpointed(mpa_batch_plan* b, void* fields, double z0,
                                      void* stream) {
     if (!b || !fields) return fail(MPA_EINVAL, "NULL batch plan or fields");
     return forward_checkpointed(batch_target(b), fields, z0, z1, checkpoints, (hipStream_t)stream);
+}
+
+int mpa_batch_adjoint_keep_inputs(mpa_batch_plan* b, int64_t max_bytes) {
+    if (!b) return fail(MPA_EINVAL, "NULL batch plan");
+    if (max_bytes < 0) return fail(MPA_EINVAL, "max_bytes must be >= 0");
+    b->adj.keep_bytes = max_bytes;
+    b->adj.kept = false;
+    return MPA_OK;
 }
 
 int mpa_batch_adjoint(mpa_batch_plan* b, const void* checkpoints, void* grads, double z0, double z1,

@@ -136,6 +136,8 @@ int main() {
     EXPECT(mpa_plan_destroy(nullptr) == MPA_OK);
     int64_t cnt = 0;
     EXPECT(mpa_checkpoint_count(nullptr, 0.0, 1.0, &cnt) == MPA_EINVAL);
+    EXPECT(mpa_adjoint_keep_inputs(nullptr, 0) == MPA_EINVAL);
+    EXPECT(mpa_batch_adjoint_keep_inputs(nullptr, 1 << 20) == MPA_EINVAL);
     for (int s = 0; s >= -8; --s) EXPECT(std::strncmp(mpa_status_string(s), "MPA_", 4) == 0);
     EXPECT(mpa_status_string(-99) != nullptr);
     EXPECT(mpa_last_error_detail(nullptr, 0) >= 0);

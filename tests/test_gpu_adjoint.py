@@ -361,3 +361,49 @@ def test_autograd_binding():
     assert torch.equal(sig.grad, pg[0].cpu()) and torch.equal(b2.grad, pg[1].cpu())
     with pytest.raises(ValueError):
         propagate(plan, x, 0.3, 1.2, sigma=sig * 2)
+
+
+def test_kept_inputs_equal_the_recomputing_pass():
+    """mpa_adjoint_keep_inputs: the checkpointed forward keeps every step
+    input (field and checkpoints bitwise those of the plain checkpointed
+    forward), and the reverse over the same range and checkpoints, which then
+    recomputes nothing, is bitwise the recomputing reverse; a forward of
+    another field moves the kept inputs to its own checkpoints, and the
+    first run's reverse then recomputes (still bitwise); a budget smaller
+    than the range keeps nothing."""
+    import torch
+    grid, a, band, halo, L = _blocked(1024)
+    dmmap = dm_map(beta3=0.1)
+    z0, z1 = 0.5 - 2 * L, 1.0 + L                 # two checkpoints (map period at 1.0)
+    rng = np.random.default_rng(21)
+    g_out = 0.1 * (rng.normal(size=a.size) + 1j * rng.normal(size=a.size))
+    say("kept inputs")
+    ref = _plan(grid, dmmap, L, 2, 2, 1024, halo, 0, band)
+    x = to_dev(a, 0)
+    ck_ref = ref.propagate_checkpointed(x, z0, z1)
+    g_ref = to_dev(g_out, 0)
+    pg_ref = ref.adjoint(ck_ref, g_ref, z0, z1)
+    x_ref, ck_ref, g_ref, pg_ref = to_host(x), ck_ref.cpu().numpy(), to_host(g_ref), pg_ref.cpu().numpy()
+    ref.close()
+    plan = _plan(grid, dmmap, L, 2, 2, 1024, halo, 0, band)
+    plan.keep_inputs(1 << 30)
+    x1 = to_dev(a, 0)
+    ck1 = plan.propagate_checkpointed(x1, z0, z1)
+    assert np.array_equal(to_host(x1), x_ref) and np.array_equal(ck1.cpu().numpy(), ck_ref)
+    g = to_dev(g_out, 0)
+    pg = plan.adjoint(ck1, g, z0, z1).cpu().numpy()
+    assert np.array_equal(to_host(g), g_ref) and np.array_equal(pg, pg_ref)
+    x2 = to_dev(0.9 * a, 0)
+    ck2 = plan.propagate_checkpointed(x2, z0, z1)
+    g = to_dev(g_out, 0)
+    pg = plan.adjoint(ck1, g, z0, z1).cpu().numpy()
+    assert np.array_equal(to_host(g), g_ref) and np.array_equal(pg, pg_ref)
+    plan.keep_inputs(1)
+    x3 = to_dev(a, 0)
+    ck3 = plan.propagate_checkpointed(x3, z0, z1)
+    g = to_dev(g_out, 0)
+    pg = plan.adjoint(ck3, g, z0, z1).cpu().numpy()
+    assert np.array_equal(to_host(g), g_ref) and np.array_equal(pg, pg_ref)
+    plan.close()
+    del ck2
+    torch.cuda.synchronize()

@@ -187,3 +187,26 @@ def test_batch_autograd_binding():
     bp.close()
     assert torch.equal(x.grad, g)
     assert torch.equal(sig.grad, pg[0].cpu()) and torch.equal(b3.grad, pg[2].cpu())
+
+
+def test_batch_kept_inputs_equal_the_recomputing_pass():
+    """mpa_batch_adjoint_keep_inputs: field gradients and parameter
+    derivatives bitwise those of the recomputing reverse pass."""
+    import paper_1101_0086_amd as P
+    ns = [4096, 8192, 2048]
+    fields, g_out, halo, L = _case(ns, 23, 1024)
+    dmm = dm_map(beta3=0.1)
+    z0, z1 = 0.5 - 2 * L, 0.5 + 3 * L
+    out = []
+    for keep in (0, 1 << 30):
+        say("batch kept inputs", keep)
+        bp = P.MPABatchPlan(ns, DT, dmm, L, 2, 2, 1024, halo, P.MPA_C64, BAND, sigma_scale=[1.0, 1.3, 0.8])
+        bp.keep_inputs(keep)
+        x = to_dev(np.concatenate(fields), 0)
+        ck = bp.propagate_checkpointed(x, z0, z1)
+        g = to_dev(np.concatenate(g_out), 0)
+        pg = bp.adjoint(ck, g, z0, z1).cpu().numpy()
+        out.append((to_host(x), to_host(g), pg))
+        bp.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
