@@ -137,8 +137,9 @@ typedef struct {
                               exact integral of the piecewise-constant beta2,
                               beta3 and sigma sampled at the nodes (the mean of
                               both spans on a node that lies on a boundary);
-                              such plans cannot be combined with distributed
-                              gain (MPA_EUNSUPPORTED); their reverse pass runs
+                              with distributed gain the map period and z_amp
+                              must share a multiple of at most 2^26 long steps
+                              (else MPA_EUNSUPPORTED); the reverse pass runs
                               each such step once per span it overlaps      */
     int32_t M;             /* quadrature intervals per long step (>= 1)          */
     int32_t n_iter;        /* Picard sweeps per long step (1..5)                 */

@@ -9,6 +9,8 @@
 #include <cstring>
 #include <algorithm>
 #include <functional>
+#include <map>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -290,6 +292,9 @@ struct mpa_plan {
     bool window = false;
     int n1 = 0, n2 = 0, split = 0;
     std::vector<double> ns_host;        // node-scale rows (FP64, as built)
+    // distributed gain with boundary-crossing steps: node-scale row of each (step table,
+    // gain row) pair that occurs (the step's node sigma times the gain profile of its row)
+    std::map<std::pair<int, int>, int> combo_row;
     void* w_tw[8] = {};                 // tw1, tw1_64, tw2, tw2_64, twl, twh, twl_64, twh_64
     void* w_psi0 = nullptr;
     void* w_sums = nullptr;
@@ -363,8 +368,13 @@ static int validate_params(const mpa_params* p, const mpa_map* map, Schedule* sc
     }
     st = make_schedule(map, p->L, "long step L", sched, true);
     if (st) return st;
-    if (!sched->straddles.empty() && map->raman_g0 > 0)
-        return fail(MPA_EUNSUPPORTED, "long steps across span boundaries with distributed gain are not supported");
+    if (!sched->straddles.empty() && map->raman_g0 > 0) {
+        // one node-scale row per (boundary-crossing step, position in the amplifier period)
+        const int64_t P = sched->period_steps, A = sched->amp_steps;
+        if (P / std::gcd(P, A) > (int64_t(1) << 26) / A)
+            return fail(MPA_EUNSUPPORTED, "distributed gain with long steps across span boundaries needs the map "
+                                          "period and amplifier spacing to share a multiple of at most 2^26 long steps");
+    }
     if (!full) {
         const double pi = 3.14159265358979323846;
         const double w = p->omega_band > 0 ? p->omega_band : pi / p->dt;
@@ -460,7 +470,23 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
     // tables: one per span, then one per boundary-crossing step of the period
     for (auto& st : p->sched.straddles) fill_straddle(map, params->L, M, &st);
     const int TT = S + (int)p->sched.straddles.size();
-    const int NSR = p->gain_rows ? (int)sched.amp_steps : TT;   // node-scale rows
+    int NSR = p->gain_rows ? (int)sched.amp_steps : TT;   // node-scale rows
+    // with distributed gain a boundary-crossing step needs its node sigma and the gain
+    // profile of its position in the amplifier period: one more row for every (step
+    // table, gain row) pair that occurs within a common multiple of period and spacing
+    std::vector<std::pair<int, int>> combos;
+    if (p->gain_rows && !p->sched.straddles.empty()) {
+        const int64_t P = sched.period_steps, A = sched.amp_steps;
+        const int64_t lcm = P / std::gcd(P, A) * A;
+        for (size_t t = 0; t < p->sched.straddles.size(); ++t)
+            for (int64_t m = p->sched.straddles[t].step; m < lcm; m += P) {
+                const std::pair<int, int> key{S + (int)t, (int)(m % A)};
+                if (p->combo_row.count(key)) continue;
+                p->combo_row[key] = NSR + (int)combos.size();
+                combos.push_back(key);
+            }
+        NSR += (int)combos.size();
+    }
 
     const bool f32 = params->precision == MPA_C64;
     const size_t rsz = f32 ? 4 : 8;
@@ -504,15 +530,19 @@ int mpa_plan_create(const mpa_params* params, const mpa_map* map, int device, mp
     //   Gamma_j = -gamma j dz + (g0 / alpha) (exp(-alpha (z_a - zeta0 - j dz)) - exp(-alpha (z_a - zeta0)))
     std::vector<double> ns((size_t)NSR * 2 * (M + 1));
     p->row_out.assign(NSR, 1.0);
+    const int NG = NSR - (int)combos.size();              // rows before the combined ones
     for (int r = 0; r < NSR; ++r)
         for (int j = 0; j <= M; ++j) {
+            const int rg = r < NG ? r : combos[(size_t)(r - NG)].second;       // gain row
             double g = -p->gamma * j * dz;
             if (p->gain_rows) {
-                const double zeta0 = r * params->L, a = p->raman_alpha;
+                const double zeta0 = rg * params->L, a = p->raman_alpha;
                 g += p->raman_g0 / a * (std::exp(-a * (p->z_amp - zeta0 - j * dz)) - std::exp(-a * (p->z_amp - zeta0)));
             }
             // a boundary-crossing step carries sigma(z_j) here (its kernel sigma is 1)
-            const double sj = (!p->gain_rows && r >= S) ? p->sched.straddles[r - S].sig[j] : 1.0;
+            double sj = 1.0;
+            if (r >= NG) sj = p->sched.straddles[(size_t)(combos[(size_t)(r - NG)].first - S)].sig[j];
+            else if (!p->gain_rows && r >= S) sj = p->sched.straddles[(size_t)(r - S)].sig[j];
             ns[(size_t)r * 2 * (M + 1) + 2 * j] = std::exp(g) / B;
             ns[(size_t)r * 2 * (M + 1) + 2 * j + 1] = sj * dz * std::exp(-g);
             if (j == M) p->row_out[r] = std::exp(g);
@@ -664,9 +694,24 @@ int mpa_plan_get_info(const mpa_plan* p, mpa_plan_info* info) {
     return MPA_OK;
 }
 
-// Row of the node-scale table for long step m in span s.
+// Row of the node-scale table for long step m with step table s (a span, or a
+// boundary-crossing step of the period).
 static int gain_row(const mpa_plan* p, int64_t m, int s) {
     if (!p->gain_rows) return s;
+    int64_t r = m % p->sched.amp_steps;
+    if (r < 0) r += p->sched.amp_steps;
+    if (s >= (int)p->beta2.size()) {
+        const auto it = p->combo_row.find({s, (int)r});
+        if (it != p->combo_row.end()) return it->second;
+    }
+    return (int)r;
+}
+
+// The row without a boundary-crossing step's node sigma (the reverse pass takes
+// sigma_j from its node weights): the gain row of step m, or row 0 (every span's
+// row is the same without distributed gain).
+static int plain_row(const mpa_plan* p, int64_t m) {
+    if (!p->gain_rows) return 0;
     int64_t r = m % p->sched.amp_steps;
     if (r < 0) r += p->sched.amp_steps;
     return (int)r;
@@ -1022,9 +1067,8 @@ static int adjoint_long_step(const AdjTarget& t, const void* in, const void* g_o
     const int M = p->prm.M, S = (int)p->beta2.size();
     const double gain = p->sched.amp_after(m) ? p->lumped : 1.0;
     // a boundary-crossing step's own node-scale row carries sigma_j; the reverse kernel
-    // takes sigma_j from the node weights and the row without it, which every span
-    // shares when there is no distributed gain (such steps exclude it)
-    const int ns_row = s < S ? gain_row(p, m, s) : 0;
+    // takes sigma_j from the node weights and the row without it
+    const int ns_row = s < S ? gain_row(p, m, s) : plain_row(p, m);
     mpa::AdjointStepArgs a;
     a.in = in;
     a.g_out = g_out;

@@ -195,3 +195,34 @@ def test_batch_steps_across_boundaries():
         di = dmm.__class__(**{**dmm.__dict__, "sigma": tuple(sc * s for s in dmm.sigma)})
         ref = O.mpa_propagate(a, dt, di, L, 3, 2, z0, z1, B, halo)
         assert rel_l2(g, ref) < TOL_F64, sc
+
+
+@pytest.mark.parametrize("z_amp,prec", [(1.0, 1), (1.0, 0), (2.0, 1)])
+def test_distributed_gain_with_boundary_crossing_steps(z_amp, prec):
+    """Distributed gain and L = 1/7 (steps across z = 0.5 and 1.5): each such
+    step takes its node sigma and the gain profile of its position in the
+    amplifier period (z_amp = 2: two positions per crossing step of the
+    period); forward over several amplifiers against the oracle, and the
+    reverse pass against the oracle's gradient (FP64)."""
+    from tests.test_gpu_adjoint import _compare, _gpu_grad, _oracle, _target
+    import paper_1101_0086_amd as P
+    from workloads.wdm import DMMap
+    w = WORKLOADS["dm1ch_n4096_f64"]
+    dmm = DMMap(**{**w.dmmap.__dict__, "sigma": (1.0, 2.0), "z_amp": z_amp, "raman_g0": 0.2,
+                   "raman_alpha": 3.0})
+    a = w.field()
+    L, M, nit = 1.0 / 7.0, 3, 2
+    z0, z1 = 2.0 / 7.0, 2.0 / 7.0 + (4.0 if z_amp == 2.0 else 2.0)
+    say("distributed gain with crossing steps", z_amp, prec)
+    plan = P.MPAPlan(w.grid.n, w.grid.dt, dmm, L, M, nit, 0, 0, prec)
+    x = to_dev(a, prec)
+    plan.propagate(x, z0, z1)
+    ref = O.mpa_propagate(a, w.grid.dt, dmm, L, M, nit, z0, z1)
+    assert rel_l2(to_host(x), ref) < TOL[prec]
+    if prec == 1:
+        zr1 = z0 + 1.0
+        target = _target(a, w.grid.dt, np.random.default_rng(65), 0.8, 0.05, 10.0)
+        _, g_out, ref_g, ref_p = _oracle(a, w.grid.dt, dmm, L, M, nit, z0, zr1, target)
+        _, got_g, got_p = _gpu_grad(plan, a, g_out, z0, zr1, 1)
+        _compare(1, got_g, got_p, ref_g, ref_p)
+    plan.close()

@@ -195,3 +195,25 @@ def test_vjp_of_a_step_over_three_spans_matches_finite_differences():
     d = rng.normal(size=n) + 1j * rng.normal(size=n)
     _check(lambda a: _loss(run(a=a), target), float(np.real(np.vdot(g_a, d))), a0, d, 1e-6, 1e-6)
     _span_fd(run, dmm, (g_sigma, g_beta2, g_beta3), target, 1e-5, (0, 1, 2))
+
+
+def test_vjp_across_a_boundary_with_distributed_gain_matches_finite_differences():
+    """Distributed gain with a step across the span boundary (L = 1/7) and
+    an amplifier inside the range (z = 1)."""
+    from workloads.wdm import DMMap
+    rng = np.random.default_rng(6)
+    n, dt = 256, 10 / 128
+    a0 = wdm_field(Grid(n, dt), 2, 1, "ook", rng)
+    target = a0 * 0.9 + 0.01 * (rng.normal(size=n) + 1j * rng.normal(size=n))
+    base = dm_map(beta3=0.1)
+    dmm = DMMap(**{**base.__dict__, "sigma": (1.0, 2.0), "raman_g0": 0.2, "raman_alpha": 3.0})
+    L, z0, z1 = 1.0 / 7.0, 3.0 / 7.0, 8.0 / 7.0
+
+    def run(a=a0, dmm=dmm):
+        return O.mpa_propagate(a, dt, dmm, L, 3, 2, z0, z1)
+
+    out = run()
+    g_a, g_sigma, g_beta2, g_beta3 = AD.mpa_propagate_vjp(a0, dt, dmm, L, 3, 2, z0, z1, 2 * (out - target))
+    d = rng.normal(size=n) + 1j * rng.normal(size=n)
+    _check(lambda a: _loss(run(a=a), target), float(np.real(np.vdot(g_a, d))), a0, d, 1e-6, 1e-6)
+    _span_fd(run, dmm, (g_sigma, g_beta2, g_beta3), target, 1e-5, (0, 1))
