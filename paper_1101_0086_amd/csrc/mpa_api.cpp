@@ -755,7 +755,9 @@ static int launch_long_step(mpa_plan* p, const void* in, void* out, int64_t m, h
         w.out = out;
         w.n = p->block;
         w.windows = p->n_blocks;
-        w.blocked = p->block < p->prm.n;
+        // time blocks whenever the plan is not one full window: a block as long as the
+        // field with halos still has several windows (n_blocks > 1) that wrap around it
+        w.blocked = p->halo > 0 || p->block < p->prm.n;
         w.n_field = p->prm.n;
         w.core = p->core;
         w.lead = p->halo + p->shift;

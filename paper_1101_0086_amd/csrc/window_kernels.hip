@@ -303,6 +303,8 @@ template <typename T>
 static hipError_t window_step_t(const WindowStepArgs& w) {
     const size_t N = (size_t)w.n;
     hipError_t e;
+    // one full window reads and writes the field itself: exactly one window
+    if (w.windows < 1 || (!w.blocked && (w.windows != 1 || w.n_field != w.n))) return hipErrorInvalidValue;
     WinRowArgs a{};
     a.psi0 = static_cast<double*>(w.psi0);
     a.S = static_cast<double*>(w.sums);

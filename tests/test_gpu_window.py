@@ -74,11 +74,15 @@ def _large_block_case(n, H, seed):
     (1 << 15, 8192, 1024, 0, False),
     (1 << 16, 16384, 3072, 0, True),
     (1 << 17, 32768, 4096, 1, True),
+    # a block as long as the field, with halos: two windows wrapping around it
+    (1 << 15, 32768, 4096, 1, True),
 ])
 def test_blocks_above_4096_against_oracle(n, B, H, prec, shifted):
     """Blocked plans with B > 4096 (gather with halos and taper, roll-off,
     stitched cores; ragged last core) across the span change and, for the
-    FP64 8192-blocks, an amplifier."""
+    FP64 8192-blocks, an amplifier; also B = N with halos (the autotuner's
+    largest candidate on a 2^15-mode field), whose windows wrap around the
+    field."""
     import paper_1101_0086_amd as P
     a, dt, band, L = _large_block_case(n, H, 72)
     dmm = dm_map(beta3=0.1)
