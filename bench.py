@@ -131,6 +131,9 @@ def main():
                     help="for rocprofv3 --kernel-trace: 40 headline launches, 20 split-steps of each precision")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="for rocprofv3 --pmc: a 512 MiB copy (counter calibration), then 20 headline launches")
+    ap.add_argument("--profile-large", action="store_true",
+                    help="for rocprofv3 --kernel-trace: 10 long steps each of the 2^22-mode workload with "
+                         "8192-blocks (H 1024, M 4) and 16384-blocks (H 4096, M 16), the autotuner's shapes")
     ap.add_argument("--pmc-grad", action="store_true",
                     help="for rocprofv3: 20 reverse long steps of the 2^16-mode gradient workload, "
                          "then 20 of a batch of 32 such fields")
@@ -167,6 +170,20 @@ def main():
         torch.cuda.synchronize()
         bp.close()
         print(json.dumps({"pmc_grad": True, "reverse_launches": 20, "batch_reverse_launches": 20}), flush=True)
+        return
+
+    if args.profile_large:
+        # blocks above 4096 (four-step windows, node order) at the headline's dz
+        w = WORKLOADS[HEADLINE]
+        dz = w.mpa.L / w.mpa.M
+        x = torch.from_numpy(w.field()).to(device="cuda:0", dtype=torch.complex64)
+        for block, halo, M, shift in ((8192, 1024, 4, 192), (16384, 4096, 16, 769)):
+            pl = P.MPAPlan(w.grid.n, w.grid.dt, w.dmmap, M * dz, M, w.mpa.n_iter, block, halo, P.MPA_C64,
+                           w.mpa.omega_band, shift=shift)
+            pl.propagate(x, 0.0, 10 * M * dz)
+            torch.cuda.synchronize()
+            pl.close()
+        print(json.dumps({"profile_large": True, "long_steps_each": 10}), flush=True)
         return
 
     w = WORKLOADS[HEADLINE]
