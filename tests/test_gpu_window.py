@@ -171,3 +171,31 @@ def test_window_refusals():
     with pytest.raises(P.MPAError) as e:
         plan.adjoint(ck, x.clone(), 0.0, 0.1)
     assert e.value.status == P._lib.MPA_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_large_blocks_with_crossing_steps_and_distributed_gain(prec):
+    """8192-blocks with L = 1/k, k odd (steps across the span boundary at 0.5
+    and 1.5, sigma 1 and 2) and distributed gain, over an amplifier: the
+    window path takes the boundary-crossing tables and the combined gain rows
+    of the fused path."""
+    import paper_1101_0086_amd as P
+    from workloads.wdm import DMMap
+    n, B, H = 1 << 15, 8192, 1024
+    a, dt, band, _ = _large_block_case(n, H, 74)
+    rate = O.halo_rate(band, 20.0, 0.1)
+    k = math.ceil(1.0 / (0.25 * H * dt / rate))
+    k += 1 - k % 2                                   # odd: L divides the period, not the spans
+    L = 1.0 / k
+    base = dm_map(beta3=0.1)
+    dmm = DMMap(**{**base.__dict__, "sigma": (1.0, 2.0), "raman_g0": 0.2, "raman_alpha": 3.0})
+    m0 = k // 2 - 2
+    z0, z1 = m0 * L, (m0 + 5) * L
+    for zz0, zz1 in ((z0, z1), (1.0 - 2 * L, 1.0 + 2 * L)):
+        say("large blocks, crossing steps, gain", prec, zz0, zz1)
+        plan = P.MPAPlan(n, dt, dmm, L, 3, 2, B, H, prec, band)
+        x = to_dev(a, prec)
+        plan.propagate(x, zz0, zz1)
+        plan.close()
+        ref = O.mpa_propagate(a, dt, dmm, L, 3, 2, zz0, zz1, B, H)
+        assert rel_l2(to_host(x), ref) < TOL[prec], (zz0, zz1)
