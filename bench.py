@@ -285,7 +285,20 @@ def main():
         log("CPU oracle baselines ...")
         out["cpu_baseline"] = cpu_baseline(w)
         out["cpu_baseline_all_cores"] = cpu_all_cores(w)
+    out["paper_context"] = paper_context()
     print(json.dumps(out), flush=True)
+
+
+def paper_context():
+    """The paper's own CPU numbers, with its hardware (context only, another
+    machine and workload): read from the numbers the test suite pins."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "paper_numbers.json")
+    with open(path) as f:
+        g = json.load(f)
+    keys = ("cpu_speedup_over_one_processor", "near_linear_scaling_up_to_processors",
+            "ss_over_mpa_time_ratio_32_cores_n2")
+    return {"note": "the paper's shared-memory CPU runs: another machine and workload, not a target",
+            **{k: g[k] for k in keys if k in g}}
 
 
 # ---- accuracy and the split-step comparator -----------------------------------------
