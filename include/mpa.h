@@ -301,7 +301,8 @@ int mpa_adjoint(mpa_plan* plan, const void* checkpoints, void* grad, double z0, 
  * can keep them all.  After this call, mpa_propagate_checkpointed also keeps
  * the input of every long step of [z0, z1] in the plan's reverse-pass
  * workspace whenever they fit in max_bytes (steps x N complex samples of the
- * plan precision; 0, the default, keeps none).  A following mpa_adjoint over
+ * plan precision; 0, the default, keeps none; plans without a reverse pass,
+ * windows above 4096 modes, keep none).  A following mpa_adjoint over
  * the same z0, z1 and checkpoints with store_steps = 0 then reverses from
  * them without recomputing any long step; the results are bitwise those of
  * the recomputing pass.  The inputs stay valid until the next

@@ -1169,8 +1169,8 @@ static int forward_checkpointed(const AdjTarget& t, void* field, double z0, doub
     w->kept = false;
     const int64_t steps = m1 - m0;
     const int64_t field_bytes = t.count * (int64_t)p->elem;
-    if (steps > 0 && w->keep_bytes > 0 && steps <= w->keep_bytes / field_bytes) {
-        // keep every step input: slot i holds the input of step m0 + i, the last step
+    if (steps > 0 && !p->window && w->keep_bytes > 0 && steps <= w->keep_bytes / field_bytes) {
+        // keep every step input (plans with a reverse pass): slot i holds the input of step m0 + i, the last step
         // writes the field; checkpoint k is copied from the slot of its step
         st = reserve_fields(t, &w->inputs, &w->inputs_cap, steps);
         if (st) return st;
