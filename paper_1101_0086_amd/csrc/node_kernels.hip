@@ -96,39 +96,56 @@ np_node_kernel(const cx<double>* __restrict__ psi0_buf, const cx<T>* __restrict_
     const int b = (k / M) * XCDS + xcd;
     if (b >= n_blocks) return;                    // the whole workgroup leaves together
     __shared__ cx<T> lds[lds_elems<B>()];
+    // the transforms' twiddles from an LDS table (the B-point table's values, the
+    // arithmetic of block_fft), filled while the trapezoid sums load
+    __shared__ cx<T> twl[tl_elems(B)];
+    fill_twiddle_table<T, B>(twl, tw, threadIdx.x, B / PTS);
     const int tid = threadIdx.x;
     const size_t base = (size_t)b * B;
     const size_t row = (size_t)b * M;              // increments of block b: rows (b, j - 1), j = 1..M
     cx<T> cur[R], ph[R];
+    if (first_sweep) {
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-        const int t = tid + NT * m;
-        const cx<double> p0 = psi0_buf[base + t];
-        if (first_sweep) {
-            cur[m] = narrow<T>(p0);
-        } else {
-            // Eq. 6: psi_0 + (U_0/2 + U_1 + ... + U_{l-1} + U_l/2), summed left to right in FP64
+        for (int m = 0; m < R; ++m) cur[m] = narrow<T>(psi0_buf[base + tid + NT * m]);
+    } else {
+        // Eq. 6: psi_0 + (U_0/2 + U_1 + ... + U_{l-1} + U_l/2), summed left to right in FP64;
+        // the increments outside, the points inside, so that the loads of all points of
+        // one increment are in flight together
 #pragma clang fp contract(off)
-            cx<double> S = widen(h0_buf[base + t]);
-            for (int j = 1; j < l; ++j) S = S + widen(u_prev[(row + j - 1) * B + t]);
-            const cx<double> nxt = p0 + (S + scale(widen(u_prev[(row + l - 1) * B + t]), 0.5));
+        cx<double> S[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) S[m] = widen(h0_buf[base + tid + NT * m]);
+#pragma unroll 2
+        for (int j = 1; j < l; ++j) {
+            const cx<T>* __restrict__ u = u_prev + (row + j - 1) * B;
+#pragma unroll
+            for (int m = 0; m < R; ++m) S[m] = S[m] + widen(u[tid + NT * m]);
+        }
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int t = tid + NT * m;
+            const cx<double> nxt = psi0_buf[base + t] + (S[m] + scale(widen(u_prev[(row + l - 1) * B + t]), 0.5));
             cur[m] = narrow<T>(nxt);
         }
-        ph[m] = phase[(size_t)l * B + t];
     }
+#pragma unroll
+    for (int m = 0; m < R; ++m) ph[m] = phase[(size_t)l * B + tid + NT * m];
     const T cl = node_scale[2 * l];
     const T dl = sigma * node_scale[2 * l + 1];
     // steps 2-3: A = e^{Gamma_l} F^-1[psi e^{i beta_l}]
 #pragma unroll
     for (int m = 0; m < R; ++m) cur[m] = cmul(cur[m], ph[m]);
-    block_fft<T, B, R, -1>(cur, lds, tw, tid);
+    cx<T>* l0 = lds;
+    cx<T>* l1 = lds;
+    __syncthreads();                              // the twiddle table is complete
+    block_fft_warm<T, B, R, -1, false, TW_TABLE>(cur, l0, l1, tw, tid, twl);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const cx<T> a = scale(cur[m], cl);
         cur[m] = scale(a, norm2(a));
     }
     // step 4: U_l = i sigma dz e^{-Gamma_l} e^{-i beta_l} F[|A|^2 A]
-    block_fft<T, B, R, +1>(cur, lds, tw, tid);
+    block_fft_warm<T, B, R, +1, false, TW_TABLE>(cur, l0, l1, tw, tid, twl);
 #pragma unroll
     for (int m = 0; m < R; ++m)
         u_cur[(row + l - 1) * B + tid + NT * m] = rot<+1>(scale(cmulc(cur[m], ph[m]), dl));
@@ -148,13 +165,23 @@ np_final_kernel(const cx<double>* __restrict__ psi0_buf, const cx<T>* __restrict
     const size_t base = (size_t)b * B;
     const size_t row = (size_t)b * M;
     cx<double> v[R];
+    {
+        // the trapezoid sum to node M, increments outside and points inside (as np_node_kernel)
+#pragma clang fp contract(off)
+#pragma unroll
+        for (int m = 0; m < R; ++m) v[m] = widen(h0_buf[base + tid + NT * m]);
+#pragma unroll 2
+        for (int j = 1; j < M; ++j) {
+            const cx<T>* __restrict__ u = u_last + (row + j - 1) * B;
+#pragma unroll
+            for (int m = 0; m < R; ++m) v[m] = v[m] + widen(u[tid + NT * m]);
+        }
+    }
 #pragma unroll
     for (int m = 0; m < R; ++m) {
 #pragma clang fp contract(off)
         const int t = tid + NT * m;
-        cx<double> S = widen(h0_buf[base + t]);
-        for (int j = 1; j < M; ++j) S = S + widen(u_last[(row + j - 1) * B + t]);
-        const cx<double> psiM = psi0_buf[base + t] + (S + scale(widen(u_last[(row + M - 1) * B + t]), 0.5));
+        const cx<double> psiM = psi0_buf[base + t] + (v[m] + scale(widen(u_last[(row + M - 1) * B + t]), 0.5));
         // step 7: A(z0 + L) = e^{Gamma_M} F^-1[psi_M e^{i beta_M}] (times the roll-off and gain)
         v[m] = scale(cmul(psiM, phase_last[t]), out_scale);
     }
